@@ -1,0 +1,175 @@
+"""CPU oracle for ask/bid pricing of American options under proportional
+transaction costs (Zhang, Roux & Zastawniak 2011, Sections 3 and 4.1) and the
+zero-cost CRR price (Section 3, Appendix).
+
+TEST INFRASTRUCTURE ONLY: tests, the smoke check and the benchmark's CPU
+baseline may import this package; the product path (``paper_1110_2477_amd``)
+never does.
+
+``btoracle.c`` holds the recursion and the piecewise-linear operations;
+``definitions.py`` holds the plain definitions the recursion is pinned to
+(superhedging linear programs, stopping-time enumeration, brute-force
+inf-convolution).
+"""
+import ctypes
+import os
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+PUT, CALL, BULL = 0, 1, 2
+EUROPEAN, COST_AT_T0 = 1, 2
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(LIB_PATH)
+    for suffix in ("_v", "_g"):
+        f = getattr(lib, "oracle_price" + suffix)
+        f.restype = ctypes.c_int
+        f.argtypes = [ctypes.c_double] * 7 + [ctypes.c_int, ctypes.c_int, ctypes.c_uint,
+                                              ctypes.c_int, _dp, _i64p, _dp]
+    lib.oracle_model_v.restype = ctypes.c_int
+    lib.oracle_model_v.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int, _dp, _dp]
+    lib.oracle_pwl_op_v.restype = ctypes.c_int
+    lib.oracle_pwl_op_v.argtypes = ([ctypes.c_int] + [ctypes.c_int, _dp, _dp, _dp] * 2
+                                    + [ctypes.c_double, ctypes.c_double, ctypes.c_int, _ip, _dp, _dp, _dp])
+    lib.oracle_pwl_eval_v.restype = ctypes.c_double
+    lib.oracle_pwl_eval_v.argtypes = [ctypes.c_int, _dp, _dp, _dp, ctypes.c_double]
+    lib.oracle_node_v.restype = ctypes.c_int
+    lib.oracle_node_v.argtypes = ([ctypes.c_int] + [ctypes.c_int, _dp, _dp, _dp] * 2
+                                  + [ctypes.c_double] * 5 + [ctypes.c_int]
+                                  + [_ip, _dp, _dp, _dp] * 2)
+    _lib = lib
+    return lib
+
+
+def _arr(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+class OracleError(ValueError):
+    pass
+
+
+def price(S0, K, R, sigma, T, k, N, payoff=PUT, K2=0.0, flags=0, sides=3, grad=False):
+    """Ask, bid and zero-cost price of one option, with breakpoint counts.
+
+    Returns a dict with ask, bid, price0, bp_total_ask, bp_total_bid,
+    bp_max_ask, bp_max_bid and, with ``grad=True``, ``grad_ask`` and
+    ``grad_bid`` = d/d(S0, sigma, R, k)."""
+    lib = _load()
+    out = np.zeros(3)
+    cnt = np.zeros(4, dtype=np.int64)
+    g = np.full(8, np.nan)
+    fn = lib.oracle_price_g if grad else lib.oracle_price_v
+    rc = fn(float(S0), float(K), float(K2), float(R), float(sigma), float(T), float(k),
+            int(N), int(payoff), int(flags), int(sides),
+            out.ctypes.data_as(_dp), cnt.ctypes.data_as(_i64p),
+            g.ctypes.data_as(_dp) if grad else None)
+    if rc != 0:
+        raise OracleError("invalid option parameters")
+    res = dict(ask=out[0], bid=out[1], price0=out[2],
+               bp_total_ask=int(cnt[0]), bp_total_bid=int(cnt[1]),
+               bp_max_ask=int(cnt[2]), bp_max_bid=int(cnt[3]))
+    if grad:
+        res["grad_ask"] = g[:4].copy()
+        res["grad_bid"] = g[4:].copy()
+    return res
+
+
+def price_params(p, grad=False, sides=3):
+    """``price`` for one record of a parameter book (a dict or a numpy
+    structured row with fields S0, K, K2, R, sigma, T, k, N, payoff, flags)."""
+    return price(p["S0"], p["K"], p["R"], p["sigma"], p["T"], p["k"], int(p["N"]),
+                 payoff=int(p["payoff"]), K2=p["K2"], flags=int(p["flags"]),
+                 sides=sides, grad=grad)
+
+
+def price_book(book, threads=None, grad=False):
+    """Prices every option of a book, one option per task on a thread pool
+    (the library releases the GIL), longest tree first.  Returns a list of
+    result dicts in book order."""
+    n = len(book)
+    order = sorted(range(n), key=lambda i: -int(book[i]["N"]))
+    threads = threads or os.cpu_count() or 1
+    res = [None] * n
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        futs = {i: ex.submit(price_params, book[i], grad) for i in order}
+        for i, f in futs.items():
+            res[i] = f.result()
+    return res
+
+
+def model_table(S0, sigma, R, T, N):
+    """Stock table S0 u^j for j = -(N+1)..N+1 and (u, d, r, rho, p)."""
+    lib = _load()
+    tab = np.zeros(2 * N + 3)
+    consts = np.zeros(5)
+    rc = lib.oracle_model_v(float(S0), float(sigma), float(R), float(T), int(N),
+                            tab.ctypes.data_as(_dp), consts.ctypes.data_as(_dp))
+    if rc != 0:
+        raise OracleError("invalid model parameters")
+    return tab, dict(zip(("u", "d", "r", "rho", "p"), consts))
+
+
+MERGE_MAX, MERGE_MIN, SCALE, CLIP, ENV, CANON = range(6)
+
+
+def pwl_op(op, F, G=None, a=0.0, b=0.0):
+    """One canonical PWL operation.  Functions are (x, v, s) tuples with
+    len(s) == len(x) + 1."""
+    lib = _load()
+    xF, pxF = _arr(F[0]); vF, pvF = _arr(F[1]); sF, psF = _arr(F[2])
+    if G is None:
+        G = F
+    xG, pxG = _arr(G[0]); vG, pvG = _arr(G[1]); sG, psG = _arr(G[2])
+    cap = 16 * (len(xF) + len(xG)) + 16
+    xo = np.zeros(cap); vo = np.zeros(cap); so = np.zeros(cap + 1)
+    mo = ctypes.c_int(0)
+    rc = lib.oracle_pwl_op_v(op, len(xF), pxF, pvF, psF, len(xG), pxG, pvG, psG,
+                             float(a), float(b), cap, ctypes.byref(mo),
+                             xo.ctypes.data_as(_dp), vo.ctypes.data_as(_dp), so.ctypes.data_as(_dp))
+    if rc != 0:
+        raise OracleError("output capacity exceeded")
+    m = mo.value
+    return xo[:m].copy(), vo[:m].copy(), so[:m + 1].copy()
+
+
+def pwl_eval(F, y):
+    lib = _load()
+    x, px = _arr(F[0]); v, pv = _arr(F[1]); s, ps = _arr(F[2])
+    return lib.oracle_pwl_eval_v(len(x), px, pv, ps, float(y))
+
+
+def node(side, Zu, Zd, S, kt, rho, xi, zeta):
+    """One node update (children Zu, Zd), returns (z, v) as (x, v, s) tuples."""
+    lib = _load()
+    xu, pxu = _arr(Zu[0]); vu, pvu = _arr(Zu[1]); su, psu = _arr(Zu[2])
+    xd, pxd = _arr(Zd[0]); vd, pvd = _arr(Zd[1]); sd, psd = _arr(Zd[2])
+    cap = 64 * (len(xu) + len(xd)) + 64
+    out = [np.zeros(cap) for _ in range(6)]
+    mz = ctypes.c_int(0); mv = ctypes.c_int(0)
+    rc = lib.oracle_node_v(side, len(xu), pxu, pvu, psu, len(xd), pxd, pvd, psd,
+                           float(S), float(kt), float(rho), float(xi), float(zeta), cap,
+                           ctypes.byref(mz), *[o.ctypes.data_as(_dp) for o in out[:3]],
+                           ctypes.byref(mv), *[o.ctypes.data_as(_dp) for o in out[3:]])
+    if rc != 0:
+        raise OracleError("output capacity exceeded")
+    z = (out[0][:mz.value].copy(), out[1][:mz.value].copy(), out[2][:mz.value + 1].copy())
+    v = (out[3][:mv.value].copy(), out[4][:mv.value].copy(), out[5][:mv.value + 1].copy())
+    return z, v
