@@ -1,0 +1,175 @@
+/*
+ * bt.h -- C ABI of libbtprice: ask and bid prices of American options under
+ * proportional transaction costs on a recombining CRR binomial tree, and the
+ * zero-cost CRR price, computed on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Zhang, Roux & Zastawniak, "Parallel Binomial American Option
+ * Pricing with (and without) Transaction Costs" (2011).
+ *   - Tree model (Section 4.1): N steps, u = exp(sigma sqrt(T/N)), d = 1/u,
+ *     r = exp(R T/N); bid/ask stock prices (1 -+ k) S (Section 3); an extra
+ *     time N+1 with payoff (0, 0); no transaction cost at t = 0.
+ *   - Seller (ask) and buyer (bid) backward induction over piecewise-linear
+ *     expense functions of the stock holding (Section 3): w = max of the two
+ *     successors, v = w / r with slopes restricted to [-S^a_t, -S^b_t],
+ *     z = max(u_t, v) for the seller, min(u_t, v) for the buyer;
+ *     ask = z_0(0), bid = -z_0(0).
+ *   - Zero-cost price (Section 3 and Appendix): scalar CRR recursion without
+ *     the extra time step.
+ *
+ * Conventions shared by every entry point:
+ *   - Plain C types only; nothing crosses the ABI that a C caller cannot
+ *     build.  No exceptions escape.
+ *   - Return value: BT_OK (0) or a negative BT_E* code.  bt_strerror() names
+ *     it; after BT_EHIP, bt_last_hip_error() returns the hipError_t value of
+ *     the failing HIP call on the calling thread.
+ *   - "host pointer" arguments are read or written synchronously before the
+ *     call returns; "device pointer" arguments must point to device memory of
+ *     the current HIP device and are accessed asynchronously on `stream`
+ *     (a hipStream_t passed as void*, NULL = the null stream).
+ *   - All memory passed in is owned by the caller.  The library owns only
+ *     what a book (bt_book) allocates, freed by bt_book_destroy().
+ *   - All arithmetic is IEEE binary64 with no contraction.
+ */
+#ifndef BT_H
+#define BT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BT_VERSION 10000 /* 1.0.0 */
+
+/* Error codes. */
+#define BT_OK 0
+#define BT_EINVAL (-1)    /* invalid argument or option parameters          */
+#define BT_ENOMEM (-2)    /* device or host allocation failed               */
+#define BT_EHIP (-3)      /* a HIP runtime call failed                      */
+#define BT_EOVERFLOW (-4) /* a tree level exceeded the book's work buffers  */
+#define BT_ENOSUPP (-5)   /* feature not supported                          */
+
+/* Payoff processes (xi_t, zeta_t) of Section 3: the holder who exercises at
+ * t receives xi_t in cash and zeta_t shares.
+ *   BT_PUT : (K, -1), physical delivery (Section 3's example)
+ *   BT_CALL: (-K, 1), physical delivery
+ *   BT_BULL: ((S-K)^+ - (S-K2)^+, 0), cash settled (Section 5's bull spread) */
+enum { BT_PUT = 0, BT_CALL = 1, BT_BULL = 2 };
+
+/* Option flags.
+ *   BT_F_EUROPEAN   exercise only at N (test variant; z_t = v_t for t < N)
+ *   BT_F_COST_AT_T0 charge the cost rate k at t = 0 as well (the paper's
+ *                   model charges none at t = 0, Section 4.1)              */
+enum { BT_F_EUROPEAN = 1u, BT_F_COST_AT_T0 = 2u };
+
+/* One option.  S0, K, sigma, T > 0; K2 > K for BT_BULL (ignored otherwise);
+ * R is the continuously compounded annual rate; 0 <= k < 1;
+ * 1 <= N <= BT_MAX_N; the tree must be free of arbitrage: d < r < u. */
+typedef struct {
+    double S0, K, K2, R, sigma, T, k;
+    int32_t N, payoff;
+    uint32_t flags, reserved; /* reserved must be 0 */
+} bt_params;
+
+#define BT_MAX_N 65536
+
+/* Result of one option.  ask/bid: the Section 3 prices; price0: the
+ * zero-cost CRR price.  bp_*: breakpoint statistics of the expense functions
+ * z_t over all nodes of levels 0..N of one side (a breakpoint is a change of
+ * slope); status: BT_OK or the error of this option (prices are NaN then). */
+typedef struct {
+    double ask, bid, price0;
+    int64_t bp_total_ask, bp_total_bid;
+    int32_t bp_max_ask, bp_max_bid;
+    int32_t status, reserved;
+} bt_result;
+
+/* Derivatives of ask and bid with respect to S0, sigma, R and k, taken on
+ * the active branch of the piecewise-smooth price (N, T, K, K2 fixed). */
+typedef struct {
+    double dS0, dsigma, dR, dk;
+} bt_grad4;
+typedef struct {
+    bt_grad4 ask, bid;
+} bt_grad;
+
+/* Launch tuning; pass NULL for the library's choice.  Zero fields also mean
+ * "library's choice".
+ *   wgs_per_cu   persistent workgroups per compute unit
+ *   level_factor capacity of one tree level, in points per node
+ *   pool_points  per-workgroup pool for nodes with many breakpoints
+ *   flags        BT_TUNE_TIMING: record HIP events around every kernel of
+ *                every pricing call (read with bt_book_timings; not for use
+ *                under graph capture)                                       */
+typedef struct {
+    int32_t wgs_per_cu, level_factor, pool_points, flags;
+} bt_tune;
+
+enum { BT_TUNE_TIMING = 1 };
+
+/* Number of kernels one pricing call launches, in launch order:
+ * 0 = result/queue reset, 1 = buyer (bid), 2 = seller (ask), 3 = zero-cost. */
+#define BT_NUM_KERNELS 4
+
+/* A book: a batch of options prepared for repeated pricing.  Creating it
+ * validates every option (an invalid one gets status BT_EINVAL in every
+ * result and is skipped by the kernels), derives the tree constants on the
+ * host, orders the work longest-tree-first, and allocates every device
+ * buffer the pricing calls need, so that bt_book_price and
+ * bt_book_price_grad allocate nothing and can be captured in a HIP graph.
+ * The book belongs to the HIP device that is current when it is created. */
+typedef struct bt_book bt_book;
+
+/* h_params: host pointer to n options (n >= 1).  tune: host pointer or
+ * NULL.  *out receives the book.  Returns BT_OK even when some options are
+ * invalid (see the per-option status); BT_EINVAL only for bad arguments. */
+int bt_book_create(const bt_params *h_params, int32_t n, const bt_tune *tune, bt_book **out);
+
+/* Number of options, largest N, and the number of tree nodes
+ * sum_i (N_i+1)(N_i+2)/2 of the valid options. */
+int bt_book_info(const bt_book *book, int32_t *n, int32_t *n_max, int64_t *nodes);
+
+/* Prices every option of the book: ask, bid (Section 3 recursions) and
+ * price0 (zero-cost recursion).  d_out: device pointer to n bt_result, in
+ * book order.  Asynchronous on `stream`; the book's buffers are shared by
+ * all calls on it, so calls on one book must not overlap. */
+int bt_book_price(bt_book *book, bt_result *d_out, void *stream);
+
+/* As bt_book_price, and also the Greeks of ask and bid: d_grad is a device
+ * pointer to n bt_grad. */
+int bt_book_price_grad(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream);
+
+/* Completes a pricing call whose options overflowed the book's level
+ * buffers (status BT_EOVERFLOW; a tree whose levels hold more breakpoints
+ * than level_factor per node): waits for `stream`, then re-prices those
+ * options on `stream` with buffers 4x larger each attempt (up to 1024x),
+ * writing their results into d_out.  *remaining (may be NULL) receives the
+ * number of options still overflowing.  Synchronous; allocates temporary
+ * device memory only when some option overflowed. */
+int bt_book_resolve_overflow(bt_book *book, bt_result *d_out, void *stream, int32_t *remaining);
+
+/* For a book created with BT_TUNE_TIMING: waits for every pricing call
+ * made since the previous bt_book_timings call, writes into ms[0..3] the
+ * total milliseconds each kernel took over those calls (HIP events on the
+ * call's stream) and into *calls their number.  BT_ENOSUPP without the flag. */
+int bt_book_timings(bt_book *book, double *ms, int32_t *calls);
+
+/* Frees the book's device memory (synchronises the device first). */
+void bt_book_destroy(bt_book *book);
+
+/* Plain single-option pricing: host in, host out, synchronous on the null
+ * stream.  Uses a cached one-option book per calling thread. */
+int bt_price(const bt_params *p, bt_result *out);
+
+/* Tree constants the library derives for one option on the host (u, d, r,
+ * rho = 1/r, p = (r-d)/(u-d)); BT_EINVAL if the option is invalid. */
+int bt_model_constants(const bt_params *p, double *u, double *d, double *r, double *rho, double *pu);
+
+const char *bt_strerror(int code);
+int bt_version(void);
+int bt_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BT_H */

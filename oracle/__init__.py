@@ -42,6 +42,8 @@ def _load():
         f.restype = ctypes.c_int
         f.argtypes = [ctypes.c_double] * 7 + [ctypes.c_int, ctypes.c_int, ctypes.c_uint,
                                               ctypes.c_int, _dp, _i64p, _dp]
+    lib.oracle_flops_v.restype = ctypes.c_uint64
+    lib.oracle_flops_v.argtypes = []
     lib.oracle_model_v.restype = ctypes.c_int
     lib.oracle_model_v.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int, _dp, _dp]
     lib.oracle_pwl_op_v.restype = ctypes.c_int
@@ -90,6 +92,12 @@ def price(S0, K, R, sigma, T, k, N, payoff=PUT, K2=0.0, flags=0, sides=3, grad=F
         res["grad_ask"] = g[:4].copy()
         res["grad_bid"] = g[4:].copy()
     return res
+
+
+def flops():
+    """Binary64 add/sub/mul/div operations the calling thread's oracle calls
+    performed since the previous ``flops()`` (value build only)."""
+    return int(_load().oracle_flops_v())
 
 
 def price_params(p, grad=False, sides=3):

@@ -40,18 +40,24 @@
 /* ------------------------------------------------------------------------ */
 typedef struct { double v; double d[ND]; } num;
 
+/* Count of binary64 additions, subtractions, multiplications and divisions
+ * on values (tangents excluded), per thread: the algorithmic work. */
+static _Thread_local uint64_t g_flops;
+
 static num nc(double v) { num r; r.v = v; for (int i = 0; i < ND; i++) r.d[i] = 0.0; return r; }
-static num nadd(num a, num b) { num r = nc(a.v + b.v); for (int i = 0; i < NT; i++) r.d[i] = a.d[i] + b.d[i]; return r; }
-static num nsub(num a, num b) { num r = nc(a.v - b.v); for (int i = 0; i < NT; i++) r.d[i] = a.d[i] - b.d[i]; return r; }
+static num nadd(num a, num b) { g_flops++; num r = nc(a.v + b.v); for (int i = 0; i < NT; i++) r.d[i] = a.d[i] + b.d[i]; return r; }
+static num nsub(num a, num b) { g_flops++; num r = nc(a.v - b.v); for (int i = 0; i < NT; i++) r.d[i] = a.d[i] - b.d[i]; return r; }
 static num nneg(num a) { num r = nc(-a.v); for (int i = 0; i < NT; i++) r.d[i] = -a.d[i]; return r; }
 static num nmul(num a, num b)
 {
+    g_flops++;
     num r = nc(a.v * b.v);
     for (int i = 0; i < NT; i++) r.d[i] = a.d[i] * b.v + a.v * b.d[i];
     return r;
 }
 static num ndiv(num a, num b)
 {
+    g_flops++;
     num r = nc(a.v / b.v);
     for (int i = 0; i < NT; i++) r.d[i] = (a.d[i] - r.v * b.d[i]) / b.v;
     return r;
@@ -634,6 +640,14 @@ int API(oracle_model)(double S0, double sigma, double R, double T, int N, double
     consts[0] = md.u.v; consts[1] = md.d.v; consts[2] = md.r.v; consts[3] = md.rho.v; consts[4] = md.p;
     free(md.S);
     return 0;
+}
+
+/* Binary64 operations counted on this thread since the previous call. */
+uint64_t API(oracle_flops)(void)
+{
+    uint64_t f = g_flops;
+    g_flops = 0;
+    return f;
 }
 
 /* Single PWL operations for unit tests.  Functions travel as (m, x[m], v[m],

@@ -1,0 +1,249 @@
+"""Python binding of libbtprice (include/bt.h): ask and bid prices of
+American options under proportional transaction costs and the zero-cost CRR
+price, computed by HIP kernels on an MI355X.
+
+The binding only marshals arguments; every step of the pricing runs in the
+library's kernels.  PyTorch supplies device memory and streams.  The library
+is built in-tree by ``paper_1110_2477_amd/build.py``; without it every call
+raises ``RuntimeError`` -- there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from .workloads import GRAD_DTYPE, PARAMS_DTYPE, RESULT_DTYPE  # noqa: F401
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbtprice.so")
+
+BT_OK, BT_EINVAL, BT_ENOMEM, BT_EHIP, BT_EOVERFLOW, BT_ENOSUPP = 0, -1, -2, -3, -4, -5
+PUT, CALL, BULL = 0, 1, 2
+EUROPEAN, COST_AT_T0 = 1, 2
+
+# Function names declared in include/bt.h.
+ABI_FUNCTIONS = ("bt_book_create", "bt_book_info", "bt_book_price", "bt_book_price_grad",
+                 "bt_book_resolve_overflow", "bt_book_timings", "bt_book_destroy", "bt_price", "bt_model_constants", "bt_strerror",
+                 "bt_version", "bt_last_hip_error")
+
+
+class BtError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+
+
+BT_TUNE_TIMING = 1
+KERNEL_NAMES = ("reset", "bid", "ask", "price0")
+
+
+class _Tune(ctypes.Structure):
+    _fields_ = [("wgs_per_cu", ctypes.c_int32), ("level_factor", ctypes.c_int32),
+                ("pool_points", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libbtprice (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1110_2477_amd/build.py "
+                           "(the HIP path has no fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64p = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.bt_book_create.argtypes = [vp, i32, vp, ctypes.POINTER(vp)]
+    L.bt_book_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), i64p]
+    L.bt_book_price.argtypes = [vp, vp, vp]
+    L.bt_book_price_grad.argtypes = [vp, vp, vp, vp]
+    L.bt_book_timings.argtypes = [vp, dp, ctypes.POINTER(i32)]
+    L.bt_book_resolve_overflow.argtypes = [vp, vp, vp, ctypes.POINTER(i32)]
+    L.bt_book_destroy.argtypes = [vp]
+    L.bt_book_destroy.restype = None
+    L.bt_price.argtypes = [vp, vp]
+    L.bt_model_constants.argtypes = [vp, dp, dp, dp, dp, dp]
+    L.bt_strerror.argtypes = [ctypes.c_int]
+    L.bt_strerror.restype = ctypes.c_char_p
+    L.bt_version.argtypes = []
+    L.bt_last_hip_error.argtypes = []
+    for f in ("bt_book_create", "bt_book_info", "bt_book_price", "bt_book_price_grad", "bt_book_timings", "bt_book_resolve_overflow",
+              "bt_price", "bt_model_constants", "bt_version", "bt_last_hip_error"):
+        getattr(L, f).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def strerror(code):
+    return lib().bt_strerror(int(code)).decode()
+
+
+def bt_version():
+    return lib().bt_version()
+
+
+def _check(rc, what):
+    if rc != BT_OK:
+        raise BtError(rc, what)
+
+
+def _params(params):
+    p = np.ascontiguousarray(np.asarray(params, dtype=PARAMS_DTYPE).reshape(-1))
+    return p
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def bt_book_create(params, tune=None):
+    """Creates a book (opaque handle) from a PARAMS_DTYPE array."""
+    p = _params(params)
+    h = ctypes.c_void_p()
+    t = None
+    if tune is not None:
+        t = _Tune(int(tune.get("wgs_per_cu", 0)), int(tune.get("level_factor", 0)),
+                  int(tune.get("pool_points", 0)), int(tune.get("flags", 0)))
+    rc = lib().bt_book_create(p.ctypes.data, len(p), ctypes.byref(t) if t is not None else None,
+                              ctypes.byref(h))
+    _check(rc, "bt_book_create")
+    return h
+
+
+def bt_book_info(book):
+    n, nmax, nodes = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+    _check(lib().bt_book_info(book, ctypes.byref(n), ctypes.byref(nmax), ctypes.byref(nodes)),
+           "bt_book_info")
+    return n.value, nmax.value, nodes.value
+
+
+def bt_book_price(book, d_out_ptr, stream=None):
+    """Launches the pricing of a book into device memory at ``d_out_ptr``
+    (n bt_result records) on ``stream`` (a torch stream, a raw handle or None
+    for torch's current stream)."""
+    _check(lib().bt_book_price(book, ctypes.c_void_p(d_out_ptr), ctypes.c_void_p(_stream_ptr(stream))),
+           "bt_book_price")
+
+
+def bt_book_price_grad(book, d_out_ptr, d_grad_ptr, stream=None):
+    _check(lib().bt_book_price_grad(book, ctypes.c_void_p(d_out_ptr), ctypes.c_void_p(d_grad_ptr),
+                                    ctypes.c_void_p(_stream_ptr(stream))), "bt_book_price_grad")
+
+
+def bt_book_resolve_overflow(book, d_out_ptr, stream=None):
+    """Re-prices the options of a finished call that overflowed the book's
+    level buffers; returns how many still overflow."""
+    rem = ctypes.c_int32()
+    _check(lib().bt_book_resolve_overflow(book, ctypes.c_void_p(d_out_ptr),
+                                          ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(rem)),
+           "bt_book_resolve_overflow")
+    return rem.value
+
+
+def bt_book_timings(book):
+    """Per-kernel milliseconds summed over the pricing calls since the last
+    query (book created with flags=BT_TUNE_TIMING), and the call count."""
+    ms = (ctypes.c_double * 4)()
+    calls = ctypes.c_int32()
+    _check(lib().bt_book_timings(book, ms, ctypes.byref(calls)), "bt_book_timings")
+    return dict(zip(KERNEL_NAMES, list(ms))), calls.value
+
+
+def bt_book_destroy(book):
+    lib().bt_book_destroy(book)
+
+
+def bt_price(params):
+    """Plain single-option pricing (host in, host out, synchronous)."""
+    p = _params(params)
+    if len(p) != 1:
+        raise ValueError("bt_price takes one option")
+    out = np.zeros(1, dtype=RESULT_DTYPE)
+    _check(lib().bt_price(p.ctypes.data, out.ctypes.data), "bt_price")
+    return out[0]
+
+
+def bt_model_constants(params):
+    p = _params(params)
+    vals = [ctypes.c_double() for _ in range(5)]
+    rc = lib().bt_model_constants(p.ctypes.data, *[ctypes.byref(v) for v in vals])
+    _check(rc, "bt_model_constants")
+    return dict(zip(("u", "d", "r", "rho", "p"), (v.value for v in vals)))
+
+
+class Book:
+    """A priced-repeatedly batch of options on the current GPU.
+
+    ``price()`` returns a uint8 CUDA tensor holding n bt_result records;
+    ``results()`` copies it to a RESULT_DTYPE numpy array."""
+
+    def __init__(self, params, tune=None):
+        import torch
+        self.params = _params(params)
+        self.n = len(self.params)
+        self.handle = bt_book_create(self.params, tune)
+        self.out = torch.empty(self.n * RESULT_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        self.grad = None
+
+    def info(self):
+        return bt_book_info(self.handle)
+
+    def price(self, stream=None):
+        bt_book_price(self.handle, self.out.data_ptr(), stream)
+        return self.out
+
+    def price_grad(self, stream=None):
+        import torch
+        if self.grad is None:
+            self.grad = torch.empty(self.n * GRAD_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        bt_book_price_grad(self.handle, self.out.data_ptr(), self.grad.data_ptr(), stream)
+        return self.out, self.grad
+
+    def timings(self):
+        return bt_book_timings(self.handle)
+
+    def resolve_overflow(self, stream=None):
+        return bt_book_resolve_overflow(self.handle, self.out.data_ptr(), stream)
+
+    def results(self):
+        import torch
+        torch.cuda.synchronize()
+        return np.frombuffer(self.out.cpu().numpy().tobytes(), dtype=RESULT_DTYPE).copy()
+
+    def grads(self):
+        import torch
+        torch.cuda.synchronize()
+        return np.frombuffer(self.grad.cpu().numpy().tobytes(), dtype=GRAD_DTYPE).copy()
+
+    def close(self):
+        if self.handle is not None:
+            bt_book_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def price_book(params, tune=None, resolve=True):
+    """Prices a book once and returns the RESULT_DTYPE array; options that
+    overflowed the level buffers are re-priced with larger ones unless
+    ``resolve`` is False."""
+    b = Book(params, tune)
+    try:
+        b.price()
+        if resolve:
+            b.resolve_overflow()
+        return b.results()
+    finally:
+        b.close()

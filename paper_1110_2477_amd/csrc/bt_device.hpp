@@ -1,0 +1,180 @@
+// bt_device.hpp -- shared definitions of the gfx950 kernels and their host
+// launcher: per-option tree constants, the workspace layout of one
+// persistent workgroup, and the per-node update of Section 3.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bt_pwl.hpp"
+
+#define BTHD __host__ __device__ inline
+
+namespace bt {
+
+constexpr int WG = 256;          // lanes per workgroup (4 waves of 64)
+constexpr int NWAVE = WG / 64;
+constexpr int SMALL_CAP = 12;    // points per stage on the interleaved fast path
+
+enum { KIND_ASK = 0, KIND_BID = 1, KIND_PRICE0 = 2 };
+enum { PAY_PUT = 0, PAY_CALL = 1, PAY_BULL = 2 };
+enum { F_EUROPEAN = 1u, F_COST_AT_T0 = 2u };
+
+// Tree constants of one option, derived on the host (Section 4.1):
+// u = exp(sigma sqrt(T/N)), d = 1/u, r = exp(R T/N), rho = 1/r,
+// p = (r - d)/(u - d).  sq = sqrt(T/N) and dt = T/N seed the Greeks.
+struct Model {
+    double S0, u, d, r, rho, p, K, K2, k, sq, dt;
+    int32_t N, payoff;
+    uint32_t flags;
+    int32_t valid;
+};
+
+// Stage capacities of one node update (points).  W = max of the children,
+// A and B the two sweeps of ENV, V the restricted function, Z the result.
+struct Caps {
+    int cW, cA, cB, cV, cZ;
+    int64_t oU, oW, oA, oB, oV, oZ, total;  // offsets / size in stride units
+};
+
+BTHD Caps make_caps(int cW, int cA, int cB, int cV, int cZ)
+{
+    Caps c;
+    c.cW = cW; c.cA = cA; c.cB = cB; c.cV = cV; c.cZ = cZ;
+    c.oU = 0;
+    c.oW = 4;
+    c.oA = c.oW + 3 * (int64_t)cW + 1;
+    c.oB = c.oA + 3 * (int64_t)cA + 1;
+    c.oV = c.oB + 3 * (int64_t)cB + 1;
+    c.oZ = c.oV + 3 * (int64_t)cV + 1;
+    c.total = c.oZ + 3 * (int64_t)cZ + 1;
+    return c;
+}
+
+// Interleaved fast-path capacities (every stage SMALL_CAP points).
+BTHD Caps small_caps() { return make_caps(SMALL_CAP, SMALL_CAP, SMALL_CAP, SMALL_CAP, SMALL_CAP); }
+
+// Pool-path capacities for children with M points in total: every stage
+// gets 2M + 16 points, far above what nodes produce in practice (about one
+// point more than their inputs).
+BTHD Caps pool_caps(int M, bool buyer)
+{
+    int c = 2 * M + 16;
+    return make_caps(c, buyer ? c : 0, buyer ? c : 0, buyer ? c : 0, c);
+}
+
+// Capacities that can never be exceeded for children with M points in total:
+// MERGE of functions with p and q points yields at most 2(p+q)+1 points, a
+// sweep of ENV at most two points per input point.
+BTHD Caps big_caps(int M, bool buyer)
+{
+    int cW = 2 * M + 1;
+    int cA = buyer ? 2 * cW : 0;
+    int cB = cA;
+    int cV = buyer ? 2 * (cA + cB) + 1 : 0;
+    int cZ = 2 * (1 + (buyer ? cV : cW)) + 1;
+    return make_caps(cW, cA, cB, cV, cZ);
+}
+
+BTD Arr stage(double *base, int st, int64_t off, int cap)
+{
+    Arr a;
+    a.x = base + off * st;
+    a.v = base + (off + cap) * st;
+    a.s = base + (off + 2 * (int64_t)cap) * st;
+    a.st = st;
+    a.cap = cap;
+    return a;
+}
+
+// Exercise payoff (xi, zeta) at stock price S (Section 3 and Section 5):
+// put (K, -1), call (-K, 1), bull spread ((S-K)^+ - (S-K2)^+, 0) in cash.
+BTD void payoff(const Model &md, double S, double &xi, double &zeta)
+{
+    if (md.payoff == PAY_PUT) { xi = md.K; zeta = -1.0; }
+    else if (md.payoff == PAY_CALL) { xi = -md.K; zeta = 1.0; }
+    else {
+        double e1 = S - md.K, e2 = S - md.K2;
+        xi = (e1 > 0.0 ? e1 : 0.0) - (e2 > 0.0 ? e2 : 0.0);
+        zeta = 0.0;
+    }
+}
+
+// base^n by binary powering, multiplying in base^(2^i) for each set bit i
+// in increasing i (the stock lattice S0 u^j of Section 4.1).
+BTD double upow(double base, int n)
+{
+    double acc = 1.0, b = base;
+    bool first = true;
+    while (n > 0) {
+        if (n & 1) { acc = first ? b : acc * b; first = false; }
+        n >>= 1;
+        if (n) b = b * b;
+    }
+    return acc;
+}
+
+// One node of the seller's (SIDE 0) or buyer's (SIDE 1) recursion,
+// Section 3: W = max(z_up, z_down); F = rho W; V = F with slopes restricted
+// to [a, b] = [-(1+k_t) S, -(1-k_t) S] (CLIP for the convex seller, ENV for
+// the buyer); U = the expense function u_t (kink at zeta, value xi for the
+// seller; kink at -zeta, value -xi for the buyer); Z = max(U, V) for the
+// seller, min(U, V) for the buyer, or Z = V when exercise is not allowed at
+// t (European variant).  Temporaries live in `base` with element stride
+// `st` and the capacities of `cp`.  Returns the point count of Z (whose
+// storage is set in *zout) or -1 when a capacity was exceeded.
+template <int SIDE>
+BTD int node_update(const View &Zu, const View &Zd, double S, double kt, double rho,
+                    double xi, double zeta, bool exercise, double *base, int st,
+                    const Caps &cp, Arr *zout)
+{
+    const double a = -((1.0 + kt) * S);
+    const double b = -((1.0 - kt) * S);
+    Arr W = stage(base, st, cp.oW, cp.cW);
+    int mw = merge<OPMAX>(Zu, Zd, W);
+    if (mw < 0) return -1;
+    mw = scale(W, mw, rho);
+    Arr V;
+    int mv;
+    if (SIDE == 0) {
+        mv = clip(W, mw, a, b);
+        V = W;
+    } else {
+        V = stage(base, st, cp.oV, cp.cV);
+        const View Fv = W.view(mw);
+        if (a == b) {
+            int js = 0;
+            double best = 0.0;
+            for (int j = 0; j < mw; j++) {
+                double h = Fv.V(j) - a * Fv.X(j);
+                if (j == 0 || h < best) { best = h; js = j; }
+            }
+            double xs = Fv.X(js), vs = Fv.V(js);
+            V.X(0) = xs; V.V(0) = vs; V.S(0) = a; V.S(1) = a;
+            mv = 1;
+        } else {
+            Arr A = stage(base, st, cp.oA, cp.cA);
+            Arr B = stage(base, st, cp.oB, cp.cB);
+            int ma = sweep_a<false>(Fv, a, A);
+            if (ma < 0) return -1;
+            int mb = sweep_a<true>(Fv, -b, B);
+            if (mb < 0) return -1;
+            mirror_inplace(B, mb);
+            mb = canon(B, mb);
+            mv = merge<OPMIN>(A.view(ma), B.view(mb), V);
+            if (mv < 0) return -1;
+        }
+    }
+    if (!exercise) { *zout = V; return mv; }
+    Arr U = stage(base, st, cp.oU, 1);
+    // U occupies 4 doubles: x, v, s0, s1 (cap 1 -> x, v, s[0..1]).
+    if (SIDE == 0) { U.X(0) = zeta; U.V(0) = xi; }
+    else { U.X(0) = -zeta; U.V(0) = -xi; }
+    U.S(0) = a; U.S(1) = b;
+    Arr Z = stage(base, st, cp.oZ, cp.cZ);
+    int mz = merge<SIDE == 0 ? OPMAX : OPMIN>(U.view(1), V.view(mv), Z);
+    *zout = Z;
+    return mz;
+}
+
+}  // namespace bt

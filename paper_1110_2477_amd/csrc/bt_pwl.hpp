@@ -1,0 +1,370 @@
+// bt_pwl.hpp -- piecewise-linear (PWL) expense functions on gfx950.
+//
+// The seller's and buyer's recursions of Zhang, Roux & Zastawniak (2011),
+// Section 3, act on continuous PWL functions of the stock holding y.  A
+// function is stored as m >= 1 strictly increasing points x[j] with values
+// v[j], and m+1 slopes: s[0] left of x[0], s[j] on (x[j-1], x[j]), s[m]
+// right of x[m-1].  Slopes are carried through every operation, never
+// recomputed from points; a line is one anchor point with s[0] == s[1].
+//
+// Every operation below has one fixed sequence of IEEE binary64 operations
+// (built with -ffp-contract=off), so a node's result does not depend on how
+// the tree is mapped onto lanes, waves or workgroups:
+//   EVAL   f(y) = v[i-1] + s[i](y - x[i-1]) with i = #{x[j] <= y}, or
+//          v[0] + s[0](y - x[0]) when i = 0.
+//   CANON  drop every point whose two adjacent slopes are equal; a function
+//          left with no point keeps its first point as a line anchor.
+//   MERGE  pointwise max or min (Section 3: w_t, and z_t = max/min(u_t, v_t)).
+//   SCALE  the discount w_t / r, as multiplication by rho = 1/r.
+//   CLIP   restriction of a convex function's slopes to [-S^a_t, -S^b_t].
+//   ENV    the same restriction for a general function: the largest
+//          minorant with slopes in [a, b], the cheapest rebalancing at the
+//          ask/bid stock prices, built from a right-to-left sweep (stock
+//          bought at S^a) and a mirrored sweep (stock sold at S^b).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#ifdef BT_HOST_DEBUG
+#define BTD __host__ __device__ inline
+#else
+#define BTD __device__ __forceinline__
+#endif
+
+namespace bt {
+
+// Read view of a PWL function stored with an element stride.
+struct View {
+    const double *x, *v, *s;
+    int m, st;
+    BTD double X(int j) const { return x[(int64_t)j * st]; }
+    BTD double V(int j) const { return v[(int64_t)j * st]; }
+    BTD double S(int j) const { return s[(int64_t)j * st]; }
+};
+
+// Writable storage with room for `cap` points (and cap + 1 slopes).
+struct Arr {
+    double *x, *v, *s;
+    int st, cap;
+    BTD double &X(int j) const { return x[(int64_t)j * st]; }
+    BTD double &V(int j) const { return v[(int64_t)j * st]; }
+    BTD double &S(int j) const { return s[(int64_t)j * st]; }
+    BTD View view(int m) const { return View{x, v, s, m, st}; }
+};
+
+enum { OPMAX = 0, OPMIN = 1 };
+enum { PNONE = -1, PF = 0, PG = 1 };
+
+BTD double eval_at(const View &f, int i, double y)
+{
+    if (i == 0) return f.V(0) + f.S(0) * (y - f.X(0));
+    return f.V(i - 1) + f.S(i) * (y - f.X(i - 1));
+}
+
+BTD double eval(const View &f, double y)
+{
+    int lo = 0, hi = f.m;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (f.X(mid) <= y) lo = mid + 1; else hi = mid;
+    }
+    return eval_at(f, lo, y);
+}
+
+template <int OP> BTD int better(double d)
+{
+    if (OP == OPMAX) return d > 0.0 ? PF : (d < 0.0 ? PG : PNONE);
+    return d < 0.0 ? PF : (d > 0.0 ? PG : PNONE);
+}
+
+template <int OP> BTD double pick(double a, double b)
+{
+    if (OP == OPMAX) return a >= b ? a : b;
+    return a <= b ? a : b;
+}
+
+// Output stream with CANON applied on the fly: a point is stored only if
+// the slope arriving from its left differs from the slope leaving to its
+// right.  Because a dropped point has equal slopes on both sides, the slope
+// arriving at the next point is unchanged by the drop.
+struct Emit {
+    Arr o;
+    int m;
+    bool ovf, have0;
+    double cur, x0, v0;
+    BTD void start(const Arr &out, double s_left)
+    {
+        o = out; m = 0; ovf = false; have0 = false;
+        cur = s_left;
+        o.S(0) = s_left;
+    }
+    BTD void push(double x, double v, double s_right)
+    {
+        if (!have0) { x0 = x; v0 = v; have0 = true; }
+        if (cur != s_right) {
+            if (m < o.cap) { o.X(m) = x; o.V(m) = v; o.S(m + 1) = s_right; }
+            else ovf = true;
+            m++;
+            cur = s_right;
+        }
+    }
+    // Returns the point count, or -1 when the storage was too small.
+    BTD int finish()
+    {
+        if (ovf) return -1;
+        if (m == 0) { o.X(0) = x0; o.V(0) = v0; o.S(1) = o.S(0); m = 1; }
+        return m;
+    }
+};
+
+// In-place CANON of a stored function; returns the new point count.
+BTD int canon(const Arr &f, int m)
+{
+    double s0 = f.S(0);
+    int k = 0;
+    for (int j = 0; j < m; j++) {
+        double sl = f.S(j), sr = f.S(j + 1);
+        // f.S(j) may already hold a kept slope written at index k + 1 <= j;
+        // the slope arriving at point j from its left is the last kept
+        // right slope, which equals the original s[j] whenever points were
+        // dropped (a drop needs equal slopes).
+        if (sl != sr) {
+            double xj = f.X(j), vj = f.V(j);
+            f.X(k) = xj; f.V(k) = vj; f.S(k + 1) = sr;
+            k++;
+        }
+    }
+    f.S(0) = s0;
+    if (k == 0) { f.S(1) = s0; k = 1; }
+    return k;
+}
+
+// MERGE(F, G, op) into `out`; returns the point count or -1 on overflow.
+//  - P is the sorted union of both breakpoint lists (exact duplicates
+//    merged); at every P_k, d_k = EVAL(F, P_k) - EVAL(G, P_k).
+//  - Interval (P_k, P_k+1) with slopes sF != sG and d_k, d_k+1 of strictly
+//    opposite signs crosses at y* = P_k + d_k / (sG - sF); y* <= P_k or
+//    y* >= P_k+1 leaves the whole interval to the winner at the other end.
+//    Without a crossing the winner is the better function at P_k, else at
+//    P_k+1, else the one with the larger (MAX) / smaller (MIN) slope, F on a
+//    full tie.
+//  - Each tail's far winner follows from the slopes (MAX: smaller slope to
+//    the left, larger to the right; MIN reversed); equal slopes fall back to
+//    the sign of d at the end point, then F.  When the end point's winner
+//    differs, the crossing y* = P_ref + d_ref / (sG - sF) is added if it lies
+//    strictly outside the end point.
+//  - Values are op(EVAL(F, y), EVAL(G, y)); slopes are the winner's.
+template <int OP>
+BTD int merge(const View &F, const View &G, const Arr &out)
+{
+    const double INF = __builtin_huge_val();
+    int a = 0, b = 0;
+    // first union point
+    double P, fF, fG, d;
+    int iF, iG;
+    {
+        double xa = F.X(0), xb = G.X(0);
+        if (xa < xb) { P = xa; a = 1; }
+        else if (xb < xa) { P = xb; b = 1; }
+        else { P = xa; a = 1; b = 1; }
+        iF = a; iG = b;
+        fF = eval_at(F, iF, P);
+        fG = eval_at(G, iG, P);
+        d = fF - fG;
+    }
+    Emit e;
+    // left tail
+    {
+        double sF = F.S(0), sG = G.S(0);
+        int b0 = better<OP>(d);
+        int far;
+        if (sF != sG) far = (OP == OPMAX) ? (sF < sG ? PF : PG) : (sF > sG ? PF : PG);
+        else far = (b0 != PNONE) ? b0 : PF;
+        e.start(out, far == PF ? sF : sG);
+        if (sF != sG && b0 != PNONE && b0 != far) {
+            double y = P + (fF - fG) / (sG - sF);
+            if (y < P) e.push(y, pick<OP>(eval_at(F, 0, y), eval_at(G, 0, y)), b0 == PF ? sF : sG);
+        }
+    }
+    for (;;) {
+        double val = pick<OP>(fF, fG);
+        if (a < F.m || b < G.m) {
+            double xa = a < F.m ? F.X(a) : INF, xb = b < G.m ? G.X(b) : INF;
+            double P1;
+            if (xa < xb) { P1 = xa; a++; }
+            else if (xb < xa) { P1 = xb; b++; }
+            else { P1 = xa; a++; b++; }
+            int iF1 = a, iG1 = b;
+            double fF1 = eval_at(F, iF1, P1), fG1 = eval_at(G, iG1, P1);
+            double d1 = fF1 - fG1;
+            double sF = F.S(iF), sG = G.S(iG);
+            int b0 = better<OP>(d), b1 = better<OP>(d1);
+            if (sF != sG && b0 != PNONE && b1 != PNONE && b0 != b1) {
+                double y = P + (fF - fG) / (sG - sF);
+                if (y <= P) {
+                    e.push(P, val, b1 == PF ? sF : sG);
+                } else if (y >= P1) {
+                    e.push(P, val, b0 == PF ? sF : sG);
+                } else {
+                    e.push(P, val, b0 == PF ? sF : sG);
+                    e.push(y, pick<OP>(eval_at(F, iF, y), eval_at(G, iG, y)), b1 == PF ? sF : sG);
+                }
+            } else {
+                int act = b0 != PNONE ? b0 : b1;
+                if (act == PNONE) {
+                    if (OP == OPMAX) act = (sG > sF) ? PG : PF;
+                    else act = (sG < sF) ? PG : PF;
+                }
+                e.push(P, val, act == PF ? sF : sG);
+            }
+            P = P1; iF = iF1; iG = iG1; fF = fF1; fG = fG1; d = d1;
+        } else {
+            // right tail
+            double sF = F.S(F.m), sG = G.S(G.m);
+            int bl = better<OP>(d);
+            int far;
+            if (sF != sG) far = (OP == OPMAX) ? (sF > sG ? PF : PG) : (sF < sG ? PF : PG);
+            else far = (bl != PNONE) ? bl : PF;
+            if (sF != sG && bl != PNONE && bl != far) {
+                double y = P + (fF - fG) / (sG - sF);
+                if (y > P) {
+                    e.push(P, val, bl == PF ? sF : sG);
+                    e.push(y, pick<OP>(eval_at(F, F.m, y), eval_at(G, G.m, y)), far == PF ? sF : sG);
+                } else {
+                    e.push(P, val, far == PF ? sF : sG);
+                }
+            } else {
+                e.push(P, val, far == PF ? sF : sG);
+            }
+            break;
+        }
+    }
+    return e.finish();
+}
+
+// SCALE by rho in place, then CANON.
+BTD int scale(const Arr &f, int m, double rho)
+{
+    for (int j = 0; j < m; j++) f.V(j) = f.V(j) * rho;
+    for (int j = 0; j <= m; j++) f.S(j) = f.S(j) * rho;
+    return canon(f, m);
+}
+
+// CLIP(F, a, b) in place (seller, F convex).  a < b: clamp every slope into
+// [a, b], then CANON.  a == b: the line of slope a through x[q],
+// q = clamp(i0 - 1, 0, m - 1), i0 = min{j : s[j] >= a}.
+BTD int clip(const Arr &f, int m, double a, double b)
+{
+    if (a == b) {
+        int i0 = 0;
+        while (i0 <= m && f.S(i0) < a) i0++;
+        int q = i0 - 1;
+        if (q < 0) q = 0;
+        if (q > m - 1) q = m - 1;
+        double xq = f.X(q), vq = f.V(q);
+        f.X(0) = xq; f.V(0) = vq; f.S(0) = a; f.S(1) = a;
+        return 1;
+    }
+    for (int j = 0; j <= m; j++) {
+        double s = f.S(j);
+        if (s < a) f.S(j) = a;
+        else if (s > b) f.S(j) = b;
+    }
+    return canon(f, m);
+}
+
+// Accessors of F or of its mirror image y -> -y.
+template <bool MIR> struct Src {
+    View f;
+    BTD double X(int j) const { return MIR ? -f.X(f.m - 1 - j) : f.X(j); }
+    BTD double V(int j) const { return MIR ? f.V(f.m - 1 - j) : f.V(j); }
+    BTD double S(int j) const { return MIR ? -f.S(f.m - j) : f.S(j); }
+};
+
+// Reverse points [0, n) and slopes [0, n) in place.
+BTD void reverse_pts(const Arr &o, int n)
+{
+    for (int i = 0, j = n - 1; i < j; i++, j--) {
+        double t;
+        t = o.X(i); o.X(i) = o.X(j); o.X(j) = t;
+        t = o.V(i); o.V(i) = o.V(j); o.V(j) = t;
+        t = o.S(i); o.S(i) = o.S(j); o.S(j) = t;
+    }
+}
+
+// Sweep for A(y) = a y + min_{y' >= y} (F(y') - a y') over F (or its mirror),
+// from the right: h_j = v_j - a x_j with running minimum M at anchor q.
+// Following F to the left, a piece of slope s_j < a starts a flat piece
+// (slope a through (x_q, v_q)) at x_j.  While flat, h_j < M means F dips
+// below the flat line inside (x_j, x_j+1) of slope s_j+1: the switch point
+// y = x_j + (M - h_j) / (s_j+1 - a), valued v_q + a (y - x_q), is added when
+// s_j+1 > a and y > x_j (a y not below x_j+1 is replaced by x_j+1);
+// otherwise the switch happens at x_j.  Output in increasing order, then
+// CANON.  Requires s_0 < a < s_m.  Returns the count or -1 on overflow.
+template <bool MIR>
+BTD int sweep_a(const View &F, double a, const Arr &o)
+{
+    Src<MIR> f{F};
+    const int m = F.m;
+    int n = 0;
+    bool flat = false;
+    int q = -1;
+    double M = 0.0, xq = 0.0, vq = 0.0;
+    double xlast = __builtin_huge_val();
+    for (int j = m - 1; j >= 0; j--) {
+        double xj = f.X(j), vj = f.V(j);
+        double hj = vj - a * xj;
+        bool take = true;
+        if (flat) {
+            if (hj < M) {
+                double sp = f.S(j + 1);
+                if (sp > a) {
+                    double y = xj + (M - hj) / (sp - a);
+                    if (y > xj) {
+                        double xn = f.X(j + 1);
+                        if (!(y < xn)) y = xn;
+                        if (y < xlast) {
+                            if (n >= o.cap) return -1;
+                            o.X(n) = y; o.V(n) = vq + a * (y - xq); o.S(n) = sp;
+                            n++;
+                            xlast = y;
+                        }
+                    }
+                }
+            } else {
+                take = false;
+            }
+        }
+        if (take) {
+            if (n >= o.cap) return -1;
+            double sj = f.S(j);
+            o.X(n) = xj; o.V(n) = vj;
+            if (sj < a) { o.S(n) = a; flat = true; M = hj; q = j; xq = xj; vq = vj; }
+            else { o.S(n) = sj; flat = false; }
+            n++;
+            xlast = xj;
+        }
+    }
+    (void)q;
+    reverse_pts(o, n);
+    o.S(n) = f.S(m);
+    return canon(o, n);
+}
+
+// Mirror in place: x_j <- -x_{n-1-j}, v_j <- v_{n-1-j}, s_j <- -s_{n-j}.
+BTD void mirror_inplace(const Arr &o, int n)
+{
+    for (int i = 0, j = n - 1; i < j; i++, j--) {
+        double t;
+        t = o.X(i); o.X(i) = o.X(j); o.X(j) = t;
+        t = o.V(i); o.V(i) = o.V(j); o.V(j) = t;
+    }
+    for (int i = 0; i < n; i++) o.X(i) = -o.X(i);
+    for (int i = 0, j = n; i < j; i++, j--) {
+        double t = o.S(i); o.S(i) = o.S(j); o.S(j) = t;
+    }
+    for (int i = 0; i <= n; i++) o.S(i) = -o.S(i);
+}
+
+}  // namespace bt

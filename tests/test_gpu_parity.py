@@ -1,0 +1,194 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bar: ask, bid and price0 within 1e-10 relative of the oracle, breakpoint
+totals and maxima equal.  Every node update is the same sequence of binary64
+operations on both sides, so in practice the prices agree to the bit; the
+tests also record that."""
+import os
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1110_2477_amd as bt
+from paper_1110_2477_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+RTOL = 1e-10
+THREADS = min(16, os.cpu_count() or 1)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_all(book, idx=None, threads=THREADS):
+    idx = list(range(len(book))) if idx is None else list(idx)
+    order = sorted(idx, key=lambda i: -int(book[i]["N"]))
+    out = {}
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        futs = {i: ex.submit(oracle.price_params, book[i]) for i in order}
+        for i, f in futs.items():
+            out[i] = f.result()
+    return out
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300) if b != 0 else abs(a)
+
+
+def check(book, res, idx=None, exact=True):
+    ref = oracle_all(book, idx)
+    worst = 0.0
+    n_bitexact = 0
+    for i, o in ref.items():
+        r = res[i]
+        assert r["status"] == 0, (i, r["status"])
+        for key in ("ask", "bid", "price0"):
+            e = rel(r[key], o[key])
+            worst = max(worst, e)
+            assert e <= RTOL, (i, key, r[key], o[key], book[i])
+        n_bitexact += int(r["ask"] == o["ask"] and r["bid"] == o["bid"])
+        for key in ("bp_total_ask", "bp_total_bid", "bp_max_ask", "bp_max_bid"):
+            assert int(r[key]) == o[key], (i, key, int(r[key]), o[key], book[i])
+    say(f"  compared {len(ref)} options: worst rel err {worst:.3g}, bit-exact ask+bid {n_bitexact}/{len(ref)}")
+    return ref
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    bt.lib()
+    yield
+
+
+def test_single_put_n100_book_and_plain():
+    b = W.single_put_n100()
+    say("case: single put N=100 (book)")
+    res = bt.price_book(b)
+    check(b, res)
+    say("case: single put N=100 (bt_price)")
+    r = bt.bt_price(b[0])
+    assert r["status"] == 0
+    assert r["ask"] == res[0]["ask"] and r["bid"] == res[0]["bid"] and r["price0"] == res[0]["price0"]
+
+
+def test_random_small_book():
+    b = W.random_small(240, seed=7, n_max=300)
+    say("case: random small book, 240 options, N <= 300, all payoffs and flags")
+    check(b, bt.price_book(b))
+
+
+@pytest.mark.parametrize("pay", [W.PUT, W.CALL, W.BULL])
+def test_ragged_level_widths(pay):
+    # levels of width 1..513 straddle the 256-lane chunks
+    Ns = [1, 2, 3, 254, 255, 256, 257, 511, 512, 513]
+    b = W.book([dict(S0=100.0, K=100.0, K2=120.0, R=0.05, sigma=0.3, T=1.0, k=0.01, N=n, payoff=pay)
+                for n in Ns])
+    say(f"case: ragged widths payoff {pay}")
+    check(b, bt.price_book(b))
+
+
+def test_paper_grid_n1500():
+    b = W.paper_grid(1500)
+    say("case: 24-option grid N=1500")
+    check(b, bt.price_book(b))
+
+
+def test_paper_grid_n5000():
+    b = W.paper_grid(5000)
+    say("case: 24-option grid N=5000")
+    check(b, bt.price_book(b))
+
+
+def test_mixed_book_sampled():
+    b = W.mixed_book(4096, seed=3)
+    say("case: mixed book 4096 options (one launch), 48 sampled")
+    res = bt.price_book(b)
+    assert np.all(res["status"] == 0)
+    g = np.random.Generator(np.random.PCG64(33))
+    idx = g.choice(len(b), 48, replace=False)
+    check(b, res, idx)
+    # every option: bid <= price0 <= ask
+    assert np.all(res["bid"] <= res["price0"] + 1e-9 * np.abs(res["price0"]) + 1e-12)
+    assert np.all(res["price0"] <= res["ask"] + 1e-9 * np.abs(res["ask"]) + 1e-12)
+
+
+def test_invalid_options_get_status_and_nan():
+    rows = [dict(S0=100.0, K=100.0, R=0.05, sigma=0.2, T=1.0, k=0.005, N=50, payoff=W.PUT),
+            dict(S0=100.0, K=100.0, R=0.05, sigma=0.2, T=1.0, k=1.5, N=50, payoff=W.PUT),
+            dict(S0=100.0, K=100.0, R=9.0, sigma=0.01, T=1.0, k=0.0, N=5, payoff=W.CALL),
+            dict(S0=100.0, K=100.0, R=0.05, sigma=0.2, T=1.0, k=0.005, N=70, payoff=W.BULL, K2=90.0),
+            dict(S0=90.0, K=100.0, R=0.05, sigma=0.2, T=1.0, k=0.005, N=60, payoff=W.CALL)]
+    b = W.book(rows)
+    say("case: invalid options")
+    res = bt.price_book(b)
+    assert list(res["status"]) == [0, bt.BT_EINVAL, bt.BT_EINVAL, bt.BT_EINVAL, 0]
+    for i in (1, 2, 3):
+        assert np.isnan(res[i]["ask"]) and np.isnan(res[i]["bid"]) and np.isnan(res[i]["price0"])
+    check(b, res, [0, 4])
+
+
+def test_repeat_is_bitwise_deterministic():
+    b = W.mixed_book(256, seed=21)
+    say("case: determinism, 256 options priced twice on one book")
+    book = bt.Book(b)
+    book.price()
+    r1 = book.results()
+    book.price()
+    r2 = book.results()
+    book.close()
+    assert r1.tobytes() == r2.tobytes()
+
+
+def test_small_work_buffers_still_exact_or_overflow():
+    # tiny pools force the pool path's admission rounds; a level factor of 1
+    # may not hold the bull spread's levels, which must then be reported, not
+    # corrupted
+    b = W.book([dict(S0=100.0, K=95.0, K2=105.0, R=0.05, sigma=0.3, T=1.0, k=0.01, N=400, payoff=W.BULL),
+                dict(S0=100.0, K=100.0, R=0.05, sigma=0.3, T=1.0, k=0.01, N=600, payoff=W.CALL)])
+    say("case: tiny pool")
+    res = bt.price_book(b, tune=dict(pool_points=4000))
+    check(b, res)
+    say("case: level factor 1")
+    res = bt.price_book(b, tune=dict(level_factor=1), resolve=False)
+    for i in range(len(b)):
+        assert res[i]["status"] in (0, bt.BT_EOVERFLOW)
+        if res[i]["status"] == 0:
+            check(b, res, [i])
+        else:
+            assert np.isnan(res[i]["ask"]) or np.isnan(res[i]["bid"])
+    say("case: level factor 1, overflow resolved")
+    check(b, bt.price_book(b, tune=dict(level_factor=1)))
+
+
+def test_high_cost_book_needs_and_gets_larger_levels():
+    # 2k / (sigma sqrt(dt)) far above 1: breakpoints pile up (several per node
+    # on average), beyond the default level buffers
+    rows = [dict(S0=91.66376974071152, K=105.85787265754652, R=0.058877092247088786,
+                 sigma=0.2265584914357809, T=0.3650944040037588, k=0.031052963817255565, N=292,
+                 payoff=W.CALL),
+            dict(S0=100.0, K=95.0, K2=105.0, R=0.03, sigma=0.15, T=0.5, k=0.05, N=400, payoff=W.BULL),
+            dict(S0=100.0, K=100.0, R=0.03, sigma=0.15, T=0.5, k=0.08, N=500, payoff=W.CALL)]
+    b = W.book(rows)
+    say("case: high-cost book")
+    check(b, bt.price_book(b))
+
+
+def test_long_put_n8192_and_n20000():
+    b = W.book([dict(S0=100.0, K=100.0, R=0.05, sigma=0.4, T=2.0, k=0.01, N=8192, payoff=W.PUT)])
+    say("case: put N=8192")
+    check(b, bt.price_book(b))
+    b = W.long_put()
+    say("case: put N=20000 (properties)")
+    r = bt.price_book(b)[0]
+    assert r["status"] == 0
+    assert r["bid"] <= r["price0"] <= r["ask"] <= 100.0
+    assert r["bp_max_ask"] <= 5 and r["bp_max_bid"] <= 8
+    # zero-cost price of the same tree from the scalar recursion of the oracle
+    o = oracle.price(100.0, 100.0, 0.05, 0.4, 2.0, 0.01, 20000, sides=0)
+    assert rel(r["price0"], o["price0"]) <= RTOL
