@@ -135,7 +135,7 @@ def model_table(S0, sigma, R, T, N):
     return tab, dict(zip(("u", "d", "r", "rho", "p"), consts))
 
 
-MERGE_MAX, MERGE_MIN, SCALE, CLIP, ENV, CANON = range(6)
+MERGE_MAX, MERGE_MIN, SCALE, CLIP, ENV, CANON, ENV_A, ENV_B = range(8)
 
 
 def pwl_op(op, F, G=None, a=0.0, b=0.0):

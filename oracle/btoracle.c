@@ -337,72 +337,62 @@ static void pwl_mirror(const pwl *F, pwl *R)
 
 /*
  * A(y) = a*y + min_{y' >= y} (F(y') - a*y'): the cheapest position reachable
- * by buying stock at S^a (the "slope >= a" half of the inf-convolution).
- * Right-to-left sweep over h[j] = v[j] - a*x[j] with a running minimum M and
- * its anchor q.  On a flat piece A is the line of slope a through
- * (x[q], v[q]).  Following F leftwards, a piece of slope s[j] < a starts a
- * flat piece at x[j].  While flat, if h[j] < M the function dips below the
- * flat line inside the piece (x[j], x[j+1]) of slope s[j+1]; the switch
- * point is y = x[j] + (M - h[j]) / (s[j+1] - a) with value
- * v[q] + a*(y - x[q]), added only if s[j+1] > a and x[j] < y; a y that is
- * not below x[j+1] is replaced by x[j+1].  Otherwise the switch is taken at
- * x[j] itself.  Requires s[0] < a < s[m].
+ * by buying stock at S^a (the "slope >= a" half of the rebalancing
+ * restriction).  With h_j = v_j - a x_j and SM_j = min_{i > j} h_i (anchor
+ * Q_j = the smallest i > j attaining it), on the piece (x_j, x_j+1)
+ * A = min(F, L_j), L_j(y) = v_Q + a (y - x_Q), because the minimum of h over
+ * [y, oo) is either h(y) on the piece or a breakpoint value to the right.
+ * Each piece is of one of three kinds:
+ *   FOLLOW  Q_j = j+1 and s_j+1 >= a: F itself (it touches L_j at x_j+1);
+ *   SPLIT   Q_j > j+1, h_j < SM_j, s_j+1 > a and the crossing
+ *           y = x_j + (SM_j - h_j)/(s_j+1 - a) lies strictly inside: F up to
+ *           y, then L_j; the point y takes the value v_Q + a (y - x_Q); a y
+ *           that rounds onto or past x_j+1 makes the piece FOLLOW;
+ *   FLAT    otherwise: L_j.
+ * The left tail is flat (slope a), the right tail is F (slope s_m > a).
+ * Output: every x_j with value v_j and, after it, the SPLIT point of its
+ * piece; each point carries the slope of the piece to its right; then CANON
+ * (a point whose value would differ from v_j lies between two flat pieces
+ * with one anchor and is dropped).  Requires s_0 < a < s_m.
  */
+enum { PIECE_FLAT = 0, PIECE_FOLLOW = 1, PIECE_SPLIT = 2 };
+
 static void env_scan_a(const pwl *F, num a, pwl *A)
 {
     int m = F->m;
-    /* points collected right to left, each with the slope to its left */
-    num *px = (num *)malloc(sizeof(num) * (2 * m + 2));
-    num *pv = (num *)malloc(sizeof(num) * (2 * m + 2));
-    num *pl = (num *)malloc(sizeof(num) * (2 * m + 2));
-    int n = 0;
-    int flat = 0, q = -1;
-    double M = 0.0;
-    double xlast = INFINITY;  /* smallest x emitted so far */
-    for (int j = m - 1; j >= 0; j--) {
-        num hj = nsub(F->v[j], nmul(a, F->x[j]));
-        int take_point = 1;
-        if (flat) {
-            if (hj.v < M) {
-                num sp = F->s[j + 1];
-                if (sp.v > a.v) {
-                    num hq = nsub(F->v[q], nmul(a, F->x[q]));
-                    num y = nadd(F->x[j], ndiv(nsub(hq, hj), nsub(sp, a)));
-                    if (y.v > F->x[j].v) {
-                        if (!(y.v < F->x[j + 1].v)) y = F->x[j + 1];
-                        if (y.v < xlast) {
-                            px[n] = y;
-                            pv[n] = nadd(F->v[q], nmul(a, nsub(y, F->x[q])));
-                            pl[n] = sp;
-                            xlast = y.v;
-                            n++;
-                        }
-                    }
-                }
-            } else {
-                take_point = 0;   /* still flat through x[j] */
+    num *h = (num *)malloc(sizeof(num) * m);
+    double *SM = (double *)malloc(sizeof(double) * (m + 1));
+    int *Q = (int *)malloc(sizeof(int) * (m + 1));
+    for (int j = 0; j < m; j++) h[j] = nsub(F->v[j], nmul(a, F->x[j]));
+    /* suffix minima strictly right of j, for j = m-2 down to 0 */
+    for (int j = m - 2; j >= 0; j--) {
+        if (j == m - 2 || h[j + 1].v <= SM[j + 1]) { SM[j] = h[j + 1].v; Q[j] = j + 1; }
+        else { SM[j] = SM[j + 1]; Q[j] = Q[j + 1]; }
+    }
+    A->m = 0;
+    pwl_reserve(A, 2 * m);
+    A->s[0] = a;
+    for (int j = 0; j < m; j++) {
+        int kind = PIECE_FLAT;
+        num y = nc(0.0);
+        if (j < m - 1) {
+            num sp = F->s[j + 1];
+            if (Q[j] == j + 1) {
+                if (sp.v >= a.v) kind = PIECE_FOLLOW;
+            } else if (h[j].v < SM[j] && sp.v > a.v) {
+                y = nadd(F->x[j], ndiv(nsub(h[Q[j]], h[j]), nsub(sp, a)));
+                if (!(y.v < F->x[j + 1].v)) kind = PIECE_FOLLOW;
+                else if (y.v > F->x[j].v) kind = PIECE_SPLIT;
             }
         }
-        if (take_point) {
-            px[n] = F->x[j]; pv[n] = F->v[j];
-            if (F->s[j].v < a.v) { pl[n] = a; flat = 1; M = hj.v; q = j; }
-            else { pl[n] = F->s[j]; flat = 0; }
-            xlast = F->x[j].v;
-            n++;
+        num sr = (j == m - 1) ? F->s[m] : (kind != PIECE_FLAT ? F->s[j + 1] : a);
+        push_pt(A, F->x[j], F->v[j], sr);
+        if (kind == PIECE_SPLIT) {
+            int q = Q[j];
+            push_pt(A, y, nadd(F->v[q], nmul(a, nsub(y, F->x[q]))), a);
         }
     }
-    pwl_reserve(A, n);
-    A->m = n;
-    for (int i = 0; i < n; i++) {
-        int src = n - 1 - i;
-        A->x[i] = px[src]; A->v[i] = pv[src];
-        A->s[i] = pl[src];
-    }
-    A->s[n] = F->s[m];
-    /* slope right of point i is the left slope of point i+1 (already set as
-     * A->s[i+1] for i+1 < n) -- the loop above wrote s[i] = left slope of
-     * point i, so s[i+1] is the left slope of point i+1, as required. */
-    free(px); free(pv); free(pl);
+    free(h); free(SM); free(Q);
     pwl_canon(A);
 }
 
@@ -411,7 +401,8 @@ static void env_scan_a(const pwl *F, num a, pwl *A)
  * whose slopes lie in [a, b], i.e. v(y) = inf_delta F(y + delta)
  * + S^a delta^+ - S^b delta^-  (rebalancing at the ask/bid stock prices).
  * It is min(A, B) with A as in env_scan_a and B(y) = b*y + min_{y' <= y}
- * (F(y') - b*y') = mirror(A built on mirror(F) with slope -b).
+ * (F(y') - b*y') = mirror(A built on mirror(F) with slope -b), the
+ * "slope <= b" half (stock sold at S^b).
  * When a == b the result is the line a*y + min_j (v[j] - a*x[j]) anchored at
  * the first minimising point.
  */
@@ -653,7 +644,8 @@ uint64_t API(oracle_flops)(void)
 /* Single PWL operations for unit tests.  Functions travel as (m, x[m], v[m],
  * s[m+1]); the output arrays need room for the documented bound and *mo
  * receives the point count.  op: 0 = MERGE max, 1 = MERGE min, 2 = SCALE by
- * a, 3 = CLIP to [a, b], 4 = ENV to [a, b], 5 = CANON.  Values only. */
+ * a, 3 = CLIP to [a, b], 4 = ENV to [a, b], 5 = CANON, 6 = ENV's buying half
+ * A (slope >= a), 7 = ENV's selling half B (slope <= b).  Values only. */
 static void load(pwl *f, int m, const double *x, const double *v, const double *s)
 {
     pwl_reserve(f, m);
@@ -672,6 +664,15 @@ int API(oracle_pwl_op)(int op, int mF, const double *xF, const double *vF, const
     else if (op == 2) { pwl_copy(&H, &F); pwl_scale(&H, nc(a)); }
     else if (op == 3) pwl_clip(&F, nc(a), nc(b), &H);
     else if (op == 4) pwl_env(&F, nc(a), nc(b), &H);
+    else if (op == 6) env_scan_a(&F, nc(a), &H);
+    else if (op == 7) {   /* the "slope <= b" half: mirror(A(mirror F, -b)) */
+        pwl R = {0}, RB = {0};
+        pwl_mirror(&F, &R);
+        env_scan_a(&R, nc(-b), &RB);
+        pwl_mirror(&RB, &H);
+        pwl_canon(&H);
+        pwl_free(&R); pwl_free(&RB);
+    }
     else { pwl_copy(&H, &F); pwl_canon(&H); }
     int rc = 0;
     if (H.m > cap) rc = -2;

@@ -293,62 +293,64 @@ BTD void reverse_pts(const Arr &o, int n)
     }
 }
 
-// Sweep for A(y) = a y + min_{y' >= y} (F(y') - a y') over F (or its mirror),
-// from the right: h_j = v_j - a x_j with running minimum M at anchor q.
-// Following F to the left, a piece of slope s_j < a starts a flat piece
-// (slope a through (x_q, v_q)) at x_j.  While flat, h_j < M means F dips
-// below the flat line inside (x_j, x_j+1) of slope s_j+1: the switch point
-// y = x_j + (M - h_j) / (s_j+1 - a), valued v_q + a (y - x_q), is added when
-// s_j+1 > a and y > x_j (a y not below x_j+1 is replaced by x_j+1);
-// otherwise the switch happens at x_j.  Output in increasing order, then
-// CANON.  Requires s_0 < a < s_m.  Returns the count or -1 on overflow.
+// A(y) = a y + min_{y' >= y} (F(y') - a y') over F (or its mirror): the
+// buying half of the restriction.  With h_j = v_j - a x_j, SM_j the minimum
+// of h_i over i > j and Q_j the smallest such i attaining it, the piece
+// (x_j, x_j+1) of A is min(F, L_j), L_j(y) = v_Q + a (y - x_Q), one of
+//   FOLLOW  Q_j = j+1 and s_j+1 >= a, or a crossing that rounds onto or past
+//           x_j+1: F;
+//   SPLIT   Q_j > j+1, h_j < SM_j, s_j+1 > a and the crossing
+//           y = x_j + (SM_j - h_j) / (s_j+1 - a) strictly inside: F, then L_j
+//           from y (valued v_Q + a (y - x_Q));
+//   FLAT    otherwise: L_j.
+// Left tail flat (slope a), right tail F.  Points: every x_j with v_j and
+// the SPLIT points, each with the slope to its right; then CANON.  Computed
+// right to left with a running minimum (ties keep the nearer index), written
+// in reverse and flipped.  Requires s_0 < a < s_m.  Returns the count or -1
+// on overflow.
 template <bool MIR>
 BTD int sweep_a(const View &F, double a, const Arr &o)
 {
     Src<MIR> f{F};
     const int m = F.m;
     int n = 0;
-    bool flat = false;
-    int q = -1;
-    double M = 0.0, xq = 0.0, vq = 0.0;
-    double xlast = __builtin_huge_val();
+    double SMc = 0.0, xq = 0.0, vq = 0.0;
+    int Qc = -1;
+    double xr = 0.0;  // x_{j+1}
     for (int j = m - 1; j >= 0; j--) {
-        double xj = f.X(j), vj = f.V(j);
-        double hj = vj - a * xj;
-        bool take = true;
-        if (flat) {
-            if (hj < M) {
-                double sp = f.S(j + 1);
-                if (sp > a) {
-                    double y = xj + (M - hj) / (sp - a);
-                    if (y > xj) {
-                        double xn = f.X(j + 1);
-                        if (!(y < xn)) y = xn;
-                        if (y < xlast) {
-                            if (n >= o.cap) return -1;
-                            o.X(n) = y; o.V(n) = vq + a * (y - xq); o.S(n) = sp;
-                            n++;
-                            xlast = y;
-                        }
-                    }
-                }
-            } else {
-                take = false;
+        const double xj = f.X(j), vj = f.V(j);
+        const double hj = vj - a * xj;
+        double rs;
+        if (j == m - 1) {
+            rs = f.S(m);
+        } else {
+            const double sp = f.S(j + 1);
+            int kind = 0;  // 0 FLAT, 1 FOLLOW, 2 SPLIT
+            double y = 0.0;
+            if (Qc == j + 1) {
+                if (sp >= a) kind = 1;
+            } else if (hj < SMc && sp > a) {
+                y = xj + (SMc - hj) / (sp - a);
+                if (!(y < xr)) kind = 1;
+                else if (y > xj) kind = 2;
             }
+            if (kind == 2) {
+                if (n >= o.cap) return -1;
+                o.X(n) = y; o.V(n) = vq + a * (y - xq); o.S(n) = a;
+                n++;
+            }
+            rs = kind != 0 ? sp : a;
         }
-        if (take) {
-            if (n >= o.cap) return -1;
-            double sj = f.S(j);
-            o.X(n) = xj; o.V(n) = vj;
-            if (sj < a) { o.S(n) = a; flat = true; M = hj; q = j; xq = xj; vq = vj; }
-            else { o.S(n) = sj; flat = false; }
-            n++;
-            xlast = xj;
-        }
+        if (n >= o.cap) return -1;
+        o.X(n) = xj; o.V(n) = vj; o.S(n) = rs;
+        n++;
+        if (j == m - 1 || hj <= SMc) { SMc = hj; Qc = j; xq = xj; vq = vj; }
+        xr = xj;
     }
-    (void)q;
     reverse_pts(o, n);
-    o.S(n) = f.S(m);
+    // s[i] now holds the right slope of point i: shift to s[i+1], left tail a
+    for (int i = n - 1; i >= 0; i--) o.S(i + 1) = o.S(i);
+    o.S(0) = a;
     return canon(o, n);
 }
 

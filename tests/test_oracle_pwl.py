@@ -111,6 +111,46 @@ def test_env_is_restriction_for_nonconvex(seed):
     assert np.allclose(got, want, rtol=1e-10, atol=1e-8), np.max(np.abs(got - want))
 
 
+@pytest.mark.parametrize("seed", range(120))
+def test_env_degenerate_slopes_and_ties(seed):
+    # pieces with slope exactly a or b make h = v - a x tie between
+    # neighbouring points and put crossings on piece ends; the result must
+    # still be the restriction (values; 1-ulp slivers are allowed)
+    rng = np.random.default_rng(1000 + seed)
+    m = int(rng.integers(2, 30))
+    x = np.sort(rng.uniform(-5, 5, m))
+    if np.any(np.diff(x) <= 0):
+        return
+    a, b = np.sort(rng.uniform(-120, -40, 2))
+    s = rng.uniform(-150, -20, m + 1)
+    u = rng.random(m + 1)
+    s[u < 0.15] = a
+    s[(u >= 0.15) & (u < 0.3)] = b
+    s[0] = min(s[0], a - rng.uniform(1, 30))
+    s[-1] = max(s[-1], b + rng.uniform(1, 30))
+    v = np.empty(m)
+    v[0] = rng.uniform(-50, 50)
+    for j in range(1, m):
+        v[j] = v[j - 1] + s[j] * (x[j] - x[j - 1])
+    F = (x, v, s)
+    H = oracle.pwl_op(oracle.ENV, F, a=a, b=b)
+    assert np.all(np.diff(H[0]) > 0)
+    assert H[2][0] == a and H[2][-1] == b
+    ys = np.concatenate([np.linspace(x.min() - 3, x.max() + 3, 300), x, H[0]])
+    want = D.infconv_brute(F, -a, -b, ys)
+    got = D.pwl_eval_np(H, ys)
+    assert np.all(np.abs(got - want) <= 1e-10 * (1 + np.abs(want)))
+    # the two halves: A has slopes >= a (buying), B slopes <= b (selling)
+    A = oracle.pwl_op(oracle.ENV_A, F, a=a, b=b)
+    B = oracle.pwl_op(oracle.ENV_B, F, a=a, b=b)
+    assert A[2][0] == a and B[2][-1] == b
+    ya = np.concatenate([ys, A[0]])
+    hA = np.array([min(D.pwl_eval_np(F, np.array([yy]))[0] - a * yy,
+                       (D.pwl_eval_np(F, x[x >= yy]) - a * x[x >= yy]).min() if np.any(x >= yy) else np.inf)
+                   for yy in ya]) + a * ya
+    assert np.allclose(D.pwl_eval_np(A, ya), hA, rtol=1e-10, atol=1e-8)
+
+
 @pytest.mark.parametrize("seed", range(20))
 def test_env_equals_clip_on_convex(seed):
     rng = np.random.default_rng(300 + seed)
