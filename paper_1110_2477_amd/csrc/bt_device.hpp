@@ -54,28 +54,6 @@ BTHD Caps make_caps(int cW, int cA, int cB, int cV, int cZ)
 // Interleaved fast-path capacities (every stage SMALL_CAP points).
 BTHD Caps small_caps() { return make_caps(SMALL_CAP, SMALL_CAP, SMALL_CAP, SMALL_CAP, SMALL_CAP); }
 
-// Pool-path capacities for children with M points in total: every stage
-// gets 2M + 16 points, far above what nodes produce in practice (about one
-// point more than their inputs).
-BTHD Caps pool_caps(int M, bool buyer)
-{
-    int c = 2 * M + 16;
-    return make_caps(c, buyer ? c : 0, buyer ? c : 0, buyer ? c : 0, c);
-}
-
-// Capacities that can never be exceeded for children with M points in total:
-// MERGE of functions with p and q points yields at most 2(p+q)+1 points, a
-// sweep of ENV at most two points per input point.
-BTHD Caps big_caps(int M, bool buyer)
-{
-    int cW = 2 * M + 1;
-    int cA = buyer ? 2 * cW : 0;
-    int cB = cA;
-    int cV = buyer ? 2 * (cA + cB) + 1 : 0;
-    int cZ = 2 * (1 + (buyer ? cV : cW)) + 1;
-    return make_caps(cW, cA, cB, cV, cZ);
-}
-
 BTD Arr stage(double *base, int st, int64_t off, int cap)
 {
     Arr a;

@@ -1,15 +1,25 @@
 // bt_kernels.hip -- gfx950 kernels of libbtprice and the C ABI around them.
 //
-// One persistent kernel prices a book.  Every option contributes three work
-// items -- the seller's recursion (ask), the buyer's recursion (bid) and the
-// zero-cost recursion (price0) -- handed out longest-first from a queue in
-// device memory.  A workgroup of 256 lanes takes one item at a time and
-// sweeps its tree from level N+1 to the root (Section 3 recursions; tree of
-// Section 4.1), one lane per node and 256 nodes per chunk, holding the
-// current and the next level as packed variable-length records.  Node
-// temporaries live in an interleaved per-lane area (coalesced across the
-// wave); a node whose breakpoints overflow it is redone on a pool path whose
-// capacities cannot be exceeded, admitted by a workgroup prefix sum.
+// Seller (ask) and buyer (bid) recursions of Section 3 on the tree of
+// Section 4.1.  Every tree side (option x party) is swept from level N+1 to
+// the root in bands of BAND levels.  A band is cut into column blocks of
+// BLOCK_COLS output columns; the workgroup that owns a block also recomputes
+// the halo of up to BAND-1 columns to its right that its trapezoid needs, so
+// the blocks of a band are independent (the block/region partition of
+// Section 4.2, with the region that would wait for a neighbour recomputed
+// instead).  Consecutive bands are separated by kernel boundaries.  Band
+// tasks of all tree sides of a book are handed to persistent workgroups from
+// one counter per (band, party).
+//
+// Inside a block one lane owns one column; a level's records are packed
+// variable-length PWL functions in per-workgroup buffers, the band's input
+// and output levels live in per-tree-side buffers.  Node temporaries live in
+// an interleaved per-lane area (coalesced across the wave); nodes with many
+// breakpoints are collected per level and computed one per wavefront by the
+// cooperative path of bt_wave.hpp.
+//
+// The zero-cost recursion runs in its own persistent kernel, one workgroup
+// per option.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -17,31 +27,55 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
-#include <mutex>
 #include <new>
 #include <vector>
 
 #include "../../include/bt.h"
 #include "bt_device.hpp"
+#include "bt_wave.hpp"
 
 using namespace bt;
 
 namespace {
 
+constexpr int BAND = 32;                   // levels per band
+constexpr int BLOCK_COLS = WG - BAND;      // output columns per block (+ halo <= WG)
+
+// One tree side: option `opt`, party `side` (0 seller, 1 buyer); offsets of
+// its two band-boundary level buffers (doubles) and index arrays (ints).
+struct Item {
+    int opt, side, N, nbands;
+    int64_t lbuf, lcap;     // doubles: two buffers of lcap each at lbuf
+    int64_t ibuf;           // ints: off[2][N+2], cnt[2][N+2]
+    int64_t ctr;            // index of the first of nbands+1 fill counters
+};
+
+struct Task {
+    int item, block;
+};
+
 struct KArgs {
     const Model *models;
-    const int *sched;
-    int n_items;
-    int *queue;
+    const Item *items;
+    const Task *tasks;
+    const int *task_off;    // [2 * nbands_max + 1]: tasks of (band r, side s) at r*2+s
+    int *band_ctr;          // persistent-workgroup counters, [2 * nbands_max]
+    unsigned long long *fill;   // band-buffer fill counters
+    int *failed;            // per item
+    int n_opts, n_items, nbands_max;
     bt_result *out;
-    double *ws;
-    int64_t ws_doubles;  // per workgroup
-    int *wsi;
-    int64_t wsi_ints;    // per workgroup
-    int n_max;
-    int64_t lcapd;       // doubles per level buffer
-    int64_t pool;        // doubles in the pool
-    int64_t oStab, oL0, oL1, oSmall, oPool;
+    double *lvl;            // tree-side band buffers
+    int *lvli;
+    double *ws;             // per workgroup: private levels, Stab, small area, pool
+    int64_t ws_doubles;
+    int *wsi;               // per workgroup: private level index arrays
+    int64_t wsi_ints;
+    int64_t pcap;           // doubles per private level buffer
+    int64_t pool;           // doubles in the pool
+    int64_t oStab, oP0, oP1, oSmall, oPool;
+    int *p0_queue;
+    const int *p0_sched;
+    int n_p0;
 };
 
 // Exclusive prefix sum over the workgroup; *total gets the sum.
@@ -83,6 +117,7 @@ __device__ __forceinline__ void write_record(double *dst, const Arr &z, int m)
     }
 }
 
+// Stock lattice S0 u^j for j = -(N+1)..N+1 (Section 4.1), by binary powering.
 __device__ void stock_table(const Model &md, double *Stab)
 {
     const int N = md.N;
@@ -93,14 +128,277 @@ __device__ void stock_table(const Model &md, double *Stab)
     }
 }
 
+// Stock price at lattice index j without a table (same binary powering).
+__device__ __forceinline__ double stock_at(const Model &md, int j)
+{
+    return md.S0 * (j >= 0 ? upow(md.u, j) : upow(md.d, -j));
+}
+
+// Level N+1 of every tree side: the liquidation value y^- S^a - y^+ S^b
+// (payoff (0, 0), Section 4.1), record [-(1+k) S, 0, 0, -(1-k) S], in band
+// buffer 0.
+__global__ void bt_init_kernel(KArgs A)
+{
+    const int it = blockIdx.y;
+    if (it >= A.n_items) return;
+    const Item I = A.items[it];
+    const Model md = A.models[I.opt];
+    const int N = I.N;
+    double *L = A.lvl + I.lbuf;
+    int *off = A.lvli + I.ibuf, *cnt = off + 2 * (int64_t)(N + 2);
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c <= N + 1; c += gridDim.x * blockDim.x) {
+        const double S = stock_at(md, 2 * c - (N + 1));
+        const double Sa = (1.0 + md.k) * S, Sb = (1.0 - md.k) * S;
+        double *r = L + 4 * (int64_t)c;
+        r[0] = -Sa; r[1] = 0.0; r[2] = 0.0; r[3] = -Sb;
+        off[c] = 4 * c;
+        cnt[c] = 1;
+    }
+}
+
+// One band task: block `blk` of band `r` of tree side `item`.
+template <int SIDE>
+__device__ void band_task(const KArgs &A, int r, int item, int blk, int64_t *sh, int *sflag)
+{
+    __shared__ int sbig[WG];
+    __shared__ unsigned long long sloff;
+    __shared__ unsigned long long sbase;
+    const int tid = threadIdx.x;
+    const Item I = A.items[item];
+    const Model md = A.models[I.opt];
+    const int N = I.N;
+    const int t_top = N - r * BAND;
+    const int t_bot = t_top - BAND + 1 > 0 ? t_top - BAND + 1 : 0;
+    const int c0 = blk * BLOCK_COLS;
+    const int c1 = min(c0 + BLOCK_COLS, t_bot + 1);
+    const bool last = c1 == t_bot + 1;
+
+    double *ws = A.ws + (int64_t)blockIdx.x * A.ws_doubles;
+    int *wsi = A.wsi + (int64_t)blockIdx.x * A.wsi_ints;
+    double *Stab = ws + A.oStab;
+    double *Pb[2] = {ws + A.oP0, ws + A.oP1};
+    int *poff[2] = {wsi, wsi + WG + 1};
+    int *pcnt[2] = {wsi + 2 * (WG + 1), wsi + 3 * (WG + 1)};
+    double *small = ws + A.oSmall;
+    double *pool = ws + A.oPool;
+    // band-boundary buffers of this tree side
+    const int64_t NN = N + 2;
+    const double *Lin = A.lvl + I.lbuf + (int64_t)(r & 1) * I.lcap;
+    double *Lout = A.lvl + I.lbuf + (int64_t)((r + 1) & 1) * I.lcap;
+    const int *offin = A.lvli + I.ibuf + (int64_t)(r & 1) * NN;
+    const int *cntin = A.lvli + I.ibuf + 2 * NN + (int64_t)(r & 1) * NN;
+    int *offout = A.lvli + I.ibuf + (int64_t)((r + 1) & 1) * NN;
+    int *cntout = A.lvli + I.ibuf + 2 * NN + (int64_t)((r + 1) & 1) * NN;
+
+    // stock prices of the lattice indices this block touches:
+    // j = 2c - t for c in [c0, c0 + WG], t in [t_bot, t_top]
+    const int jlo = 2 * c0 - t_top, jhi = 2 * (c0 + WG) - t_bot;
+    for (int j = jlo + tid; j <= jhi; j += WG) Stab[j - jlo] = stock_at(md, j);
+    if (tid == 0) *sflag = 0;
+    __syncthreads();
+
+    const Caps sc = small_caps();
+    const bool euro = (md.flags & F_EUROPEAN) != 0;
+    int64_t bp_sum = 0;
+    int bp_max = 0;
+    bool fatal = false;
+    int cur = 0;
+    for (int t = t_top; t >= t_bot && !fatal; t--) {
+        const double kt = (t >= 1 || (md.flags & F_COST_AT_T0)) ? md.k : 0.0;
+        const bool exercise = !(euro && t < N);
+        const int right = last ? t + 1 : min(c1 + (t - t_bot), t + 1);  // columns [c0, right)
+        // children: the band's input level, or the previous private level
+        const bool first = t == t_top;
+        const double *Lc = first ? Lin : Pb[cur ^ 1];
+        const int *offc = first ? offin + c0 : poff[cur ^ 1];
+        const int *cntc = first ? cntin + c0 : pcnt[cur ^ 1];
+        double *Ln = Pb[cur];
+        int *offn = poff[cur], *cntn = pcnt[cur];
+        const int i = tid;            // column c0 + i
+        const int c = c0 + i;
+        const bool act = c < right;
+        View Zu{}, Zd{};
+        double S = 0.0, xi = 0.0, ze = 0.0;
+        int M = 0;
+        if (act) {
+            Zd = record_view(Lc, offc[i], cntc[i]);
+            Zu = record_view(Lc, offc[i + 1], cntc[i + 1]);
+            M = cntc[i] + cntc[i + 1];
+            S = Stab[2 * c - t - jlo];
+            payoff(md, S, xi, ze);
+        }
+        const bool owned = c < c1 || last;
+        Arr Z{};
+        int mz = 0;
+        bool big = act && M > SMALL_CAP;
+        if (act && !big) {
+            mz = node_update<SIDE>(Zu, Zd, S, kt, md.rho, xi, ze, exercise, small + tid, WG, sc, &Z);
+            big = mz < 0;
+        }
+        // one scan for the record sizes (low 40 bits) and the big-node count
+        const int64_t sz = (act && !big) ? 3 * (int64_t)mz + 1 : 0;
+        const int64_t LOW = ((int64_t)1 << 40) - 1;
+        int64_t tot;
+        const int64_t ex = block_scan(sz + (big ? ((int64_t)1 << 40) : 0), &tot, sh);
+        const int64_t nbig = tot >> 40, bix = ex >> 40, exs = ex & LOW;
+        tot &= LOW;
+        if (tot > A.pcap) {
+            fatal = true;
+        } else if (sz) {
+            write_record(Ln + exs, Z, mz);
+            offn[i] = (int)exs;
+            cntn[i] = mz;
+            if (owned) {
+                const int bp = (mz == 1 && Z.S(0) == Z.S(1)) ? 0 : mz;
+                bp_sum += bp;
+                bp_max = bp > bp_max ? bp : bp_max;
+            }
+        }
+        int64_t loff = tot;
+        if (nbig > 0 && !fatal) {
+            if (big) sbig[bix] = i;
+            if (tid == 0) sloff = (unsigned long long)loff;
+            __syncthreads();
+            const int w = tid >> 6, lane = tid & 63;
+            const int64_t slice = A.pool / NWAVE;
+            for (int bi = w; bi < (int)nbig; bi += NWAVE) {
+                const int ii = sbig[bi];
+                const int cc = c0 + ii;
+                const View Zd2 = record_view(Lc, offc[ii], cntc[ii]);
+                const View Zu2 = record_view(Lc, offc[ii + 1], cntc[ii + 1]);
+                const double S2 = Stab[2 * cc - t - jlo];
+                double xi2, ze2;
+                payoff(md, S2, xi2, ze2);
+                WaveTmp T{pool + w * slice, slice, 0};
+                Arr Zb;
+                const int mzb = wave_node_update<SIDE>(Zu2, Zd2, S2, kt, md.rho, xi2, ze2, exercise, T, &Zb);
+                if (mzb < 0) {
+                    if (lane == 0) *sflag = 1;
+                    continue;
+                }
+                const int64_t rec = 3 * (int64_t)mzb + 1;
+                unsigned long long pos = 0;
+                if (lane == 0) pos = atomicAdd(&sloff, (unsigned long long)rec);
+                pos = __shfl(pos, 0, 64);
+                if ((int64_t)pos + rec > A.pcap) {
+                    if (lane == 0) *sflag = 1;
+                    continue;
+                }
+                double *dst = Ln + pos;
+                for (int j = lane; j < mzb; j += 64) {
+                    dst[1 + 3 * j] = Zb.X(j);
+                    dst[2 + 3 * j] = Zb.V(j);
+                    dst[3 + 3 * j] = Zb.S(j + 1);
+                }
+                if (lane == 0) {
+                    dst[0] = Zb.S(0);
+                    offn[ii] = (int)pos;
+                    cntn[ii] = mzb;
+                    if (cc < c1 || last) {
+                        const int bp = (mzb == 1 && Zb.S(0) == Zb.S(1)) ? 0 : mzb;
+                        bp_sum += bp;
+                        bp_max = bp > bp_max ? bp : bp_max;
+                    }
+                }
+            }
+            __syncthreads();
+            loff = (int64_t)sloff;
+            if (*sflag) fatal = true;
+        }
+        __syncthreads();
+        if (t == t_bot && !fatal) {
+            // the band's output level (columns [c0, c1)) goes to the tree
+            // side's band buffer; level 0 gives the price
+            if (tid == 0) {
+                sbase = atomicAdd(A.fill + I.ctr + r + 1, (unsigned long long)loff);
+                if ((int64_t)sbase + loff > I.lcap) *sflag = 1;
+            }
+            __syncthreads();
+            if (*sflag) {
+                fatal = true;
+            } else {
+                const int64_t base = (int64_t)sbase;
+                for (int64_t q = tid; q < loff; q += WG) Lout[base + q] = Ln[q];
+                if (tid < c1 - c0) {
+                    offout[c0 + tid] = (int)(base + offn[tid]);
+                    cntout[c0 + tid] = cntn[tid];
+                }
+                if (t == 0 && tid == 0) {
+                    const double root = eval(record_view(Ln, offn[0], cntn[0]), 0.0);
+                    if (SIDE == 0) A.out[I.opt].ask = root;
+                    else A.out[I.opt].bid = -root;
+                }
+            }
+        }
+        cur ^= 1;
+    }
+
+    // breakpoint statistics of the owned columns
+    __shared__ int64_t rs[NWAVE];
+    __shared__ int rm[NWAVE];
+    int64_t s = bp_sum;
+    int mx = bp_max;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        s += __shfl_down(s, o, 64);
+        int y = __shfl_down(mx, o, 64);
+        mx = y > mx ? y : mx;
+    }
+    if ((tid & 63) == 0) { rs[tid >> 6] = s; rm[tid >> 6] = mx; }
+    __syncthreads();
+    if (tid == 0) {
+        int64_t ts = 0;
+        int tm = 0;
+        for (int w = 0; w < NWAVE; w++) { ts += rs[w]; tm = rm[w] > tm ? rm[w] : tm; }
+        bt_result &o = A.out[I.opt];
+        if (fatal) {
+            atomicMin(&o.status, BT_EOVERFLOW);
+            atomicExch(A.failed + item, 1);
+        } else {
+            atomicAdd((unsigned long long *)(SIDE == 0 ? &o.bp_total_ask : &o.bp_total_bid),
+                      (unsigned long long)ts);
+            atomicMax(SIDE == 0 ? &o.bp_max_ask : &o.bp_max_bid, tm);
+        }
+    }
+    __syncthreads();
+}
+
+// Band r of every tree side of one party, on persistent workgroups.
+template <int SIDE>
+__global__ __launch_bounds__(WG) void bt_band_kernel(KArgs A, int r)
+{
+    __shared__ int s_task, s_skip;
+    __shared__ int s_flag;
+    __shared__ int64_t s_scan[NWAVE];
+    const int lo = A.task_off[2 * r + SIDE], hi = A.task_off[2 * r + SIDE + 1];
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const int q0 = lo + atomicAdd(A.band_ctr + 2 * r + SIDE, 1);
+            s_task = q0;
+            // a tree side whose earlier work overflowed is skipped (one read,
+            // shared by the whole workgroup)
+            s_skip = q0 < hi ? __hip_atomic_load(A.failed + A.tasks[q0].item, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT)
+                             : 0;
+        }
+        __syncthreads();
+        const int q = s_task, skip = s_skip;
+        __syncthreads();
+        if (q >= hi) break;
+        if (skip) continue;
+        const Task tk = A.tasks[q];
+        band_task<SIDE>(A, r, tk.item, tk.block, s_scan, &s_flag);
+    }
+}
+
 // Zero-cost recursion (Section 3, Appendix): no extra level;
 // V_N = max(xi + zeta S, 0), V_t = max(xi + zeta S, rho (p V_up + (1-p) V_dn))
-// (European variant: V_t = continuation value).
+// (European variant: V_t = continuation value).  One workgroup per option.
 __device__ void price0_item(const KArgs &A, const Model &md, int opt, double *ws)
 {
     const int N = md.N;
     double *Stab = ws + A.oStab;
-    double *V0 = ws + A.oL0, *V1 = ws + A.oL1;
+    double *V0 = ws + A.oPool, *V1 = ws + A.oPool + (N + 1);
     stock_table(md, Stab);
     __syncthreads();
     const bool euro = (md.flags & F_EUROPEAN) != 0;
@@ -129,179 +427,43 @@ __device__ void price0_item(const KArgs &A, const Model &md, int opt, double *ws
     if (threadIdx.x == 0) A.out[opt].price0 = cur[0];
 }
 
-// Seller (SIDE 0) or buyer (SIDE 1) recursion of Section 3 for one option.
-template <int SIDE>
-__device__ void side_item(const KArgs &A, const Model &md, int opt, double *ws, int *wsi,
-                          int64_t *sh, int *sflag)
-{
-    const int N = md.N;
-    const int tid = threadIdx.x;
-    double *Stab = ws + A.oStab;
-    double *Lb[2] = {ws + A.oL0, ws + A.oL1};
-    int *offb[2] = {wsi, wsi + 2 * (A.n_max + 2)};
-    int *cntb[2] = {wsi + (A.n_max + 2), wsi + 3 * (A.n_max + 2)};
-    double *small = ws + A.oSmall;
-    double *pool = ws + A.oPool;
-
-    stock_table(md, Stab);
-    if (tid == 0) *sflag = 0;
-    __syncthreads();
-    // level N+1: liquidation y^- S^a - y^+ S^b (payoff (0, 0)), record
-    // [s0, x0, v0, s1] = [-(1+k) S, 0, 0, -(1-k) S]
-    for (int c = tid; c <= N + 1; c += WG) {
-        double S = Stab[2 * c];
-        double Sa = (1.0 + md.k) * S, Sb = (1.0 - md.k) * S;
-        double *r = Lb[0] + 4 * (int64_t)c;
-        r[0] = -Sa; r[1] = 0.0; r[2] = 0.0; r[3] = -Sb;
-        offb[0][c] = 4 * c;
-        cntb[0][c] = 1;
-    }
-    __syncthreads();
-
-    const Caps sc = small_caps();
-    const bool euro = (md.flags & F_EUROPEAN) != 0;
-    int64_t bp_sum = 0;
-    int bp_max = 0;
-    bool fatal = false;
-    int cur = 0;
-    for (int t = N; t >= 0 && !fatal; t--) {
-        const double kt = (t >= 1 || (md.flags & F_COST_AT_T0)) ? md.k : 0.0;
-        const bool exercise = !(euro && t < N);
-        const double *Lc = Lb[cur];
-        const int *offc = offb[cur], *cntc = cntb[cur];
-        double *Ln = Lb[cur ^ 1];
-        int *offn = offb[cur ^ 1], *cntn = cntb[cur ^ 1];
-        int64_t loff = 0;
-        for (int cb = 0; cb <= t && !fatal; cb += WG) {
-            const int c = cb + tid;
-            const bool act = c <= t;
-            View Zu{}, Zd{};
-            double S = 0.0, xi = 0.0, ze = 0.0;
-            int M = 0;
-            if (act) {
-                Zd = record_view(Lc, offc[c], cntc[c]);
-                Zu = record_view(Lc, offc[c + 1], cntc[c + 1]);
-                M = cntc[c] + cntc[c + 1];
-                S = Stab[2 * c - t + N + 1];
-                payoff(md, S, xi, ze);
-            }
-            // Rounds: round 0 runs every node on the interleaved area; later
-            // rounds rerun the nodes that overflowed it on the pool, tier 1
-            // with generous capacities, tier 2 with capacities that cannot be
-            // exceeded, admitted by a prefix sum over the pool size.
-            int tier = act ? 0 : -1;
-            for (int round = 0; !fatal; round++) {
-                if (round > 0 && !__syncthreads_or(tier >= 1)) break;
-                Caps cp = sc;
-                double *base = small + tid;
-                int st = WG;
-                bool run = (round == 0) ? (tier == 0) : false;
-                if (round > 0) {
-                    cp = tier == 2 ? big_caps(M, SIDE == 1) : pool_caps(M, SIDE == 1);
-                    int64_t need = tier >= 1 ? cp.total : 0, ntot;
-                    int64_t nex = block_scan(need, &ntot, sh);
-                    run = tier >= 1 && (nex + need <= A.pool);
-                    if (tier >= 1 && nex == 0 && need > A.pool) *sflag = 1;
-                    base = pool + nex;
-                    st = 1;
-                }
-                Arr Z{};
-                int mz = 0;
-                if (run) {
-                    mz = node_update<SIDE>(Zu, Zd, S, kt, md.rho, xi, ze, exercise, base, st, cp, &Z);
-                    if (mz < 0 && tier == 2) *sflag = 1;
-                }
-                int64_t sz = (run && mz > 0) ? 3 * (int64_t)mz + 1 : 0, tot;
-                int64_t ex = block_scan(sz, &tot, sh);
-                if (*sflag || loff + tot > A.lcapd) {
-                    fatal = true;
-                } else if (sz) {
-                    write_record(Ln + loff + ex, Z, mz);
-                    offn[c] = (int)(loff + ex);
-                    cntn[c] = mz;
-                    int bp = (mz == 1 && Z.S(0) == Z.S(1)) ? 0 : mz;
-                    bp_sum += bp;
-                    bp_max = bp > bp_max ? bp : bp_max;
-                }
-                loff += tot;
-                if (run) tier = (mz > 0) ? -1 : (tier == 0 ? 1 : 2);
-            }
-        }
-        __syncthreads();
-        cur ^= 1;
-    }
-
-    // workgroup reduction of the breakpoint statistics
-    __shared__ int64_t rs[NWAVE];
-    __shared__ int rm[NWAVE];
-    int64_t s = bp_sum;
-    int mx = bp_max;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        s += __shfl_down(s, o, 64);
-        int y = __shfl_down(mx, o, 64);
-        mx = y > mx ? y : mx;
-    }
-    if ((tid & 63) == 0) { rs[tid >> 6] = s; rm[tid >> 6] = mx; }
-    __syncthreads();
-    if (tid == 0) {
-        int64_t ts = 0;
-        int tm = 0;
-        for (int w = 0; w < NWAVE; w++) { ts += rs[w]; tm = rm[w] > tm ? rm[w] : tm; }
-        bt_result &o = A.out[opt];
-        if (fatal) {
-            atomicMin(&o.status, BT_EOVERFLOW);
-        } else {
-            View z0 = record_view(Lb[cur], offb[cur][0], cntb[cur][0]);
-            double root = eval(z0, 0.0);
-            if (SIDE == 0) { o.ask = root; o.bp_total_ask = ts; o.bp_max_ask = tm; }
-            else { o.bid = -root; o.bp_total_bid = ts; o.bp_max_bid = tm; }
-        }
-    }
-    __syncthreads();
-}
-
-// One persistent kernel per kind of work item (ask, bid, price0), each with
-// its own longest-first queue; splitting the kinds keeps each kernel's
-// register footprint to that of one recursion.
-template <int KIND>
-__global__ __launch_bounds__(WG) void bt_item_kernel(KArgs A)
+__global__ __launch_bounds__(WG) void bt_price0_kernel(KArgs A)
 {
     __shared__ int s_item;
-    __shared__ int s_flag;
-    __shared__ int64_t s_scan[NWAVE];
     double *ws = A.ws + (int64_t)blockIdx.x * A.ws_doubles;
-    int *wsi = A.wsi + (int64_t)blockIdx.x * A.wsi_ints;
     for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(A.queue + KIND, 1);
+        if (threadIdx.x == 0) s_item = atomicAdd(A.p0_queue, 1);
         __syncthreads();
         const int q = s_item;
         __syncthreads();
-        if (q >= A.n_items) break;
-        const int opt = A.sched[q];
+        if (q >= A.n_p0) break;
+        const int opt = A.p0_sched[q];
         const Model md = A.models[opt];
-        if (!md.valid) continue;
-        if (KIND == KIND_PRICE0) price0_item(A, md, opt, ws);
-        else side_item<KIND>(A, md, opt, ws, wsi, s_scan, &s_flag);
+        price0_item(A, md, opt, ws);
         __syncthreads();
     }
 }
 
-// Initialises results (NaN prices, zero counts, status) and the queue.
-__global__ void bt_reset_kernel(const Model *models, int n, bt_result *out, int *queue)
+// Initialises results (NaN prices, zero counts, status), queues, fill
+// counters and failure flags.
+__global__ void bt_reset_kernel(KArgs A, int64_t n_fill)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < 4) queue[i] = 0;
-    if (i < n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = i; k < A.n_opts; k += stride) {
         const double nan = __builtin_nan("");
         bt_result r;
         r.ask = nan; r.bid = nan; r.price0 = nan;
         r.bp_total_ask = 0; r.bp_total_bid = 0;
         r.bp_max_ask = 0; r.bp_max_bid = 0;
-        r.status = models[i].valid ? BT_OK : BT_EINVAL;
+        r.status = A.models[k].valid ? BT_OK : BT_EINVAL;
         r.reserved = 0;
-        out[i] = r;
+        A.out[k] = r;
     }
+    for (int64_t k = i; k < 2 * (int64_t)A.nbands_max; k += stride) A.band_ctr[k] = 0;
+    for (int64_t k = i; k < n_fill; k += stride) A.fill[k] = 0;
+    for (int64_t k = i; k < A.n_items; k += stride) A.failed[k] = 0;
+    if (i == 0) *A.p0_queue = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -347,18 +509,24 @@ bool derive(const bt_params &p, Model &m)
     return true;
 }
 
+int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
 }  // namespace
 
 struct bt_book {
     int device = 0;
-    int n = 0, n_max = 0, n_items = 0;
-    int64_t nodes = 0;
-    int grid = 0;
-    int level_factor = 4;
-    int64_t pool_doubles = 0;
+    int n = 0, n_max = 0, n_items = 0, nbands_max = 0;
+    int64_t nodes = 0, n_fill = 0;
+    int grid = 0, grid_p0 = 0;
+    std::vector<int> ntasks;       // per (band, side)
     Model *d_models = nullptr;
-    int *d_sched = nullptr;
-    int *d_queue = nullptr;
+    Item *d_items = nullptr;
+    Task *d_tasks = nullptr;
+    int *d_task_off = nullptr;
+    int *d_ints = nullptr;         // band counters, failure flags, price0 queue and schedule
+    unsigned long long *d_fill = nullptr;
+    double *d_lvl = nullptr;
+    int *d_lvli = nullptr;
     double *d_ws = nullptr;
     int *d_wsi = nullptr;
     KArgs args{};
@@ -375,13 +543,23 @@ void book_free(bt_book *b)
     if (!b) return;
     for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
     b->events.clear();
-    if (b->d_models) (void)hipFree(b->d_models);
-    if (b->d_sched) (void)hipFree(b->d_sched);
-    if (b->d_queue) (void)hipFree(b->d_queue);
-    if (b->d_ws) (void)hipFree(b->d_ws);
-    if (b->d_wsi) (void)hipFree(b->d_wsi);
-    b->d_models = nullptr; b->d_sched = nullptr; b->d_queue = nullptr;
+    void *ptrs[] = {b->d_models, b->d_items, b->d_tasks, b->d_task_off, b->d_ints,
+                    b->d_fill, b->d_lvl, b->d_lvli, b->d_ws, b->d_wsi};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    b->d_models = nullptr; b->d_items = nullptr; b->d_tasks = nullptr; b->d_task_off = nullptr;
+    b->d_ints = nullptr; b->d_fill = nullptr; b->d_lvl = nullptr; b->d_lvli = nullptr;
     b->d_ws = nullptr; b->d_wsi = nullptr;
+}
+
+template <typename T>
+int dalloc(T **p, size_t count)
+{
+    if (hipMalloc((void **)p, sizeof(T) * std::max<size_t>(count, 1)) != hipSuccess) {
+        (void)hipGetLastError();
+        return BT_ENOMEM;
+    }
+    return BT_OK;
 }
 
 int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
@@ -395,60 +573,123 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
             nodes += (int64_t)(h[i].N + 1) * (h[i].N + 2) / 2;
         }
     }
-    // options with valid parameters, longest tree first (one queue per kind)
-    std::vector<int> sched;
-    sched.reserve(n);
+    const int lf = (tune && tune->level_factor > 0) ? tune->level_factor : 32;
+    const int wpc = (tune && tune->wgs_per_cu > 0) ? tune->wgs_per_cu : 2;
+    const int64_t pool = (tune && tune->pool_points > 0) ? (int64_t)tune->pool_points * 3 : (int64_t)1 << 20;
+
+    // tree sides (buyer first: the longer recursion), longest tree first
+    std::vector<int> order;
     for (int i = 0; i < n; i++)
-        if (models[i].valid) sched.push_back(i);
-    std::stable_sort(sched.begin(), sched.end(), [&](int x, int y) { return models[x].N > models[y].N; });
+        if (models[i].valid) order.push_back(i);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return models[x].N > models[y].N; });
+    std::vector<Item> items;
+    int64_t lbuf = 0, ibuf = 0, ctr = 0;
+    int nbands_max = 0;
+    for (int side = 1; side >= 0; side--) {
+        for (int i : order) {
+            Item it;
+            it.opt = i; it.side = side; it.N = models[i].N;
+            it.nbands = (it.N + 1 + BAND - 1) / BAND;
+            it.lcap = round_up((int64_t)lf * (it.N + 2) * 3 + (it.N + 2), 32);
+            it.lbuf = lbuf; lbuf += 2 * it.lcap;
+            it.ibuf = ibuf; ibuf += round_up(4 * (int64_t)(it.N + 2), 32);
+            it.ctr = ctr; ctr += it.nbands + 1;
+            nbands_max = std::max(nbands_max, it.nbands);
+            items.push_back(it);
+        }
+    }
+    // band tasks, grouped by (band, side)
+    std::vector<Task> tasks;
+    std::vector<int> task_off(2 * (size_t)nbands_max + 1, 0);
+    std::vector<int> ntasks(2 * (size_t)nbands_max, 0);
+    for (int r = 0; r < nbands_max; r++) {
+        for (int side = 0; side < 2; side++) {
+            task_off[2 * r + side] = (int)tasks.size();
+            for (int q = 0; q < (int)items.size(); q++) {
+                const Item &it = items[q];
+                if (it.side != side || r >= it.nbands) continue;
+                const int t_top = it.N - r * BAND;
+                const int t_bot = std::max(t_top - BAND + 1, 0);
+                const int nb = (t_bot + 1 + BLOCK_COLS - 1) / BLOCK_COLS;
+                for (int bk = 0; bk < nb; bk++) tasks.push_back(Task{q, bk});
+            }
+            ntasks[2 * r + side] = (int)tasks.size() - task_off[2 * r + side];
+        }
+    }
+    task_off[2 * (size_t)nbands_max] = (int)tasks.size();
+    std::vector<int> p0(order);
 
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     hipDeviceProp_t prop;
     HIPCHK(hipGetDeviceProperties(&prop, dev));
-    int wpc = (tune && tune->wgs_per_cu > 0) ? tune->wgs_per_cu : 2;
-    int lf = (tune && tune->level_factor > 0) ? tune->level_factor : 8;
-    int64_t pool = (tune && tune->pool_points > 0) ? (int64_t)tune->pool_points * 3 : (int64_t)1 << 20;
-    int grid = std::max(1, std::min<int>((int)sched.size(), prop.multiProcessorCount * wpc));
+    int max_tasks = 1;
+    for (int v : ntasks) max_tasks = std::max(max_tasks, v);
+    const int resident = prop.multiProcessorCount * wpc;
+    const int grid = std::max(1, std::min(max_tasks, resident));
+    const int grid_p0 = std::max(1, std::min((int)p0.size(), resident));
+    const int ws_wgs = std::max(grid, grid_p0);
 
-    const int64_t nodes_cap = n_max + 2;
-    const int64_t lcapd = (int64_t)lf * nodes_cap * 3 + nodes_cap;
-    const Caps sc = small_caps();
     KArgs a{};
+    const int64_t pcap = round_up((int64_t)lf * (WG + 1) * 3 + (WG + 1), 32);
+    const Caps sc = small_caps();
     a.oStab = 0;
-    a.oL0 = ((2 * (int64_t)n_max + 3 + 31) / 32) * 32;
-    a.oL1 = a.oL0 + ((lcapd + 31) / 32) * 32;
-    a.oSmall = a.oL1 + ((lcapd + 31) / 32) * 32;
-    a.oPool = a.oSmall + ((sc.total * WG + 31) / 32) * 32;
-    a.ws_doubles = a.oPool + ((pool + 31) / 32) * 32;
-    a.wsi_ints = ((4 * nodes_cap + 63) / 64) * 64;
-    a.lcapd = lcapd;
+    const int64_t stab_n = std::max<int64_t>(2 * (int64_t)WG + BAND + 8, 2 * (int64_t)n_max + 3);
+    a.oP0 = round_up(stab_n, 32);
+    a.oP1 = a.oP0 + pcap;
+    a.oSmall = a.oP1 + pcap;
+    a.oPool = a.oSmall + round_up(sc.total * WG, 32);
+    a.ws_doubles = a.oPool + round_up(std::max<int64_t>(pool, 2 * (int64_t)n_max + 4), 32);
+    a.wsi_ints = round_up(4 * (int64_t)(WG + 1), 64);
+    a.pcap = pcap;
     a.pool = pool;
-    a.n_max = n_max;
-    a.n_items = (int)sched.size();
+    a.n_opts = n;
+    a.n_items = (int)items.size();
+    a.nbands_max = nbands_max;
+    a.n_p0 = (int)p0.size();
 
     b->timing = tune && (tune->flags & BT_TUNE_TIMING);
     b->params.assign(h, h + n);
     if (tune) b->tune = *tune;
     b->device = dev;
-    b->n = n; b->n_max = n_max; b->nodes = nodes; b->n_items = (int)sched.size();
-    b->grid = grid; b->level_factor = lf; b->pool_doubles = pool;
-    if (hipMalloc(&b->d_models, sizeof(Model) * n) != hipSuccess ||
-        hipMalloc(&b->d_sched, sizeof(int) * std::max<size_t>(1, sched.size())) != hipSuccess ||
-        hipMalloc(&b->d_queue, sizeof(int) * 64) != hipSuccess ||
-        hipMalloc(&b->d_ws, sizeof(double) * a.ws_doubles * grid) != hipSuccess ||
-        hipMalloc(&b->d_wsi, sizeof(int) * a.wsi_ints * grid) != hipSuccess) {
-        (void)hipGetLastError();
+    b->n = n; b->n_max = n_max; b->nodes = nodes; b->n_items = (int)items.size();
+    b->nbands_max = nbands_max;
+    b->n_fill = ctr;
+    b->grid = grid; b->grid_p0 = grid_p0;
+    b->ntasks = ntasks;
+
+    const int64_t nints = 2 * (int64_t)nbands_max + (int64_t)items.size() + 64 + (int64_t)p0.size();
+    int rc = BT_OK;
+    if ((rc = dalloc(&b->d_models, n)) || (rc = dalloc(&b->d_items, items.size())) ||
+        (rc = dalloc(&b->d_tasks, tasks.size())) || (rc = dalloc(&b->d_task_off, task_off.size())) ||
+        (rc = dalloc(&b->d_ints, nints)) || (rc = dalloc(&b->d_fill, ctr)) ||
+        (rc = dalloc(&b->d_lvl, lbuf)) || (rc = dalloc(&b->d_lvli, ibuf)) ||
+        (rc = dalloc(&b->d_ws, a.ws_doubles * ws_wgs)) || (rc = dalloc(&b->d_wsi, a.wsi_ints * ws_wgs))) {
         book_free(b);
-        return BT_ENOMEM;
+        return rc;
     }
     HIPCHK(hipMemcpy(b->d_models, models.data(), sizeof(Model) * n, hipMemcpyHostToDevice));
-    if (!sched.empty()) HIPCHK(hipMemcpy(b->d_sched, sched.data(), sizeof(int) * sched.size(), hipMemcpyHostToDevice));
+    if (!items.empty()) HIPCHK(hipMemcpy(b->d_items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice));
+    if (!tasks.empty()) HIPCHK(hipMemcpy(b->d_tasks, tasks.data(), sizeof(Task) * tasks.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b->d_task_off, task_off.data(), sizeof(int) * task_off.size(), hipMemcpyHostToDevice));
+    int *band_ctr = b->d_ints;
+    int *failed = band_ctr + 2 * (int64_t)nbands_max;
+    int *p0q = failed + items.size();
+    int *p0s = p0q + 64;
+    if (!p0.empty()) HIPCHK(hipMemcpy(p0s, p0.data(), sizeof(int) * p0.size(), hipMemcpyHostToDevice));
     a.models = b->d_models;
-    a.sched = b->d_sched;
-    a.queue = b->d_queue;
+    a.items = b->d_items;
+    a.tasks = b->d_tasks;
+    a.task_off = b->d_task_off;
+    a.band_ctr = band_ctr;
+    a.fill = b->d_fill;
+    a.failed = failed;
+    a.lvl = b->d_lvl;
+    a.lvli = b->d_lvli;
     a.ws = b->d_ws;
     a.wsi = b->d_wsi;
+    a.p0_queue = p0q;
+    a.p0_sched = p0s;
     b->args = a;
     return BT_OK;
 }
@@ -489,28 +730,36 @@ int bt_book_price(bt_book *book, bt_result *d_out, void *stream)
     hipStream_t s = (hipStream_t)stream;
     KArgs a = book->args;
     a.out = d_out;
-    const int nb = (book->n + 255) / 256;
     hipEvent_t ev[BT_NUM_KERNELS + 1];
     if (book->timing) {
         for (int i = 0; i <= BT_NUM_KERNELS; i++) HIPCHK(hipEventCreate(&ev[i]));
         for (int i = 0; i <= BT_NUM_KERNELS; i++) book->events.push_back(ev[i]);
         HIPCHK(hipEventRecord(ev[0], s));
     }
-    hipLaunchKernelGGL(bt_reset_kernel, dim3(nb), dim3(256), 0, s, book->d_models, book->n, d_out, book->d_queue);
+    const int64_t nr = std::max<int64_t>({(int64_t)book->n, 2 * (int64_t)book->nbands_max, book->n_fill,
+                                          (int64_t)book->n_items, 1});
+    const int rb = (int)std::min<int64_t>((nr + 255) / 256, 1024);
+    hipLaunchKernelGGL(bt_reset_kernel, dim3(rb), dim3(256), 0, s, a, book->n_fill);
     HIPCHK(hipGetLastError());
-    if (book->timing) HIPCHK(hipEventRecord(ev[1], s));
     if (book->n_items > 0) {
-        hipLaunchKernelGGL(bt_item_kernel<KIND_BID>, dim3(book->grid), dim3(WG), 0, s, a);
+        hipLaunchKernelGGL(bt_init_kernel, dim3((book->n_max + 2 + 255) / 256, book->n_items), dim3(256), 0, s, a);
+        HIPCHK(hipGetLastError());
+    }
+    if (book->timing) HIPCHK(hipEventRecord(ev[1], s));
+    for (int r = 0; r < book->nbands_max; r++) {
+        if (book->ntasks[2 * r + 1] == 0) continue;
+        hipLaunchKernelGGL(bt_band_kernel<1>, dim3(std::min(book->grid, book->ntasks[2 * r + 1])), dim3(WG), 0, s, a, r);
         HIPCHK(hipGetLastError());
     }
     if (book->timing) HIPCHK(hipEventRecord(ev[2], s));
-    if (book->n_items > 0) {
-        hipLaunchKernelGGL(bt_item_kernel<KIND_ASK>, dim3(book->grid), dim3(WG), 0, s, a);
+    for (int r = 0; r < book->nbands_max; r++) {
+        if (book->ntasks[2 * r] == 0) continue;
+        hipLaunchKernelGGL(bt_band_kernel<0>, dim3(std::min(book->grid, book->ntasks[2 * r])), dim3(WG), 0, s, a, r);
         HIPCHK(hipGetLastError());
     }
     if (book->timing) HIPCHK(hipEventRecord(ev[3], s));
-    if (book->n_items > 0) {
-        hipLaunchKernelGGL(bt_item_kernel<KIND_PRICE0>, dim3(book->grid), dim3(WG), 0, s, a);
+    if (book->args.n_p0 > 0) {
+        hipLaunchKernelGGL(bt_price0_kernel, dim3(book->grid_p0), dim3(WG), 0, s, a);
         HIPCHK(hipGetLastError());
     }
     if (book->timing) HIPCHK(hipEventRecord(ev[4], s));
@@ -533,8 +782,8 @@ int bt_book_resolve_overflow(bt_book *book, bt_result *d_out, void *stream, int3
     std::vector<int> idx;
     for (int i = 0; i < book->n; i++)
         if (res[i].status == BT_EOVERFLOW) idx.push_back(i);
-    int base_lf = book->tune.level_factor > 0 ? book->tune.level_factor : 8;
-    int base_pool = book->tune.pool_points > 0 ? book->tune.pool_points : (1 << 20) / 3;
+    const int base_lf = book->tune.level_factor > 0 ? book->tune.level_factor : 32;
+    const int base_pool = book->tune.pool_points > 0 ? book->tune.pool_points : (1 << 20) / 3;
     for (int mult = 4; !idx.empty() && mult <= 1024; mult *= 4) {
         std::vector<bt_params> sub;
         for (int i : idx) sub.push_back(book->params[i]);
@@ -609,23 +858,26 @@ void bt_book_destroy(bt_book *book)
 int bt_price(const bt_params *p, bt_result *out)
 {
     if (!p || !out) return BT_EINVAL;
-    thread_local bt_book *cache = nullptr;
-    thread_local int cache_nmax = 0;
+    // one cached book per thread, rebuilt when N changes (the band tasks
+    // depend on N only); otherwise only the option's constants are replaced
     thread_local bt_result *d_res = nullptr;
+    thread_local bt_book *cache = nullptr;
+    thread_local int cache_N = -1;
+    if (!d_res) HIPCHK(hipMalloc(&d_res, sizeof(bt_result)));
     Model m;
-    bool ok = derive(*p, m);
-    int N = ok ? p->N : 1;
-    if (!cache || N > cache_nmax || !ok) {
-        if (cache) { bt_book_destroy(cache); cache = nullptr; }
-        int rc = bt_book_create(p, 1, nullptr, &cache);
-        if (rc != BT_OK) return rc;
-        cache_nmax = cache->n_max;
-        if (!d_res) HIPCHK(hipMalloc(&d_res, sizeof(bt_result)));
-    } else {
-        // reuse the cached buffers: new constants, same schedule shape
+    const bool ok = derive(*p, m);
+    int rc = BT_OK;
+    if (cache && ok && cache_N == p->N && cache->n_items > 0) {
         HIPCHK(hipMemcpy(cache->d_models, &m, sizeof(Model), hipMemcpyHostToDevice));
+        cache->params[0] = *p;
+    } else {
+        if (cache) { bt_book_destroy(cache); cache = nullptr; cache_N = -1; }
+        rc = bt_book_create(p, 1, nullptr, &cache);
+        if (rc != BT_OK) return rc;
+        cache_N = ok ? p->N : -1;
     }
-    int rc = bt_book_price(cache, d_res, nullptr);
+    rc = bt_book_price(cache, d_res, nullptr);
+    if (rc == BT_OK) rc = bt_book_resolve_overflow(cache, d_res, nullptr, nullptr);
     if (rc != BT_OK) return rc;
     HIPCHK(hipMemcpy(out, d_res, sizeof(bt_result), hipMemcpyDeviceToHost));
     return BT_OK;

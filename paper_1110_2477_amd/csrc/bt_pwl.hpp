@@ -124,11 +124,10 @@ BTD int canon(const Arr &f, int m)
     double s0 = f.S(0);
     int k = 0;
     for (int j = 0; j < m; j++) {
+        // Writes go to indices k <= j (slopes k + 1 <= j + 1, equal only
+        // when nothing was dropped, rewriting the same value), so s[j] and
+        // s[j+1] still hold the input here.
         double sl = f.S(j), sr = f.S(j + 1);
-        // f.S(j) may already hold a kept slope written at index k + 1 <= j;
-        // the slope arriving at point j from its left is the last kept
-        // right slope, which equals the original s[j] whenever points were
-        // dropped (a drop needs equal slopes).
         if (sl != sr) {
             double xj = f.X(j), vj = f.V(j);
             f.X(k) = xj; f.V(k) = vj; f.S(k + 1) = sr;
@@ -155,16 +154,126 @@ BTD int canon(const Arr &f, int m)
 //    differs, the crossing y* = P_ref + d_ref / (sG - sF) is added if it lies
 //    strictly outside the end point.
 //  - Values are op(EVAL(F, y), EVAL(G, y)); slopes are the winner's.
+// What MERGE emits for one union point P_k: the slope leaving P_k to the
+// right (rs) and, when the interval after P_k holds a crossing, that point
+// (cy, cv) and the slope leaving it (crs).
+struct Slot {
+    double rs;
+    bool hc;
+    double cy, cv, crs;
+};
+
+// Interval (P, P1) with F, G values fF, fG at P (d = fF - fG) and d1 at P1;
+// iF, iG = #{points <= P} in F and G.
+template <int OP>
+BTD Slot slot_interval(const View &F, const View &G, double P, int iF, int iG, double fF, double fG,
+                       double d, double P1, double d1)
+{
+    Slot o;
+    o.hc = false; o.cy = 0.0; o.cv = 0.0; o.crs = 0.0;
+    const double sF = F.S(iF), sG = G.S(iG);
+    const int b0 = better<OP>(d), b1 = better<OP>(d1);
+    if (sF != sG && b0 != PNONE && b1 != PNONE && b0 != b1) {
+        const double y = P + (fF - fG) / (sG - sF);
+        if (y <= P) {
+            o.rs = b1 == PF ? sF : sG;
+        } else if (y >= P1) {
+            o.rs = b0 == PF ? sF : sG;
+        } else {
+            o.rs = b0 == PF ? sF : sG;
+            o.hc = true;
+            o.cy = y;
+            o.cv = pick<OP>(eval_at(F, iF, y), eval_at(G, iG, y));
+            o.crs = b1 == PF ? sF : sG;
+        }
+    } else {
+        int act = b0 != PNONE ? b0 : b1;
+        if (act == PNONE) {
+            if (OP == OPMAX) act = (sG > sF) ? PG : PF;
+            else act = (sG < sF) ? PG : PF;
+        }
+        o.rs = act == PF ? sF : sG;
+    }
+    return o;
+}
+
+// Right tail after the last union point P.
+template <int OP>
+BTD Slot slot_right(const View &F, const View &G, double P, double fF, double fG, double d)
+{
+    Slot o;
+    o.hc = false; o.cy = 0.0; o.cv = 0.0; o.crs = 0.0;
+    const double sF = F.S(F.m), sG = G.S(G.m);
+    const int bl = better<OP>(d);
+    int far;
+    if (sF != sG) far = (OP == OPMAX) ? (sF > sG ? PF : PG) : (sF < sG ? PF : PG);
+    else far = (bl != PNONE) ? bl : PF;
+    if (sF != sG && bl != PNONE && bl != far) {
+        const double y = P + (fF - fG) / (sG - sF);
+        if (y > P) {
+            o.rs = bl == PF ? sF : sG;
+            o.hc = true;
+            o.cy = y;
+            o.cv = pick<OP>(eval_at(F, F.m, y), eval_at(G, G.m, y));
+            o.crs = far == PF ? sF : sG;
+        } else {
+            o.rs = far == PF ? sF : sG;
+        }
+    } else {
+        o.rs = far == PF ? sF : sG;
+    }
+    return o;
+}
+
+// Left tail before the first union point P0: the far-left slope s0 and an
+// optional crossing (cy, cv) leaving with slope crs.
+template <int OP>
+BTD Slot slot_left(const View &F, const View &G, double P0, double fF, double fG, double d)
+{
+    Slot o;
+    o.hc = false; o.cy = 0.0; o.cv = 0.0; o.crs = 0.0;
+    const double sF = F.S(0), sG = G.S(0);
+    const int b0 = better<OP>(d);
+    int far;
+    if (sF != sG) far = (OP == OPMAX) ? (sF < sG ? PF : PG) : (sF > sG ? PF : PG);
+    else far = (b0 != PNONE) ? b0 : PF;
+    o.rs = far == PF ? sF : sG;
+    if (sF != sG && b0 != PNONE && b0 != far) {
+        const double y = P0 + (fF - fG) / (sG - sF);
+        if (y < P0) {
+            o.hc = true;
+            o.cy = y;
+            o.cv = pick<OP>(eval_at(F, 0, y), eval_at(G, 0, y));
+            o.crs = b0 == PF ? sF : sG;
+        }
+    }
+    return o;
+}
+
+// MERGE(F, G, op) into `out`; returns the point count or -1 on overflow.
+//  - P is the sorted union of both breakpoint lists (exact duplicates
+//    merged); at every P_k, d_k = EVAL(F, P_k) - EVAL(G, P_k).
+//  - Interval (P_k, P_k+1) with slopes sF != sG and d_k, d_k+1 of strictly
+//    opposite signs crosses at y* = P_k + d_k / (sG - sF); y* <= P_k or
+//    y* >= P_k+1 leaves the whole interval to the winner at the other end.
+//    Without a crossing the winner is the better function at P_k, else at
+//    P_k+1, else the one with the larger (MAX) / smaller (MIN) slope, F on a
+//    full tie.
+//  - Each tail's far winner follows from the slopes (MAX: smaller slope to
+//    the left, larger to the right; MIN reversed); equal slopes fall back to
+//    the sign of d at the end point, then F.  When the end point's winner
+//    differs, the crossing y* = P_ref + d_ref / (sG - sF) is added if it lies
+//    strictly outside the end point.
+//  - Values are op(EVAL(F, y), EVAL(G, y)); slopes are the winner's.
 template <int OP>
 BTD int merge(const View &F, const View &G, const Arr &out)
 {
     const double INF = __builtin_huge_val();
     int a = 0, b = 0;
-    // first union point
     double P, fF, fG, d;
     int iF, iG;
     {
-        double xa = F.X(0), xb = G.X(0);
+        const double xa = F.X(0), xb = G.X(0);
         if (xa < xb) { P = xa; a = 1; }
         else if (xb < xa) { P = xb; b = 1; }
         else { P = xa; a = 1; b = 1; }
@@ -174,69 +283,30 @@ BTD int merge(const View &F, const View &G, const Arr &out)
         d = fF - fG;
     }
     Emit e;
-    // left tail
     {
-        double sF = F.S(0), sG = G.S(0);
-        int b0 = better<OP>(d);
-        int far;
-        if (sF != sG) far = (OP == OPMAX) ? (sF < sG ? PF : PG) : (sF > sG ? PF : PG);
-        else far = (b0 != PNONE) ? b0 : PF;
-        e.start(out, far == PF ? sF : sG);
-        if (sF != sG && b0 != PNONE && b0 != far) {
-            double y = P + (fF - fG) / (sG - sF);
-            if (y < P) e.push(y, pick<OP>(eval_at(F, 0, y), eval_at(G, 0, y)), b0 == PF ? sF : sG);
-        }
+        const Slot L = slot_left<OP>(F, G, P, fF, fG, d);
+        e.start(out, L.rs);
+        if (L.hc) e.push(L.cy, L.cv, L.crs);
     }
     for (;;) {
-        double val = pick<OP>(fF, fG);
+        const double val = pick<OP>(fF, fG);
         if (a < F.m || b < G.m) {
-            double xa = a < F.m ? F.X(a) : INF, xb = b < G.m ? G.X(b) : INF;
+            const double xa = a < F.m ? F.X(a) : INF, xb = b < G.m ? G.X(b) : INF;
             double P1;
             if (xa < xb) { P1 = xa; a++; }
             else if (xb < xa) { P1 = xb; b++; }
             else { P1 = xa; a++; b++; }
-            int iF1 = a, iG1 = b;
-            double fF1 = eval_at(F, iF1, P1), fG1 = eval_at(G, iG1, P1);
-            double d1 = fF1 - fG1;
-            double sF = F.S(iF), sG = G.S(iG);
-            int b0 = better<OP>(d), b1 = better<OP>(d1);
-            if (sF != sG && b0 != PNONE && b1 != PNONE && b0 != b1) {
-                double y = P + (fF - fG) / (sG - sF);
-                if (y <= P) {
-                    e.push(P, val, b1 == PF ? sF : sG);
-                } else if (y >= P1) {
-                    e.push(P, val, b0 == PF ? sF : sG);
-                } else {
-                    e.push(P, val, b0 == PF ? sF : sG);
-                    e.push(y, pick<OP>(eval_at(F, iF, y), eval_at(G, iG, y)), b1 == PF ? sF : sG);
-                }
-            } else {
-                int act = b0 != PNONE ? b0 : b1;
-                if (act == PNONE) {
-                    if (OP == OPMAX) act = (sG > sF) ? PG : PF;
-                    else act = (sG < sF) ? PG : PF;
-                }
-                e.push(P, val, act == PF ? sF : sG);
-            }
+            const int iF1 = a, iG1 = b;
+            const double fF1 = eval_at(F, iF1, P1), fG1 = eval_at(G, iG1, P1);
+            const double d1 = fF1 - fG1;
+            const Slot o = slot_interval<OP>(F, G, P, iF, iG, fF, fG, d, P1, d1);
+            e.push(P, val, o.rs);
+            if (o.hc) e.push(o.cy, o.cv, o.crs);
             P = P1; iF = iF1; iG = iG1; fF = fF1; fG = fG1; d = d1;
         } else {
-            // right tail
-            double sF = F.S(F.m), sG = G.S(G.m);
-            int bl = better<OP>(d);
-            int far;
-            if (sF != sG) far = (OP == OPMAX) ? (sF > sG ? PF : PG) : (sF < sG ? PF : PG);
-            else far = (bl != PNONE) ? bl : PF;
-            if (sF != sG && bl != PNONE && bl != far) {
-                double y = P + (fF - fG) / (sG - sF);
-                if (y > P) {
-                    e.push(P, val, bl == PF ? sF : sG);
-                    e.push(y, pick<OP>(eval_at(F, F.m, y), eval_at(G, G.m, y)), far == PF ? sF : sG);
-                } else {
-                    e.push(P, val, far == PF ? sF : sG);
-                }
-            } else {
-                e.push(P, val, far == PF ? sF : sG);
-            }
+            const Slot o = slot_right<OP>(F, G, P, fF, fG, d);
+            e.push(P, val, o.rs);
+            if (o.hc) e.push(o.cy, o.cv, o.crs);
             break;
         }
     }
