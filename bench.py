@@ -9,8 +9,9 @@ Inputs are resident on the GPU before timing starts.
 
 Printed: one JSON line with tree nodes/s (value), per-kernel HIP-event
 times, the roofline of the dominant kernel, batched options/s on a mixed
-4096-option book, plain single-option forward on the same GPU, and the CPU
-oracle timed on the host on a bounded sample.
+4096-option book, plain single-option forward on the same GPU, batched
+prices with Greeks on a 1024-option book, and the CPU oracle timed on the
+host on a bounded sample.
 """
 import argparse
 import json
@@ -42,31 +43,19 @@ def cpu_cores():
 
 
 def oracle_leg(sample, cores):
-    """Times the CPU oracle on a bounded sample: every option of the sample,
-    one option per task on `cores` threads.  Also returns the algorithmic
-    binary64 operation count per tree node of each side."""
+    """Times the CPU oracle on a bounded sample: every option of the sample
+    (ask, bid and price0), one option per task on `cores` threads."""
     from concurrent.futures import ThreadPoolExecutor
 
     import oracle
     from paper_1110_2477_amd import workloads as W
 
-    def one(p):
-        oracle.flops()
-        r_ask = oracle.price_params(p, sides=1)
-        f_ask = oracle.flops()
-        r_bid = oracle.price_params(p, sides=2)
-        f_bid = oracle.flops()
-        return f_ask, f_bid
-
     t0 = time.perf_counter()
     with ThreadPoolExecutor(max_workers=cores) as ex:
-        res = list(ex.map(one, sorted(sample, key=lambda p: -int(p["N"]))))
+        list(ex.map(oracle.price_params, sorted(sample, key=lambda p: -int(p["N"]))))
     dt = time.perf_counter() - t0
     nodes = W.nodes(sample)
-    f_ask = sum(r[0] for r in res)
-    f_bid = sum(r[1] for r in res)
-    return dict(seconds=dt, nodes=nodes, nodes_per_s=nodes / dt, options_per_s=len(sample) / dt,
-                flops_per_node_ask=f_ask / nodes, flops_per_node_bid=f_bid / nodes)
+    return dict(seconds=dt, nodes=nodes, nodes_per_s=nodes / dt, options_per_s=len(sample) / dt)
 
 
 def main():
@@ -94,23 +83,32 @@ def main():
     nodes = W.nodes(grid)
     book = bt.Book(grid, tune=dict(flags=bt.BT_TUNE_TIMING))
     log(f"workload: 48-tree grid, {nodes} nodes; warmup {args.warmup}")
-    for _ in range(args.warmup):
+    def step():
+        # one complete pricing of the book: the kernels, then the host check
+        # for options that outgrew the level buffers (re-priced with larger
+        # ones inside the step when there are any)
         book.price()
+        return book.resolve_overflow()
+
+    for _ in range(args.warmup):
+        step()
     torch.cuda.synchronize()
     book.timings()  # discard warm-up events
     log(f"timing {args.steps} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    remaining = 0
     for _ in range(args.steps):
-        book.price()
+        remaining += step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kms, calls = book.timings()
-    # options whose levels outgrow the buffers would need a second pass; the
-    # timed calls are only valid if there were none
-    assert book.resolve_overflow() == 0
     res = book.results()
-    assert np.all(res["status"] == 0), res["status"]
+    assert remaining == 0 and np.all(res["status"] == 0), res["status"]
+    # how many options needed the second pass (same every step)
+    book.price()
+    n_resolved = int(np.sum(book.results()["status"] == bt.BT_EOVERFLOW))
+    book.timings()
     book.close()
     ms_step = (t1 - t0) * 1e3 / args.steps
     value = nodes * args.steps / (t1 - t0)
@@ -136,6 +134,7 @@ def main():
                    "S0": 100, "R": 0.05, "sigma": 0.3, "T": 1, "outputs": ["ask", "bid", "price0"]},
         "options_per_s": len(grid) * args.steps / (t1 - t0),
         "kernel_ms": kernel_ms,
+        "options_repriced_with_larger_levels_per_step": n_resolved,
     }
 
     extra = {}
@@ -169,29 +168,60 @@ def main():
                                                     tree_nodes_per_s=W.nodes(sub) / dt,
                                                     sample="4 N=1500 trees of the grid, bt_price one at a time")
         log(f"plain: {extra['plain_single_option_forward']}")
+        # batched forward + Greeks (d ask, d bid / d S0, sigma, R, k) on the
+        # 1024-option book with N in [500, 1500]
+        gb = W.greeks_book(1024, seed=4)
+        gk = bt.Book(gb, greeks=True)
+        gk.price_grad()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gk.price_grad()
+        torch.cuda.synchronize()
+        dt_g = time.perf_counter() - t0
+        n_retry = int(np.sum(gk.results()["status"] == bt.BT_EOVERFLOW))
+        gk.resolve_overflow(grad=True)
+        ok = bool(np.all(gk.results()["status"] == 0))
+        t0 = time.perf_counter()
+        gk.price()
+        torch.cuda.synchronize()
+        dt_p = time.perf_counter() - t0
+        gk.close()
+        extra["batched_greeks_1024"] = dict(options_per_s=len(gb) / dt_g, ms=dt_g * 1e3,
+                                            price_only_ms=dt_p * 1e3, greeks_over_price=dt_g / dt_p,
+                                            ok=ok, options_needing_larger_levels=n_retry)
+        log(f"greeks book: {extra['batched_greeks_1024']}")
     out.update(extra)
 
     # roofline of the dominant kernel: binary64 operations of the canonical
-    # algorithm per node (counted by the oracle on the sample below) x nodes
-    # of one launch, over the kernel's HIP-event duration
+    # algorithm for every tree of the workload (counted by the oracle and
+    # stored by oracle/count_flops.py) over the kernel's HIP-event time; one
+    # launch is one band of one party, so flops / time over all launches is
+    # the average flops per launch over the average launch duration
+    with open(os.path.join(ROOT, "oracle", "counts", "paper_grid_flops.json")) as f:
+        counts = json.load(f)
+    dom = max(("bid", "ask"), key=lambda k: kernel_ms[k])
+    flops = counts[dom + "_flops"]
+    achieved = flops / (kernel_ms[dom] * 1e-3) / 1e12
+    # one launch per band of the longest tree: bands of 32 levels over N+1 levels
+    n_launch = (int(grid["N"].max()) + 1 + 31) // 32
+    out["roofline"] = {"bound": "alu", "kernel": f"bt_band_kernel<{1 if dom == 'bid' else 0}, double>",
+                       "achieved": achieved, "peak": PEAK_FP64_NONFMA_TFLOPS, "unit": "TFLOP/s",
+                       "frac": achieved / PEAK_FP64_NONFMA_TFLOPS, "traffic": None,
+                       "flops_per_step": flops, "launches_per_step": n_launch,
+                       "flops_per_launch": flops / n_launch,
+                       "ms_per_launch": kernel_ms[dom] / n_launch}
+
     cores = cpu_cores()
     if not args.no_cpu:
-        sample = W.paper_grid(1500)
-        log(f"cpu oracle leg: 24 N=1500 trees on {cores} threads")
+        g50 = W.paper_grid(5000)
+        sample = np.concatenate([W.paper_grid(1500), g50[g50["k"] <= 0.0025]])
+        log(f"cpu oracle leg: {len(sample)} trees on {cores} threads")
         leg = oracle_leg(sample, cores)
         out["cpu_baseline"] = {"value": leg["nodes_per_s"], "unit": "tree nodes/s", "cores": cores,
                                "kind": "oracle",
-                               "sample": "the 24 N=1500 trees of the grid (ask, bid, price0), one option "
-                                         "per thread; N=5000 half not run",
+                               "sample": "the 24 N=1500 trees of the grid and its 12 N=5000 trees with "
+                                         "k in {0, 0.25%} (ask, bid, price0), one option per thread",
                                "options_per_s": leg["options_per_s"], "seconds": leg["seconds"]}
-        dom = max(("bid", "ask"), key=lambda k: kernel_ms[k])
-        fpn = leg["flops_per_node_" + dom]
-        flops = fpn * nodes
-        achieved = flops / (kernel_ms[dom] * 1e-3) / 1e12
-        out["roofline"] = {"bound": "alu", "kernel": f"bt_item_kernel<{dom}>",
-                           "achieved": achieved, "peak": PEAK_FP64_NONFMA_TFLOPS, "unit": "TFLOP/s",
-                           "frac": achieved / PEAK_FP64_NONFMA_TFLOPS, "traffic": None,
-                           "flops_per_node": fpn, "flops_per_launch": flops}
     print(json.dumps(out), flush=True)
 
 

@@ -95,17 +95,25 @@ typedef struct {
 
 /* Launch tuning; pass NULL for the library's choice.  Zero fields also mean
  * "library's choice".
- *   wgs_per_cu   persistent workgroups per compute unit
- *   level_factor capacity of one tree level, in points per node
- *   pool_points  per-workgroup pool for nodes with many breakpoints
+ *   wgs_per_cu   persistent workgroups per compute unit (default 2)
+ *   level_factor capacity of one tree level, in points per node (default
+ *                32; a workgroup's private level holds at least 65536)
+ *   pool_points  per-workgroup temporaries of the nodes with many
+ *                breakpoints, in points (default 262144; 65536 for a
+ *                BT_TUNE_GREEKS book); a node too big for its wave's share
+ *                takes its temporaries from a book-wide arena of at least
+ *                2^28 doubles (5x that for Greeks) instead
  *   flags        BT_TUNE_TIMING: record HIP events around every kernel of
  *                every pricing call (read with bt_book_timings; not for use
- *                under graph capture)                                       */
+ *                under graph capture);
+ *                BT_TUNE_GREEKS: size the book's buffers for
+ *                bt_book_price_grad (values with four tangents, 5x the
+ *                memory of a price-only book)                              */
 typedef struct {
     int32_t wgs_per_cu, level_factor, pool_points, flags;
 } bt_tune;
 
-enum { BT_TUNE_TIMING = 1 };
+enum { BT_TUNE_TIMING = 1, BT_TUNE_GREEKS = 2 };
 
 /* Number of kernels one pricing call launches, in launch order:
  * 0 = result/queue reset, 1 = buyer (bid), 2 = seller (ask), 3 = zero-cost. */
@@ -136,17 +144,25 @@ int bt_book_info(const bt_book *book, int32_t *n, int32_t *n_max, int64_t *nodes
 int bt_book_price(bt_book *book, bt_result *d_out, void *stream);
 
 /* As bt_book_price, and also the Greeks of ask and bid: d_grad is a device
- * pointer to n bt_grad. */
+ * pointer to n bt_grad (NaN for invalid options).  The derivatives are
+ * carried forward through the same recursion as the prices (every number of
+ * every expense function holds its value and its derivatives with respect
+ * to S0, sigma, R and k), so they are exact for the active branch of the
+ * piecewise-smooth price.  The book must have been created with
+ * BT_TUNE_GREEKS (else BT_ENOSUPP). */
 int bt_book_price_grad(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream);
 
 /* Completes a pricing call whose options overflowed the book's level
  * buffers (status BT_EOVERFLOW; a tree whose levels hold more breakpoints
  * than level_factor per node): waits for `stream`, then re-prices those
  * options on `stream` with buffers 4x larger each attempt (up to 1024x),
- * writing their results into d_out.  *remaining (may be NULL) receives the
- * number of options still overflowing.  Synchronous; allocates temporary
- * device memory only when some option overflowed. */
-int bt_book_resolve_overflow(bt_book *book, bt_result *d_out, void *stream, int32_t *remaining);
+ * writing their results into d_out.  d_grad is NULL after bt_book_price;
+ * after bt_book_price_grad it is that call's Greeks buffer, and the
+ * re-pricing then also writes the Greeks of those options.  *remaining (may
+ * be NULL) receives the number of options still overflowing.  Synchronous;
+ * allocates temporary device memory only when some option overflowed. */
+int bt_book_resolve_overflow(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream,
+                             int32_t *remaining);
 
 /* For a book created with BT_TUNE_TIMING: waits for every pricing call
  * made since the previous bt_book_timings call, writes into ms[0..3] the

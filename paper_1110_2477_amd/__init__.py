@@ -34,7 +34,8 @@ class BtError(RuntimeError):
 
 
 BT_TUNE_TIMING = 1
-KERNEL_NAMES = ("reset", "bid", "ask", "price0")
+BT_TUNE_GREEKS = 2
+KERNEL_NAMES = ("setup", "bid", "ask", "price0")
 
 
 class _Tune(ctypes.Structure):
@@ -61,7 +62,7 @@ def lib():
     L.bt_book_price.argtypes = [vp, vp, vp]
     L.bt_book_price_grad.argtypes = [vp, vp, vp, vp]
     L.bt_book_timings.argtypes = [vp, dp, ctypes.POINTER(i32)]
-    L.bt_book_resolve_overflow.argtypes = [vp, vp, vp, ctypes.POINTER(i32)]
+    L.bt_book_resolve_overflow.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i32)]
     L.bt_book_destroy.argtypes = [vp]
     L.bt_book_destroy.restype = None
     L.bt_price.argtypes = [vp, vp]
@@ -138,11 +139,12 @@ def bt_book_price_grad(book, d_out_ptr, d_grad_ptr, stream=None):
                                     ctypes.c_void_p(_stream_ptr(stream))), "bt_book_price_grad")
 
 
-def bt_book_resolve_overflow(book, d_out_ptr, stream=None):
+def bt_book_resolve_overflow(book, d_out_ptr, d_grad_ptr=0, stream=None):
     """Re-prices the options of a finished call that overflowed the book's
-    level buffers; returns how many still overflow."""
+    level buffers (with their Greeks when d_grad_ptr is the Greeks buffer of
+    a bt_book_price_grad call); returns how many still overflow."""
     rem = ctypes.c_int32()
-    _check(lib().bt_book_resolve_overflow(book, ctypes.c_void_p(d_out_ptr),
+    _check(lib().bt_book_resolve_overflow(book, ctypes.c_void_p(d_out_ptr), ctypes.c_void_p(d_grad_ptr or None),
                                           ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(rem)),
            "bt_book_resolve_overflow")
     return rem.value
@@ -183,13 +185,18 @@ class Book:
     """A priced-repeatedly batch of options on the current GPU.
 
     ``price()`` returns a uint8 CUDA tensor holding n bt_result records;
-    ``results()`` copies it to a RESULT_DTYPE numpy array."""
+    ``results()`` copies it to a RESULT_DTYPE numpy array.  With
+    ``greeks=True`` the book can also run ``price_grad()`` (ask/bid Greeks
+    into a GRAD_DTYPE buffer)."""
 
-    def __init__(self, params, tune=None):
+    def __init__(self, params, tune=None, greeks=False):
         import torch
         self.params = _params(params)
         self.n = len(self.params)
-        self.handle = bt_book_create(self.params, tune)
+        tune = dict(tune or {})
+        if greeks:
+            tune["flags"] = int(tune.get("flags", 0)) | BT_TUNE_GREEKS
+        self.handle = bt_book_create(self.params, tune if tune else None)
         self.out = torch.empty(self.n * RESULT_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
         self.grad = None
 
@@ -210,8 +217,11 @@ class Book:
     def timings(self):
         return bt_book_timings(self.handle)
 
-    def resolve_overflow(self, stream=None):
-        return bt_book_resolve_overflow(self.handle, self.out.data_ptr(), stream)
+    def resolve_overflow(self, stream=None, grad=False):
+        """Re-prices overflowed options of the last call; grad=True after
+        price_grad() (Greeks re-priced too)."""
+        g = self.grad.data_ptr() if grad else 0
+        return bt_book_resolve_overflow(self.handle, self.out.data_ptr(), g, stream)
 
     def results(self):
         import torch
@@ -233,6 +243,17 @@ class Book:
             self.close()
         except Exception:
             pass
+
+
+def price_book_grad(params, tune=None):
+    """Prices a book with Greeks; returns (RESULT_DTYPE, GRAD_DTYPE) arrays."""
+    b = Book(params, tune, greeks=True)
+    try:
+        b.price_grad()
+        b.resolve_overflow(grad=True)
+        return b.results(), b.grads()
+    finally:
+        b.close()
 
 
 def price_book(params, tune=None, resolve=True):

@@ -1,6 +1,6 @@
 // bt_device.hpp -- shared definitions of the gfx950 kernels and their host
-// launcher: per-option tree constants, the workspace layout of one
-// persistent workgroup, and the per-node update of Section 3.
+// launcher: per-option tree constants, the per-lane temporary layout, and
+// the per-node update of Section 3.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -16,7 +16,6 @@ constexpr int WG = 256;          // lanes per workgroup (4 waves of 64)
 constexpr int NWAVE = WG / 64;
 constexpr int SMALL_CAP = 12;    // points per stage on the interleaved fast path
 
-enum { KIND_ASK = 0, KIND_BID = 1, KIND_PRICE0 = 2 };
 enum { PAY_PUT = 0, PAY_CALL = 1, PAY_BULL = 2 };
 enum { F_EUROPEAN = 1u, F_COST_AT_T0 = 2u };
 
@@ -30,8 +29,36 @@ struct Model {
     int32_t valid;
 };
 
+// The model's inputs as numbers of type T: plain values, or for D4 the
+// values with their tangents seeded for (S0, sigma, R, k):
+// dS0/dS0 = 1, du/dsigma = u sqrt(T/N), dr/dR = r T/N, dk/dk = 1, and
+// d = 1/u, rho = 1/r carried through the division.
+template <typename T>
+struct Inputs {
+    T S0, u, d, rho, k, K, K2;
+};
+
+BTD Inputs<double> inputs_of(const Model &md, double)
+{
+    return Inputs<double>{md.S0, md.u, md.d, md.rho, md.k, md.K, md.K2};
+}
+
+BTD Inputs<D4> inputs_of(const Model &md, D4)
+{
+    Inputs<D4> in;
+    in.S0 = mk<D4>(md.S0); in.S0.d[0] = 1.0;
+    in.u = mk<D4>(md.u); in.u.d[1] = md.u * md.sq;
+    D4 r = mk<D4>(md.r); r.d[2] = md.r * md.dt;
+    in.d = mk<D4>(1.0) / in.u;
+    in.rho = mk<D4>(1.0) / r;
+    in.k = mk<D4>(md.k); in.k.d[3] = 1.0;
+    in.K = mk<D4>(md.K);
+    in.K2 = mk<D4>(md.K2);
+    return in;
+}
+
 // Stage capacities of one node update (points).  W = max of the children,
-// A and B the two sweeps of ENV, V the restricted function, Z the result.
+// A and B the two halves of ENV, V the restricted function, Z the result.
 struct Caps {
     int cW, cA, cB, cV, cZ;
     int64_t oU, oW, oA, oB, oV, oZ, total;  // offsets / size in stride units
@@ -54,9 +81,10 @@ BTHD Caps make_caps(int cW, int cA, int cB, int cV, int cZ)
 // Interleaved fast-path capacities (every stage SMALL_CAP points).
 BTHD Caps small_caps() { return make_caps(SMALL_CAP, SMALL_CAP, SMALL_CAP, SMALL_CAP, SMALL_CAP); }
 
-BTD Arr stage(double *base, int st, int64_t off, int cap)
+template <typename T>
+BTD Arr<T> stage(T *base, int st, int64_t off, int cap)
 {
-    Arr a;
+    Arr<T> a;
     a.x = base + off * st;
     a.v = base + (off + cap) * st;
     a.s = base + (off + 2 * (int64_t)cap) * st;
@@ -67,22 +95,24 @@ BTD Arr stage(double *base, int st, int64_t off, int cap)
 
 // Exercise payoff (xi, zeta) at stock price S (Section 3 and Section 5):
 // put (K, -1), call (-K, 1), bull spread ((S-K)^+ - (S-K2)^+, 0) in cash.
-BTD void payoff(const Model &md, double S, double &xi, double &zeta)
+template <typename T>
+BTD void payoff(const Model &md, const Inputs<T> &in, const T &S, T &xi, T &zeta)
 {
-    if (md.payoff == PAY_PUT) { xi = md.K; zeta = -1.0; }
-    else if (md.payoff == PAY_CALL) { xi = -md.K; zeta = 1.0; }
+    if (md.payoff == PAY_PUT) { xi = in.K; zeta = mk<T>(-1.0); }
+    else if (md.payoff == PAY_CALL) { xi = -in.K; zeta = mk<T>(1.0); }
     else {
-        double e1 = S - md.K, e2 = S - md.K2;
-        xi = (e1 > 0.0 ? e1 : 0.0) - (e2 > 0.0 ? e2 : 0.0);
-        zeta = 0.0;
+        const T e1 = S - in.K, e2 = S - in.K2;
+        xi = (val(e1) > 0.0 ? e1 : mk<T>(0.0)) - (val(e2) > 0.0 ? e2 : mk<T>(0.0));
+        zeta = mk<T>(0.0);
     }
 }
 
 // base^n by binary powering, multiplying in base^(2^i) for each set bit i
 // in increasing i (the stock lattice S0 u^j of Section 4.1).
-BTD double upow(double base, int n)
+template <typename T>
+BTD T upow(const T &base, int n)
 {
-    double acc = 1.0, b = base;
+    T acc = mk<T>(1.0), b = base;
     bool first = true;
     while (n > 0) {
         if (n & 1) { acc = first ? b : acc * b; first = false; }
@@ -90,6 +120,13 @@ BTD double upow(double base, int n)
         if (n) b = b * b;
     }
     return acc;
+}
+
+// Stock price at lattice index j: S0 u^j (j >= 0) or S0 d^-j.
+template <typename T>
+BTD T stock_at(const Inputs<T> &in, int j)
+{
+    return in.S0 * (j >= 0 ? upow(in.u, j) : upow(in.d, -j));
 }
 
 // One node of the seller's (SIDE 0) or buyer's (SIDE 1) recursion,
@@ -101,56 +138,57 @@ BTD double upow(double base, int n)
 // t (European variant).  Temporaries live in `base` with element stride
 // `st` and the capacities of `cp`.  Returns the point count of Z (whose
 // storage is set in *zout) or -1 when a capacity was exceeded.
-template <int SIDE>
-BTD int node_update(const View &Zu, const View &Zd, double S, double kt, double rho,
-                    double xi, double zeta, bool exercise, double *base, int st,
-                    const Caps &cp, Arr *zout)
+template <int SIDE, typename T>
+BTD int node_update(const View<T> &Zu, const View<T> &Zd, const T &S, const T &kt, const T &rho,
+                    const T &xi, const T &zeta, bool exercise, T *base, int st,
+                    const Caps &cp, Arr<T> *zout)
 {
-    const double a = -((1.0 + kt) * S);
-    const double b = -((1.0 - kt) * S);
-    Arr W = stage(base, st, cp.oW, cp.cW);
-    int mw = merge<OPMAX>(Zu, Zd, W);
+    const T one = mk<T>(1.0);
+    const T a = -((one + kt) * S);
+    const T b = -((one - kt) * S);
+    Arr<T> W = stage(base, st, cp.oW, cp.cW);
+    int mw = merge<OPMAX, T>(Zu, Zd, W);
     if (mw < 0) return -1;
     mw = scale(W, mw, rho);
-    Arr V;
+    Arr<T> V;
     int mv;
     if (SIDE == 0) {
         mv = clip(W, mw, a, b);
         V = W;
     } else {
         V = stage(base, st, cp.oV, cp.cV);
-        const View Fv = W.view(mw);
-        if (a == b) {
+        const View<T> Fv = W.view(mw);
+        if (val(a) == val(b)) {
             int js = 0;
             double best = 0.0;
             for (int j = 0; j < mw; j++) {
-                double h = Fv.V(j) - a * Fv.X(j);
+                const double h = val(Fv.V(j) - a * Fv.X(j));
                 if (j == 0 || h < best) { best = h; js = j; }
             }
-            double xs = Fv.X(js), vs = Fv.V(js);
+            const T xs = Fv.X(js), vs = Fv.V(js);
             V.X(0) = xs; V.V(0) = vs; V.S(0) = a; V.S(1) = a;
             mv = 1;
         } else {
-            Arr A = stage(base, st, cp.oA, cp.cA);
-            Arr B = stage(base, st, cp.oB, cp.cB);
-            int ma = sweep_a<false>(Fv, a, A);
+            Arr<T> A = stage(base, st, cp.oA, cp.cA);
+            Arr<T> B = stage(base, st, cp.oB, cp.cB);
+            const int ma = sweep_a<false, T>(Fv, a, A);
             if (ma < 0) return -1;
-            int mb = sweep_a<true>(Fv, -b, B);
+            int mb = sweep_a<true, T>(Fv, -b, B);
             if (mb < 0) return -1;
             mirror_inplace(B, mb);
             mb = canon(B, mb);
-            mv = merge<OPMIN>(A.view(ma), B.view(mb), V);
+            mv = merge<OPMIN, T>(A.view(ma), B.view(mb), V);
             if (mv < 0) return -1;
         }
     }
     if (!exercise) { *zout = V; return mv; }
-    Arr U = stage(base, st, cp.oU, 1);
-    // U occupies 4 doubles: x, v, s0, s1 (cap 1 -> x, v, s[0..1]).
+    Arr<T> U = stage(base, st, cp.oU, 1);
+    // U occupies 4 numbers: x, v, s0, s1 (cap 1 -> x, v, s[0..1]).
     if (SIDE == 0) { U.X(0) = zeta; U.V(0) = xi; }
     else { U.X(0) = -zeta; U.V(0) = -xi; }
     U.S(0) = a; U.S(1) = b;
-    Arr Z = stage(base, st, cp.oZ, cp.cZ);
-    int mz = merge<SIDE == 0 ? OPMAX : OPMIN>(U.view(1), V.view(mv), Z);
+    Arr<T> Z = stage(base, st, cp.oZ, cp.cZ);
+    const int mz = merge<SIDE == 0 ? OPMAX : OPMIN, T>(U.view(1), V.view(mv), Z);
     *zout = Z;
     return mz;
 }

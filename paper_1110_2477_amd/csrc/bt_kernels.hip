@@ -40,6 +40,10 @@ namespace {
 
 constexpr int BAND = 32;                   // levels per band
 constexpr int BLOCK_COLS = WG - BAND;      // output columns per block (+ halo <= WG)
+constexpr int DEFAULT_LEVEL_FACTOR = 32;   // breakpoints per node the band buffers hold
+constexpr int64_t DEFAULT_POOL_POINTS = (int64_t)1 << 18;   // per-workgroup pool, in breakpoints
+constexpr int64_t MIN_PRIVATE_POINTS = (int64_t)1 << 16;    // floor of a private level, in breakpoints
+constexpr int64_t DEFAULT_ARENA_DOUBLES = (int64_t)1 << 28;  // shared by one launch's big nodes
 
 // One tree side: option `opt`, party `side` (0 seller, 1 buyer); offsets of
 // its two band-boundary level buffers (doubles) and index arrays (ints).
@@ -76,7 +80,30 @@ struct KArgs {
     int *p0_queue;
     const int *p0_sched;
     int n_p0;
+    bt_grad *grad;          // Greeks output (dual-number launches only)
+    double *arena;          // temporaries of big nodes that outgrow a wave's pool slice
+    int64_t arena_cap;      // doubles
+    unsigned long long *arena_ctr;  // bump counters, one per (band, party) launch
 };
+
+// Doubles of pool a wave needs for one cooperative node update whose
+// children hold M points in all (high-water mark measured on the host at
+// about 54 M for the buyer's update; the margin covers the rest).
+__device__ __forceinline__ int64_t big_need(int M, int nt)
+{
+    return (((int64_t)64 * M + 4096) * nt + 31) & ~(int64_t)31;
+}
+
+// Takes n doubles of the arena for one wave (all lanes call; uniform
+// result); nullptr when the arena is exhausted.
+__device__ __forceinline__ double *arena_take(const KArgs &A, int ctr, int64_t n)
+{
+    unsigned long long pos = 0;
+    if ((threadIdx.x & 63) == 0) pos = atomicAdd(A.arena_ctr + ctr, (unsigned long long)n);
+    pos = __shfl(pos, 0, 64);
+    if ((int64_t)pos + n > A.arena_cap) return nullptr;
+    return A.arena + pos;
+}
 
 // Exclusive prefix sum over the workgroup; *total gets the sum.
 __device__ __forceinline__ int64_t block_scan(int64_t v, int64_t *total, int64_t *sh)
@@ -102,12 +129,14 @@ __device__ __forceinline__ int64_t block_scan(int64_t v, int64_t *total, int64_t
     return base + x - v;
 }
 
-__device__ __forceinline__ View record_view(const double *L, int64_t off, int m)
+template <typename T>
+__device__ __forceinline__ View<T> record_view(const T *L, int64_t off, int m)
 {
-    return View{L + off + 1, L + off + 2, L + off, m, 3};
+    return View<T>{L + off + 1, L + off + 2, L + off, m, 3};
 }
 
-__device__ __forceinline__ void write_record(double *dst, const Arr &z, int m)
+template <typename T>
+__device__ __forceinline__ void write_record(T *dst, const Arr<T> &z, int m)
 {
     dst[0] = z.S(0);
     for (int j = 0; j < m; j++) {
@@ -128,44 +157,46 @@ __device__ void stock_table(const Model &md, double *Stab)
     }
 }
 
-// Stock price at lattice index j without a table (same binary powering).
-__device__ __forceinline__ double stock_at(const Model &md, int j)
-{
-    return md.S0 * (j >= 0 ? upow(md.u, j) : upow(md.d, -j));
-}
-
 // Level N+1 of every tree side: the liquidation value y^- S^a - y^+ S^b
 // (payoff (0, 0), Section 4.1), record [-(1+k) S, 0, 0, -(1-k) S], in band
 // buffer 0.
+template <typename T>
 __global__ void bt_init_kernel(KArgs A)
 {
     const int it = blockIdx.y;
     if (it >= A.n_items) return;
     const Item I = A.items[it];
     const Model md = A.models[I.opt];
+    const Inputs<T> in = inputs_of(md, T{});
     const int N = I.N;
-    double *L = A.lvl + I.lbuf;
+    T *L = (T *)(A.lvl + I.lbuf);
     int *off = A.lvli + I.ibuf, *cnt = off + 2 * (int64_t)(N + 2);
+    const T one = mk<T>(1.0);
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c <= N + 1; c += gridDim.x * blockDim.x) {
-        const double S = stock_at(md, 2 * c - (N + 1));
-        const double Sa = (1.0 + md.k) * S, Sb = (1.0 - md.k) * S;
-        double *r = L + 4 * (int64_t)c;
-        r[0] = -Sa; r[1] = 0.0; r[2] = 0.0; r[3] = -Sb;
+        const T S = stock_at(in, 2 * c - (N + 1));
+        const T Sa = (one + in.k) * S, Sb = (one - in.k) * S;
+        T *r = L + 4 * (int64_t)c;
+        r[0] = -Sa; r[1] = mk<T>(0.0); r[2] = mk<T>(0.0); r[3] = -Sb;
         off[c] = 4 * c;
         cnt[c] = 1;
     }
 }
 
 // One band task: block `blk` of band `r` of tree side `item`.
-template <int SIDE>
-__device__ void band_task(const KArgs &A, int r, int item, int blk, int64_t *sh, int *sflag)
+// s_chunk / s_chunk_cap: each wave's arena chunk (kept for the whole launch
+// and reused by the wave's later big nodes; grown when a node needs more).
+template <int SIDE, typename T>
+__device__ void band_task(const KArgs &A, int r, int item, int blk, int64_t *sh, int *sflag,
+                          double **s_chunk, int64_t *s_chunk_cap)
 {
+    constexpr int NT = sizeof(T) / sizeof(double);
     __shared__ int sbig[WG];
     __shared__ unsigned long long sloff;
     __shared__ unsigned long long sbase;
     const int tid = threadIdx.x;
     const Item I = A.items[item];
     const Model md = A.models[I.opt];
+    const Inputs<T> in = inputs_of(md, T{});
     const int N = I.N;
     const int t_top = N - r * BAND;
     const int t_bot = t_top - BAND + 1 > 0 ? t_top - BAND + 1 : 0;
@@ -175,16 +206,18 @@ __device__ void band_task(const KArgs &A, int r, int item, int blk, int64_t *sh,
 
     double *ws = A.ws + (int64_t)blockIdx.x * A.ws_doubles;
     int *wsi = A.wsi + (int64_t)blockIdx.x * A.wsi_ints;
-    double *Stab = ws + A.oStab;
-    double *Pb[2] = {ws + A.oP0, ws + A.oP1};
+    T *Stab = (T *)(ws + A.oStab);
+    T *Pb[2] = {(T *)(ws + A.oP0), (T *)(ws + A.oP1)};
+    const int64_t pcap = A.pcap / NT;        // numbers per private level
     int *poff[2] = {wsi, wsi + WG + 1};
     int *pcnt[2] = {wsi + 2 * (WG + 1), wsi + 3 * (WG + 1)};
-    double *small = ws + A.oSmall;
+    T *small = (T *)(ws + A.oSmall);
     double *pool = ws + A.oPool;
     // band-boundary buffers of this tree side
     const int64_t NN = N + 2;
-    const double *Lin = A.lvl + I.lbuf + (int64_t)(r & 1) * I.lcap;
-    double *Lout = A.lvl + I.lbuf + (int64_t)((r + 1) & 1) * I.lcap;
+    const int64_t lcap = I.lcap / NT;        // numbers per band buffer
+    const T *Lin = (const T *)(A.lvl + I.lbuf + (int64_t)(r & 1) * I.lcap);
+    T *Lout = (T *)(A.lvl + I.lbuf + (int64_t)((r + 1) & 1) * I.lcap);
     const int *offin = A.lvli + I.ibuf + (int64_t)(r & 1) * NN;
     const int *cntin = A.lvli + I.ibuf + 2 * NN + (int64_t)(r & 1) * NN;
     int *offout = A.lvli + I.ibuf + (int64_t)((r + 1) & 1) * NN;
@@ -193,7 +226,7 @@ __device__ void band_task(const KArgs &A, int r, int item, int blk, int64_t *sh,
     // stock prices of the lattice indices this block touches:
     // j = 2c - t for c in [c0, c0 + WG], t in [t_bot, t_top]
     const int jlo = 2 * c0 - t_top, jhi = 2 * (c0 + WG) - t_bot;
-    for (int j = jlo + tid; j <= jhi; j += WG) Stab[j - jlo] = stock_at(md, j);
+    for (int j = jlo + tid; j <= jhi; j += WG) Stab[j - jlo] = stock_at(in, j);
     if (tid == 0) *sflag = 0;
     __syncthreads();
 
@@ -204,35 +237,35 @@ __device__ void band_task(const KArgs &A, int r, int item, int blk, int64_t *sh,
     bool fatal = false;
     int cur = 0;
     for (int t = t_top; t >= t_bot && !fatal; t--) {
-        const double kt = (t >= 1 || (md.flags & F_COST_AT_T0)) ? md.k : 0.0;
+        const T kt = (t >= 1 || (md.flags & F_COST_AT_T0)) ? in.k : mk<T>(0.0);
         const bool exercise = !(euro && t < N);
         const int right = last ? t + 1 : min(c1 + (t - t_bot), t + 1);  // columns [c0, right)
         // children: the band's input level, or the previous private level
         const bool first = t == t_top;
-        const double *Lc = first ? Lin : Pb[cur ^ 1];
+        const T *Lc = first ? Lin : Pb[cur ^ 1];
         const int *offc = first ? offin + c0 : poff[cur ^ 1];
         const int *cntc = first ? cntin + c0 : pcnt[cur ^ 1];
-        double *Ln = Pb[cur];
+        T *Ln = Pb[cur];
         int *offn = poff[cur], *cntn = pcnt[cur];
         const int i = tid;            // column c0 + i
         const int c = c0 + i;
         const bool act = c < right;
-        View Zu{}, Zd{};
-        double S = 0.0, xi = 0.0, ze = 0.0;
+        View<T> Zu{}, Zd{};
+        T S = mk<T>(0.0), xi = mk<T>(0.0), ze = mk<T>(0.0);
         int M = 0;
         if (act) {
             Zd = record_view(Lc, offc[i], cntc[i]);
             Zu = record_view(Lc, offc[i + 1], cntc[i + 1]);
             M = cntc[i] + cntc[i + 1];
             S = Stab[2 * c - t - jlo];
-            payoff(md, S, xi, ze);
+            payoff(md, in, S, xi, ze);
         }
         const bool owned = c < c1 || last;
-        Arr Z{};
+        Arr<T> Z{};
         int mz = 0;
         bool big = act && M > SMALL_CAP;
         if (act && !big) {
-            mz = node_update<SIDE>(Zu, Zd, S, kt, md.rho, xi, ze, exercise, small + tid, WG, sc, &Z);
+            mz = node_update<SIDE, T>(Zu, Zd, S, kt, in.rho, xi, ze, exercise, small + tid, WG, sc, &Z);
             big = mz < 0;
         }
         // one scan for the record sizes (low 40 bits) and the big-node count
@@ -242,14 +275,14 @@ __device__ void band_task(const KArgs &A, int r, int item, int blk, int64_t *sh,
         const int64_t ex = block_scan(sz + (big ? ((int64_t)1 << 40) : 0), &tot, sh);
         const int64_t nbig = tot >> 40, bix = ex >> 40, exs = ex & LOW;
         tot &= LOW;
-        if (tot > A.pcap) {
+        if (tot > pcap) {
             fatal = true;
         } else if (sz) {
             write_record(Ln + exs, Z, mz);
             offn[i] = (int)exs;
             cntn[i] = mz;
             if (owned) {
-                const int bp = (mz == 1 && Z.S(0) == Z.S(1)) ? 0 : mz;
+                const int bp = (mz == 1 && val(Z.S(0)) == val(Z.S(1))) ? 0 : mz;
                 bp_sum += bp;
                 bp_max = bp > bp_max ? bp : bp_max;
             }
@@ -261,17 +294,39 @@ __device__ void band_task(const KArgs &A, int r, int item, int blk, int64_t *sh,
             __syncthreads();
             const int w = tid >> 6, lane = tid & 63;
             const int64_t slice = A.pool / NWAVE;
+            double *chunk = s_chunk[w];
+            int64_t chunk_cap = s_chunk_cap[w];
             for (int bi = w; bi < (int)nbig; bi += NWAVE) {
                 const int ii = sbig[bi];
                 const int cc = c0 + ii;
-                const View Zd2 = record_view(Lc, offc[ii], cntc[ii]);
-                const View Zu2 = record_view(Lc, offc[ii + 1], cntc[ii + 1]);
-                const double S2 = Stab[2 * cc - t - jlo];
-                double xi2, ze2;
-                payoff(md, S2, xi2, ze2);
-                WaveTmp T{pool + w * slice, slice, 0};
-                Arr Zb;
-                const int mzb = wave_node_update<SIDE>(Zu2, Zd2, S2, kt, md.rho, xi2, ze2, exercise, T, &Zb);
+                const View<T> Zd2 = record_view(Lc, offc[ii], cntc[ii]);
+                const View<T> Zu2 = record_view(Lc, offc[ii + 1], cntc[ii + 1]);
+                const T S2 = Stab[2 * cc - t - jlo];
+                T xi2, ze2;
+                payoff(md, in, S2, xi2, ze2);
+                // the wave's pool slice when the node fits, else the arena;
+                // a node that outgrows its slice is redone in the arena
+                const int64_t need = big_need(Zu2.m + Zd2.m, NT);
+                Arr<T> Zb;
+                int mzb = -1;
+#pragma unroll 1
+                for (int attempt = need > slice ? 1 : 0; attempt < 2 && mzb < 0; attempt++) {
+                    double *tb = pool + w * slice;
+                    int64_t tcap = slice;
+                    if (attempt == 1) {
+                        if (chunk_cap < 2 * need) {
+                            const int64_t take = 2 * need > 2 * chunk_cap ? 2 * need : 2 * chunk_cap;
+                            double *p = arena_take(A, 2 * r + SIDE, take);
+                            if (!p) break;
+                            chunk = p;
+                            chunk_cap = take;
+                        }
+                        tb = chunk;
+                        tcap = chunk_cap;
+                    }
+                    WaveTmp WT{tb, tcap, 0};
+                    mzb = wave_node_update<SIDE, T>(Zu2, Zd2, S2, kt, in.rho, xi2, ze2, exercise, WT, &Zb);
+                }
                 if (mzb < 0) {
                     if (lane == 0) *sflag = 1;
                     continue;
@@ -280,11 +335,11 @@ __device__ void band_task(const KArgs &A, int r, int item, int blk, int64_t *sh,
                 unsigned long long pos = 0;
                 if (lane == 0) pos = atomicAdd(&sloff, (unsigned long long)rec);
                 pos = __shfl(pos, 0, 64);
-                if ((int64_t)pos + rec > A.pcap) {
+                if ((int64_t)pos + rec > pcap) {
                     if (lane == 0) *sflag = 1;
                     continue;
                 }
-                double *dst = Ln + pos;
+                T *dst = Ln + pos;
                 for (int j = lane; j < mzb; j += 64) {
                     dst[1 + 3 * j] = Zb.X(j);
                     dst[2 + 3 * j] = Zb.V(j);
@@ -295,11 +350,15 @@ __device__ void band_task(const KArgs &A, int r, int item, int blk, int64_t *sh,
                     offn[ii] = (int)pos;
                     cntn[ii] = mzb;
                     if (cc < c1 || last) {
-                        const int bp = (mzb == 1 && Zb.S(0) == Zb.S(1)) ? 0 : mzb;
+                        const int bp = (mzb == 1 && val(Zb.S(0)) == val(Zb.S(1))) ? 0 : mzb;
                         bp_sum += bp;
                         bp_max = bp > bp_max ? bp : bp_max;
                     }
                 }
+            }
+            if (lane == 0) {
+                s_chunk[w] = chunk;
+                s_chunk_cap[w] = chunk_cap;
             }
             __syncthreads();
             loff = (int64_t)sloff;
@@ -311,7 +370,7 @@ __device__ void band_task(const KArgs &A, int r, int item, int blk, int64_t *sh,
             // side's band buffer; level 0 gives the price
             if (tid == 0) {
                 sbase = atomicAdd(A.fill + I.ctr + r + 1, (unsigned long long)loff);
-                if ((int64_t)sbase + loff > I.lcap) *sflag = 1;
+                if ((int64_t)sbase + loff > lcap) *sflag = 1;
             }
             __syncthreads();
             if (*sflag) {
@@ -324,9 +383,14 @@ __device__ void band_task(const KArgs &A, int r, int item, int blk, int64_t *sh,
                     cntout[c0 + tid] = cntn[tid];
                 }
                 if (t == 0 && tid == 0) {
-                    const double root = eval(record_view(Ln, offn[0], cntn[0]), 0.0);
-                    if (SIDE == 0) A.out[I.opt].ask = root;
-                    else A.out[I.opt].bid = -root;
+                    const T root = eval(record_view(Ln, offn[0], cntn[0]), mk<T>(0.0));
+                    const T price = SIDE == 0 ? root : -root;
+                    if (SIDE == 0) A.out[I.opt].ask = val(price);
+                    else A.out[I.opt].bid = val(price);
+                    if constexpr (NT == 5) {
+                        bt_grad4 &g = SIDE == 0 ? A.grad[I.opt].ask : A.grad[I.opt].bid;
+                        g.dS0 = price.d[0]; g.dsigma = price.d[1]; g.dR = price.d[2]; g.dk = price.d[3];
+                    }
                 }
             }
         }
@@ -364,13 +428,19 @@ __device__ void band_task(const KArgs &A, int r, int item, int blk, int64_t *sh,
 }
 
 // Band r of every tree side of one party, on persistent workgroups.
-template <int SIDE>
+template <int SIDE, typename T>
 __global__ __launch_bounds__(WG) void bt_band_kernel(KArgs A, int r)
 {
     __shared__ int s_task, s_skip;
     __shared__ int s_flag;
     __shared__ int64_t s_scan[NWAVE];
+    __shared__ double *s_chunk[NWAVE];
+    __shared__ int64_t s_chunk_cap[NWAVE];
     const int lo = A.task_off[2 * r + SIDE], hi = A.task_off[2 * r + SIDE + 1];
+    if (threadIdx.x < NWAVE) {
+        s_chunk[threadIdx.x] = nullptr;
+        s_chunk_cap[threadIdx.x] = 0;
+    }
     for (;;) {
         if (threadIdx.x == 0) {
             const int q0 = lo + atomicAdd(A.band_ctr + 2 * r + SIDE, 1);
@@ -387,7 +457,7 @@ __global__ __launch_bounds__(WG) void bt_band_kernel(KArgs A, int r)
         if (q >= hi) break;
         if (skip) continue;
         const Task tk = A.tasks[q];
-        band_task<SIDE>(A, r, tk.item, tk.block, s_scan, &s_flag);
+        band_task<SIDE, T>(A, r, tk.item, tk.block, s_scan, &s_flag, s_chunk, s_chunk_cap);
     }
 }
 
@@ -399,12 +469,13 @@ __device__ void price0_item(const KArgs &A, const Model &md, int opt, double *ws
     const int N = md.N;
     double *Stab = ws + A.oStab;
     double *V0 = ws + A.oPool, *V1 = ws + A.oPool + (N + 1);
+    const Inputs<double> in = inputs_of(md, 0.0);
     stock_table(md, Stab);
     __syncthreads();
     const bool euro = (md.flags & F_EUROPEAN) != 0;
     for (int c = threadIdx.x; c <= N; c += WG) {
         double S = Stab[2 * c + 1], xi, ze;
-        payoff(md, S, xi, ze);
+        payoff(md, in, S, xi, ze);
         double P = xi + ze * S;
         V0[c] = P > 0.0 ? P : 0.0;
     }
@@ -416,7 +487,7 @@ __device__ void price0_item(const KArgs &A, const Model &md, int opt, double *ws
             double cont = rho * (p * cur[c + 1] + q * cur[c]);
             if (euro) { nxt[c] = cont; continue; }
             double S = Stab[2 * c - t + N + 1], xi, ze;
-            payoff(md, S, xi, ze);
+            payoff(md, in, S, xi, ze);
             double P = xi + ze * S;
             if (P < 0.0) P = 0.0;
             nxt[c] = P > cont ? P : cont;
@@ -459,8 +530,17 @@ __global__ void bt_reset_kernel(KArgs A, int64_t n_fill)
         r.status = A.models[k].valid ? BT_OK : BT_EINVAL;
         r.reserved = 0;
         A.out[k] = r;
+        if (A.grad) {
+            bt_grad g;
+            g.ask.dS0 = g.ask.dsigma = g.ask.dR = g.ask.dk = nan;
+            g.bid = g.ask;
+            A.grad[k] = g;
+        }
     }
-    for (int64_t k = i; k < 2 * (int64_t)A.nbands_max; k += stride) A.band_ctr[k] = 0;
+    for (int64_t k = i; k < 2 * (int64_t)A.nbands_max; k += stride) {
+        A.band_ctr[k] = 0;
+        A.arena_ctr[k] = 0;
+    }
     for (int64_t k = i; k < n_fill; k += stride) A.fill[k] = 0;
     for (int64_t k = i; k < A.n_items; k += stride) A.failed[k] = 0;
     if (i == 0) *A.p0_queue = 0;
@@ -518,6 +598,7 @@ struct bt_book {
     int n = 0, n_max = 0, n_items = 0, nbands_max = 0;
     int64_t nodes = 0, n_fill = 0;
     int grid = 0, grid_p0 = 0;
+    bool greeks = false;           // buffers sized for dual numbers
     std::vector<int> ntasks;       // per (band, side)
     Model *d_models = nullptr;
     Item *d_items = nullptr;
@@ -529,6 +610,8 @@ struct bt_book {
     int *d_lvli = nullptr;
     double *d_ws = nullptr;
     int *d_wsi = nullptr;
+    double *d_arena = nullptr;
+    unsigned long long *d_arena_ctr = nullptr;
     KArgs args{};
     bool timing = false;
     std::vector<hipEvent_t> events;  // BT_NUM_KERNELS + 1 per timed call
@@ -544,12 +627,12 @@ void book_free(bt_book *b)
     for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
     b->events.clear();
     void *ptrs[] = {b->d_models, b->d_items, b->d_tasks, b->d_task_off, b->d_ints,
-                    b->d_fill, b->d_lvl, b->d_lvli, b->d_ws, b->d_wsi};
+                    b->d_fill, b->d_lvl, b->d_lvli, b->d_ws, b->d_wsi, b->d_arena, b->d_arena_ctr};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     b->d_models = nullptr; b->d_items = nullptr; b->d_tasks = nullptr; b->d_task_off = nullptr;
     b->d_ints = nullptr; b->d_fill = nullptr; b->d_lvl = nullptr; b->d_lvli = nullptr;
-    b->d_ws = nullptr; b->d_wsi = nullptr;
+    b->d_ws = nullptr; b->d_wsi = nullptr; b->d_arena = nullptr; b->d_arena_ctr = nullptr;
 }
 
 template <typename T>
@@ -573,9 +656,14 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
             nodes += (int64_t)(h[i].N + 1) * (h[i].N + 2) / 2;
         }
     }
-    const int lf = (tune && tune->level_factor > 0) ? tune->level_factor : 32;
+    const int lf = (tune && tune->level_factor > 0) ? tune->level_factor : DEFAULT_LEVEL_FACTOR;
+    const bool greeks = tune && (tune->flags & BT_TUNE_GREEKS);
+    const int64_t nt = greeks ? (int64_t)(sizeof(D4) / sizeof(double)) : 1;  // doubles per number
     const int wpc = (tune && tune->wgs_per_cu > 0) ? tune->wgs_per_cu : 2;
-    const int64_t pool = (tune && tune->pool_points > 0) ? (int64_t)tune->pool_points * 3 : (int64_t)1 << 20;
+    const int64_t pool_pts = (tune && tune->pool_points > 0) ? (int64_t)tune->pool_points
+                                                             : (greeks ? DEFAULT_POOL_POINTS / 4 : DEFAULT_POOL_POINTS);
+    const int64_t pool = pool_pts * 4 * nt;
+    const int64_t arena = std::max<int64_t>(DEFAULT_ARENA_DOUBLES * nt, 64 * pool);
 
     // tree sides (buyer first: the longer recursion), longest tree first
     std::vector<int> order;
@@ -590,7 +678,7 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
             Item it;
             it.opt = i; it.side = side; it.N = models[i].N;
             it.nbands = (it.N + 1 + BAND - 1) / BAND;
-            it.lcap = round_up((int64_t)lf * (it.N + 2) * 3 + (it.N + 2), 32);
+            it.lcap = round_up(((int64_t)lf * (it.N + 2) * 3 + (it.N + 2)) * nt, 32);
             it.lbuf = lbuf; lbuf += 2 * it.lcap;
             it.ibuf = ibuf; ibuf += round_up(4 * (int64_t)(it.N + 2), 32);
             it.ctr = ctr; ctr += it.nbands + 1;
@@ -631,14 +719,17 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
     const int ws_wgs = std::max(grid, grid_p0);
 
     KArgs a{};
-    const int64_t pcap = round_up((int64_t)lf * (WG + 1) * 3 + (WG + 1), 32);
+    // a private level holds the records of WG + 1 columns: lf breakpoints per
+    // node on average, and never fewer than MIN_PRIVATE_POINTS in all (a few
+    // nodes of a level can hold most of its breakpoints)
+    const int64_t pcap = round_up(std::max((int64_t)lf * (WG + 1), MIN_PRIVATE_POINTS) * 3 * nt + (WG + 1) * nt, 32);
     const Caps sc = small_caps();
     a.oStab = 0;
-    const int64_t stab_n = std::max<int64_t>(2 * (int64_t)WG + BAND + 8, 2 * (int64_t)n_max + 3);
+    const int64_t stab_n = std::max<int64_t>((2 * (int64_t)WG + BAND + 8) * nt, 2 * (int64_t)n_max + 3);
     a.oP0 = round_up(stab_n, 32);
     a.oP1 = a.oP0 + pcap;
     a.oSmall = a.oP1 + pcap;
-    a.oPool = a.oSmall + round_up(sc.total * WG, 32);
+    a.oPool = a.oSmall + round_up(sc.total * WG * nt, 32);
     a.ws_doubles = a.oPool + round_up(std::max<int64_t>(pool, 2 * (int64_t)n_max + 4), 32);
     a.wsi_ints = round_up(4 * (int64_t)(WG + 1), 64);
     a.pcap = pcap;
@@ -649,6 +740,7 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
     a.n_p0 = (int)p0.size();
 
     b->timing = tune && (tune->flags & BT_TUNE_TIMING);
+    b->greeks = greeks;
     b->params.assign(h, h + n);
     if (tune) b->tune = *tune;
     b->device = dev;
@@ -664,7 +756,8 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
         (rc = dalloc(&b->d_tasks, tasks.size())) || (rc = dalloc(&b->d_task_off, task_off.size())) ||
         (rc = dalloc(&b->d_ints, nints)) || (rc = dalloc(&b->d_fill, ctr)) ||
         (rc = dalloc(&b->d_lvl, lbuf)) || (rc = dalloc(&b->d_lvli, ibuf)) ||
-        (rc = dalloc(&b->d_ws, a.ws_doubles * ws_wgs)) || (rc = dalloc(&b->d_wsi, a.wsi_ints * ws_wgs))) {
+        (rc = dalloc(&b->d_ws, a.ws_doubles * ws_wgs)) || (rc = dalloc(&b->d_wsi, a.wsi_ints * ws_wgs)) ||
+        (rc = dalloc(&b->d_arena, arena)) || (rc = dalloc(&b->d_arena_ctr, 2 * (size_t)nbands_max))) {
         book_free(b);
         return rc;
     }
@@ -690,6 +783,9 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
     a.wsi = b->d_wsi;
     a.p0_queue = p0q;
     a.p0_sched = p0s;
+    a.arena = b->d_arena;
+    a.arena_cap = arena;
+    a.arena_ctr = b->d_arena_ctr;
     b->args = a;
     return BT_OK;
 }
@@ -724,12 +820,19 @@ int bt_book_info(const bt_book *book, int32_t *n, int32_t *n_max, int64_t *nodes
     return BT_OK;
 }
 
-int bt_book_price(bt_book *book, bt_result *d_out, void *stream)
+}  // extern "C"
+
+namespace {
+
+// Reset, level N+1, the buyer's bands, the seller's bands, the zero-cost
+// recursion; with events between the groups when the book times its calls.
+template <typename T>
+int launch_all(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream)
 {
-    if (!book || !d_out) return BT_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     KArgs a = book->args;
     a.out = d_out;
+    a.grad = d_grad;
     hipEvent_t ev[BT_NUM_KERNELS + 1];
     if (book->timing) {
         for (int i = 0; i <= BT_NUM_KERNELS; i++) HIPCHK(hipEventCreate(&ev[i]));
@@ -742,19 +845,19 @@ int bt_book_price(bt_book *book, bt_result *d_out, void *stream)
     hipLaunchKernelGGL(bt_reset_kernel, dim3(rb), dim3(256), 0, s, a, book->n_fill);
     HIPCHK(hipGetLastError());
     if (book->n_items > 0) {
-        hipLaunchKernelGGL(bt_init_kernel, dim3((book->n_max + 2 + 255) / 256, book->n_items), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(bt_init_kernel<T>, dim3((book->n_max + 2 + 255) / 256, book->n_items), dim3(256), 0, s, a);
         HIPCHK(hipGetLastError());
     }
     if (book->timing) HIPCHK(hipEventRecord(ev[1], s));
     for (int r = 0; r < book->nbands_max; r++) {
         if (book->ntasks[2 * r + 1] == 0) continue;
-        hipLaunchKernelGGL(bt_band_kernel<1>, dim3(std::min(book->grid, book->ntasks[2 * r + 1])), dim3(WG), 0, s, a, r);
+        hipLaunchKernelGGL((bt_band_kernel<1, T>), dim3(std::min(book->grid, book->ntasks[2 * r + 1])), dim3(WG), 0, s, a, r);
         HIPCHK(hipGetLastError());
     }
     if (book->timing) HIPCHK(hipEventRecord(ev[2], s));
     for (int r = 0; r < book->nbands_max; r++) {
         if (book->ntasks[2 * r] == 0) continue;
-        hipLaunchKernelGGL(bt_band_kernel<0>, dim3(std::min(book->grid, book->ntasks[2 * r])), dim3(WG), 0, s, a, r);
+        hipLaunchKernelGGL((bt_band_kernel<0, T>), dim3(std::min(book->grid, book->ntasks[2 * r])), dim3(WG), 0, s, a, r);
         HIPCHK(hipGetLastError());
     }
     if (book->timing) HIPCHK(hipEventRecord(ev[3], s));
@@ -766,15 +869,28 @@ int bt_book_price(bt_book *book, bt_result *d_out, void *stream)
     return BT_OK;
 }
 
-int bt_book_price_grad(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream)
-{
-    (void)book; (void)d_out; (void)d_grad; (void)stream;
-    return BT_ENOSUPP;
-}
+}  // namespace
 
-int bt_book_resolve_overflow(bt_book *book, bt_result *d_out, void *stream, int32_t *remaining)
+extern "C" {
+
+int bt_book_price(bt_book *book, bt_result *d_out, void *stream)
 {
     if (!book || !d_out) return BT_EINVAL;
+    return launch_all<double>(book, d_out, nullptr, stream);
+}
+
+int bt_book_price_grad(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream)
+{
+    if (!book || !d_out || !d_grad) return BT_EINVAL;
+    if (!book->greeks) return BT_ENOSUPP;
+    return launch_all<D4>(book, d_out, d_grad, stream);
+}
+
+int bt_book_resolve_overflow(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream,
+                             int32_t *remaining)
+{
+    if (!book || !d_out) return BT_EINVAL;
+    if (d_grad && !book->greeks) return BT_ENOSUPP;
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(hipStreamSynchronize(s));
     std::vector<bt_result> res(book->n);
@@ -782,43 +898,63 @@ int bt_book_resolve_overflow(bt_book *book, bt_result *d_out, void *stream, int3
     std::vector<int> idx;
     for (int i = 0; i < book->n; i++)
         if (res[i].status == BT_EOVERFLOW) idx.push_back(i);
-    const int base_lf = book->tune.level_factor > 0 ? book->tune.level_factor : 32;
-    const int base_pool = book->tune.pool_points > 0 ? book->tune.pool_points : (1 << 20) / 3;
+    std::vector<bt_grad> grd;
+    if (d_grad && !idx.empty()) {
+        grd.resize(book->n);
+        HIPCHK(hipMemcpy(grd.data(), d_grad, sizeof(bt_grad) * book->n, hipMemcpyDeviceToHost));
+    }
+    const int base_lf = book->tune.level_factor > 0 ? book->tune.level_factor : DEFAULT_LEVEL_FACTOR;
+    const int64_t base_pool = book->tune.pool_points > 0 ? book->tune.pool_points
+                                                         : (book->greeks ? DEFAULT_POOL_POINTS / 4 : DEFAULT_POOL_POINTS);
+    const bool had = !idx.empty();
     for (int mult = 4; !idx.empty() && mult <= 1024; mult *= 4) {
         std::vector<bt_params> sub;
         for (int i : idx) sub.push_back(book->params[i]);
         bt_tune t = book->tune;
-        t.flags = 0;
+        t.flags = d_grad ? BT_TUNE_GREEKS : 0;
         t.level_factor = base_lf * mult;
-        t.pool_points = (int32_t)std::min<int64_t>((int64_t)base_pool * mult, (int64_t)1 << 28);
+        t.pool_points = (int32_t)std::min<int64_t>(base_pool * mult, (int64_t)1 << 22);
         t.wgs_per_cu = 1;
         bt_book *sb = nullptr;
         int rc = bt_book_create(sub.data(), (int32_t)sub.size(), &t, &sb);
         if (rc != BT_OK) return rc;
         bt_result *d_sub = nullptr;
-        if (hipMalloc(&d_sub, sizeof(bt_result) * sub.size()) != hipSuccess) {
+        bt_grad *d_subg = nullptr;
+        if (hipMalloc(&d_sub, sizeof(bt_result) * sub.size()) != hipSuccess ||
+            (d_grad && hipMalloc(&d_subg, sizeof(bt_grad) * sub.size()) != hipSuccess)) {
+            (void)hipGetLastError();
+            if (d_sub) (void)hipFree(d_sub);
             bt_book_destroy(sb);
             return BT_ENOMEM;
         }
-        rc = bt_book_price(sb, d_sub, stream);
+        rc = d_grad ? bt_book_price_grad(sb, d_sub, d_subg, stream) : bt_book_price(sb, d_sub, stream);
         std::vector<bt_result> sres(sub.size());
+        std::vector<bt_grad> sgrd(d_grad ? sub.size() : 0);
         if (rc == BT_OK) {
             hipError_t e = hipMemcpyAsync(sres.data(), d_sub, sizeof(bt_result) * sub.size(), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess && d_grad)
+                e = hipMemcpyAsync(sgrd.data(), d_subg, sizeof(bt_grad) * sub.size(), hipMemcpyDeviceToHost, s);
             if (e == hipSuccess) e = hipStreamSynchronize(s);
             if (e != hipSuccess) { g_last_hip = (int)e; rc = BT_EHIP; }
         }
         (void)hipFree(d_sub);
+        if (d_subg) (void)hipFree(d_subg);
         bt_book_destroy(sb);
         if (rc != BT_OK) return rc;
         std::vector<int> still;
         for (size_t j = 0; j < idx.size(); j++) {
             res[idx[j]] = sres[j];
+            if (d_grad) grd[idx[j]] = sgrd[j];
             if (sres[j].status == BT_EOVERFLOW) still.push_back(idx[j]);
         }
         idx.swap(still);
     }
-    HIPCHK(hipMemcpyAsync(d_out, res.data(), sizeof(bt_result) * book->n, hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));
+    if (had) {
+        HIPCHK(hipMemcpyAsync(d_out, res.data(), sizeof(bt_result) * book->n, hipMemcpyHostToDevice, s));
+        if (d_grad)
+            HIPCHK(hipMemcpyAsync(d_grad, grd.data(), sizeof(bt_grad) * book->n, hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
     if (remaining) *remaining = (int32_t)idx.size();
     return BT_OK;
 }
@@ -877,7 +1013,7 @@ int bt_price(const bt_params *p, bt_result *out)
         cache_N = ok ? p->N : -1;
     }
     rc = bt_book_price(cache, d_res, nullptr);
-    if (rc == BT_OK) rc = bt_book_resolve_overflow(cache, d_res, nullptr, nullptr);
+    if (rc == BT_OK) rc = bt_book_resolve_overflow(cache, d_res, nullptr, nullptr, nullptr);
     if (rc != BT_OK) return rc;
     HIPCHK(hipMemcpy(out, d_res, sizeof(bt_result), hipMemcpyDeviceToHost));
     return BT_OK;

@@ -19,8 +19,13 @@
 //   CLIP   restriction of a convex function's slopes to [-S^a_t, -S^b_t].
 //   ENV    the same restriction for a general function: the largest
 //          minorant with slopes in [a, b], the cheapest rebalancing at the
-//          ask/bid stock prices, built from a right-to-left sweep (stock
-//          bought at S^a) and a mirrored sweep (stock sold at S^b).
+//          ask/bid stock prices, built from a buying half (slopes >= a) and a
+//          mirrored selling half (slopes <= b).
+//
+// The number type T is double, or D4: a value with its derivatives with
+// respect to (S0, sigma, R, k) carried forward through every operation (the
+// Greeks).  Decisions look at values only, so both types take the same
+// branches and produce the same value bits.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -34,42 +39,100 @@
 
 namespace bt {
 
+// A value and its four tangents (d/dS0, d/dsigma, d/dR, d/dk).
+struct D4 {
+    double v, d[4];
+};
+
+BTD D4 operator+(const D4 &a, const D4 &b)
+{
+    D4 r;
+    r.v = a.v + b.v;
+    for (int i = 0; i < 4; i++) r.d[i] = a.d[i] + b.d[i];
+    return r;
+}
+BTD D4 operator-(const D4 &a, const D4 &b)
+{
+    D4 r;
+    r.v = a.v - b.v;
+    for (int i = 0; i < 4; i++) r.d[i] = a.d[i] - b.d[i];
+    return r;
+}
+BTD D4 operator-(const D4 &a)
+{
+    D4 r;
+    r.v = -a.v;
+    for (int i = 0; i < 4; i++) r.d[i] = -a.d[i];
+    return r;
+}
+BTD D4 operator*(const D4 &a, const D4 &b)
+{
+    D4 r;
+    r.v = a.v * b.v;
+    for (int i = 0; i < 4; i++) r.d[i] = a.d[i] * b.v + a.v * b.d[i];
+    return r;
+}
+BTD D4 operator/(const D4 &a, const D4 &b)
+{
+    D4 r;
+    r.v = a.v / b.v;
+    for (int i = 0; i < 4; i++) r.d[i] = (a.d[i] - r.v * b.d[i]) / b.v;
+    return r;
+}
+
+BTD double val(double x) { return x; }
+BTD double val(const D4 &x) { return x.v; }
+
+template <typename T> BTD T mk(double x);
+template <> BTD double mk<double>(double x) { return x; }
+template <> BTD D4 mk<D4>(double x)
+{
+    D4 r;
+    r.v = x;
+    r.d[0] = r.d[1] = r.d[2] = r.d[3] = 0.0;
+    return r;
+}
+
 // Read view of a PWL function stored with an element stride.
+template <typename T>
 struct View {
-    const double *x, *v, *s;
+    const T *x, *v, *s;
     int m, st;
-    BTD double X(int j) const { return x[(int64_t)j * st]; }
-    BTD double V(int j) const { return v[(int64_t)j * st]; }
-    BTD double S(int j) const { return s[(int64_t)j * st]; }
+    BTD const T &X(int j) const { return x[(int64_t)j * st]; }
+    BTD const T &V(int j) const { return v[(int64_t)j * st]; }
+    BTD const T &S(int j) const { return s[(int64_t)j * st]; }
 };
 
 // Writable storage with room for `cap` points (and cap + 1 slopes).
+template <typename T>
 struct Arr {
-    double *x, *v, *s;
+    T *x, *v, *s;
     int st, cap;
-    BTD double &X(int j) const { return x[(int64_t)j * st]; }
-    BTD double &V(int j) const { return v[(int64_t)j * st]; }
-    BTD double &S(int j) const { return s[(int64_t)j * st]; }
-    BTD View view(int m) const { return View{x, v, s, m, st}; }
+    BTD T &X(int j) const { return x[(int64_t)j * st]; }
+    BTD T &V(int j) const { return v[(int64_t)j * st]; }
+    BTD T &S(int j) const { return s[(int64_t)j * st]; }
+    BTD View<T> view(int m) const { return View<T>{x, v, s, m, st}; }
 };
 
 enum { OPMAX = 0, OPMIN = 1 };
 enum { PNONE = -1, PF = 0, PG = 1 };
 
-BTD double eval_at(const View &f, int i, double y)
+template <typename T, typename F>
+BTD T eval_at(const F &f, int i, const T &y)
 {
     if (i == 0) return f.V(0) + f.S(0) * (y - f.X(0));
     return f.V(i - 1) + f.S(i) * (y - f.X(i - 1));
 }
 
-BTD double eval(const View &f, double y)
+template <typename T>
+BTD T eval(const View<T> &f, const T &y)
 {
     int lo = 0, hi = f.m;
     while (lo < hi) {
         int mid = (lo + hi) >> 1;
-        if (f.X(mid) <= y) lo = mid + 1; else hi = mid;
+        if (val(f.X(mid)) <= val(y)) lo = mid + 1; else hi = mid;
     }
-    return eval_at(f, lo, y);
+    return eval_at<T>(f, lo, y);
 }
 
 template <int OP> BTD int better(double d)
@@ -78,35 +141,37 @@ template <int OP> BTD int better(double d)
     return d < 0.0 ? PF : (d > 0.0 ? PG : PNONE);
 }
 
-template <int OP> BTD double pick(double a, double b)
+template <int OP, typename T> BTD T pick(const T &a, const T &b)
 {
-    if (OP == OPMAX) return a >= b ? a : b;
-    return a <= b ? a : b;
+    if (OP == OPMAX) return val(a) >= val(b) ? a : b;
+    return val(a) <= val(b) ? a : b;
 }
 
 // Output stream with CANON applied on the fly: a point is stored only if
 // the slope arriving from its left differs from the slope leaving to its
 // right.  Because a dropped point has equal slopes on both sides, the slope
 // arriving at the next point is unchanged by the drop.
+template <typename T>
 struct Emit {
-    Arr o;
+    Arr<T> o;
     int m;
     bool ovf, have0;
-    double cur, x0, v0;
-    BTD void start(const Arr &out, double s_left)
+    double cur;
+    T x0, v0;
+    BTD void start(const Arr<T> &out, const T &s_left)
     {
         o = out; m = 0; ovf = false; have0 = false;
-        cur = s_left;
+        cur = val(s_left);
         o.S(0) = s_left;
     }
-    BTD void push(double x, double v, double s_right)
+    BTD void push(const T &x, const T &v, const T &s_right)
     {
         if (!have0) { x0 = x; v0 = v; have0 = true; }
-        if (cur != s_right) {
+        if (cur != val(s_right)) {
             if (m < o.cap) { o.X(m) = x; o.V(m) = v; o.S(m + 1) = s_right; }
             else ovf = true;
             m++;
-            cur = s_right;
+            cur = val(s_right);
         }
     }
     // Returns the point count, or -1 when the storage was too small.
@@ -119,18 +184,19 @@ struct Emit {
 };
 
 // In-place CANON of a stored function; returns the new point count.
-BTD int canon(const Arr &f, int m)
+template <typename T>
+BTD int canon(const Arr<T> &f, int m)
 {
-    double s0 = f.S(0);
+    const T s0 = f.S(0);
     int k = 0;
     for (int j = 0; j < m; j++) {
         // Writes go to indices k <= j (slopes k + 1 <= j + 1, equal only
         // when nothing was dropped, rewriting the same value), so s[j] and
         // s[j+1] still hold the input here.
-        double sl = f.S(j), sr = f.S(j + 1);
+        const double sl = val(f.S(j)), sr = val(f.S(j + 1));
         if (sl != sr) {
-            double xj = f.X(j), vj = f.V(j);
-            f.X(k) = xj; f.V(k) = vj; f.S(k + 1) = sr;
+            const T xj = f.X(j), vj = f.V(j), srj = f.S(j + 1);
+            f.X(k) = xj; f.V(k) = vj; f.S(k + 1) = srj;
             k++;
         }
     }
@@ -139,58 +205,44 @@ BTD int canon(const Arr &f, int m)
     return k;
 }
 
-// MERGE(F, G, op) into `out`; returns the point count or -1 on overflow.
-//  - P is the sorted union of both breakpoint lists (exact duplicates
-//    merged); at every P_k, d_k = EVAL(F, P_k) - EVAL(G, P_k).
-//  - Interval (P_k, P_k+1) with slopes sF != sG and d_k, d_k+1 of strictly
-//    opposite signs crosses at y* = P_k + d_k / (sG - sF); y* <= P_k or
-//    y* >= P_k+1 leaves the whole interval to the winner at the other end.
-//    Without a crossing the winner is the better function at P_k, else at
-//    P_k+1, else the one with the larger (MAX) / smaller (MIN) slope, F on a
-//    full tie.
-//  - Each tail's far winner follows from the slopes (MAX: smaller slope to
-//    the left, larger to the right; MIN reversed); equal slopes fall back to
-//    the sign of d at the end point, then F.  When the end point's winner
-//    differs, the crossing y* = P_ref + d_ref / (sG - sF) is added if it lies
-//    strictly outside the end point.
-//  - Values are op(EVAL(F, y), EVAL(G, y)); slopes are the winner's.
 // What MERGE emits for one union point P_k: the slope leaving P_k to the
 // right (rs) and, when the interval after P_k holds a crossing, that point
 // (cy, cv) and the slope leaving it (crs).
+template <typename T>
 struct Slot {
-    double rs;
+    T rs;
     bool hc;
-    double cy, cv, crs;
+    T cy, cv, crs;
 };
 
-// Interval (P, P1) with F, G values fF, fG at P (d = fF - fG) and d1 at P1;
+// Interval (P, P1) with F, G values fF, fG at P and d1 = F - G at P1;
 // iF, iG = #{points <= P} in F and G.
-template <int OP>
-BTD Slot slot_interval(const View &F, const View &G, double P, int iF, int iG, double fF, double fG,
-                       double d, double P1, double d1)
+template <int OP, typename T, typename FF, typename GG>
+BTD Slot<T> slot_interval(const FF &F, const GG &G, const T &P, int iF, int iG, const T &fF, const T &fG,
+                          const T &P1, double d1)
 {
-    Slot o;
-    o.hc = false; o.cy = 0.0; o.cv = 0.0; o.crs = 0.0;
-    const double sF = F.S(iF), sG = G.S(iG);
-    const int b0 = better<OP>(d), b1 = better<OP>(d1);
-    if (sF != sG && b0 != PNONE && b1 != PNONE && b0 != b1) {
-        const double y = P + (fF - fG) / (sG - sF);
-        if (y <= P) {
+    Slot<T> o;
+    o.hc = false;
+    const T sF = F.S(iF), sG = G.S(iG);
+    const int b0 = better<OP>(val(fF) - val(fG)), b1 = better<OP>(d1);
+    if (val(sF) != val(sG) && b0 != PNONE && b1 != PNONE && b0 != b1) {
+        const T y = P + (fF - fG) / (sG - sF);
+        if (val(y) <= val(P)) {
             o.rs = b1 == PF ? sF : sG;
-        } else if (y >= P1) {
+        } else if (val(y) >= val(P1)) {
             o.rs = b0 == PF ? sF : sG;
         } else {
             o.rs = b0 == PF ? sF : sG;
             o.hc = true;
             o.cy = y;
-            o.cv = pick<OP>(eval_at(F, iF, y), eval_at(G, iG, y));
+            o.cv = pick<OP, T>(eval_at<T>(F, iF, y), eval_at<T>(G, iG, y));
             o.crs = b1 == PF ? sF : sG;
         }
     } else {
         int act = b0 != PNONE ? b0 : b1;
         if (act == PNONE) {
-            if (OP == OPMAX) act = (sG > sF) ? PG : PF;
-            else act = (sG < sF) ? PG : PF;
+            if (OP == OPMAX) act = (val(sG) > val(sF)) ? PG : PF;
+            else act = (val(sG) < val(sF)) ? PG : PF;
         }
         o.rs = act == PF ? sF : sG;
     }
@@ -198,23 +250,23 @@ BTD Slot slot_interval(const View &F, const View &G, double P, int iF, int iG, d
 }
 
 // Right tail after the last union point P.
-template <int OP>
-BTD Slot slot_right(const View &F, const View &G, double P, double fF, double fG, double d)
+template <int OP, typename T, typename FF, typename GG>
+BTD Slot<T> slot_right(const FF &F, const GG &G, const T &P, const T &fF, const T &fG)
 {
-    Slot o;
-    o.hc = false; o.cy = 0.0; o.cv = 0.0; o.crs = 0.0;
-    const double sF = F.S(F.m), sG = G.S(G.m);
-    const int bl = better<OP>(d);
+    Slot<T> o;
+    o.hc = false;
+    const T sF = F.S(F.m), sG = G.S(G.m);
+    const int bl = better<OP>(val(fF) - val(fG));
     int far;
-    if (sF != sG) far = (OP == OPMAX) ? (sF > sG ? PF : PG) : (sF < sG ? PF : PG);
+    if (val(sF) != val(sG)) far = (OP == OPMAX) ? (val(sF) > val(sG) ? PF : PG) : (val(sF) < val(sG) ? PF : PG);
     else far = (bl != PNONE) ? bl : PF;
-    if (sF != sG && bl != PNONE && bl != far) {
-        const double y = P + (fF - fG) / (sG - sF);
-        if (y > P) {
+    if (val(sF) != val(sG) && bl != PNONE && bl != far) {
+        const T y = P + (fF - fG) / (sG - sF);
+        if (val(y) > val(P)) {
             o.rs = bl == PF ? sF : sG;
             o.hc = true;
             o.cy = y;
-            o.cv = pick<OP>(eval_at(F, F.m, y), eval_at(G, G.m, y));
+            o.cv = pick<OP, T>(eval_at<T>(F, F.m, y), eval_at<T>(G, G.m, y));
             o.crs = far == PF ? sF : sG;
         } else {
             o.rs = far == PF ? sF : sG;
@@ -225,25 +277,25 @@ BTD Slot slot_right(const View &F, const View &G, double P, double fF, double fG
     return o;
 }
 
-// Left tail before the first union point P0: the far-left slope s0 and an
-// optional crossing (cy, cv) leaving with slope crs.
-template <int OP>
-BTD Slot slot_left(const View &F, const View &G, double P0, double fF, double fG, double d)
+// Left tail before the first union point P0: the far-left slope s0 (rs) and
+// an optional crossing (cy, cv) leaving with slope crs.
+template <int OP, typename T, typename FF, typename GG>
+BTD Slot<T> slot_left(const FF &F, const GG &G, const T &P0, const T &fF, const T &fG)
 {
-    Slot o;
-    o.hc = false; o.cy = 0.0; o.cv = 0.0; o.crs = 0.0;
-    const double sF = F.S(0), sG = G.S(0);
-    const int b0 = better<OP>(d);
+    Slot<T> o;
+    o.hc = false;
+    const T sF = F.S(0), sG = G.S(0);
+    const int b0 = better<OP>(val(fF) - val(fG));
     int far;
-    if (sF != sG) far = (OP == OPMAX) ? (sF < sG ? PF : PG) : (sF > sG ? PF : PG);
+    if (val(sF) != val(sG)) far = (OP == OPMAX) ? (val(sF) < val(sG) ? PF : PG) : (val(sF) > val(sG) ? PF : PG);
     else far = (b0 != PNONE) ? b0 : PF;
     o.rs = far == PF ? sF : sG;
-    if (sF != sG && b0 != PNONE && b0 != far) {
-        const double y = P0 + (fF - fG) / (sG - sF);
-        if (y < P0) {
+    if (val(sF) != val(sG) && b0 != PNONE && b0 != far) {
+        const T y = P0 + (fF - fG) / (sG - sF);
+        if (val(y) < val(P0)) {
             o.hc = true;
             o.cy = y;
-            o.cv = pick<OP>(eval_at(F, 0, y), eval_at(G, 0, y));
+            o.cv = pick<OP, T>(eval_at<T>(F, 0, y), eval_at<T>(G, 0, y));
             o.crs = b0 == PF ? sF : sG;
         }
     }
@@ -265,47 +317,46 @@ BTD Slot slot_left(const View &F, const View &G, double P0, double fF, double fG
 //    differs, the crossing y* = P_ref + d_ref / (sG - sF) is added if it lies
 //    strictly outside the end point.
 //  - Values are op(EVAL(F, y), EVAL(G, y)); slopes are the winner's.
-template <int OP>
-BTD int merge(const View &F, const View &G, const Arr &out)
+// F and G are any types with m, X(j), V(j), S(j).
+template <int OP, typename T, typename FF, typename GG>
+BTD int merge(const FF &F, const GG &G, const Arr<T> &out)
 {
     const double INF = __builtin_huge_val();
     int a = 0, b = 0;
-    double P, fF, fG, d;
+    T P, fF, fG;
     int iF, iG;
     {
-        const double xa = F.X(0), xb = G.X(0);
-        if (xa < xb) { P = xa; a = 1; }
-        else if (xb < xa) { P = xb; b = 1; }
-        else { P = xa; a = 1; b = 1; }
+        const double xa = val(F.X(0)), xb = val(G.X(0));
+        if (xa < xb) { P = F.X(0); a = 1; }
+        else if (xb < xa) { P = G.X(0); b = 1; }
+        else { P = F.X(0); a = 1; b = 1; }
         iF = a; iG = b;
-        fF = eval_at(F, iF, P);
-        fG = eval_at(G, iG, P);
-        d = fF - fG;
+        fF = eval_at<T>(F, iF, P);
+        fG = eval_at<T>(G, iG, P);
     }
-    Emit e;
+    Emit<T> e;
     {
-        const Slot L = slot_left<OP>(F, G, P, fF, fG, d);
+        const Slot<T> L = slot_left<OP, T>(F, G, P, fF, fG);
         e.start(out, L.rs);
         if (L.hc) e.push(L.cy, L.cv, L.crs);
     }
     for (;;) {
-        const double val = pick<OP>(fF, fG);
+        const T vv = pick<OP, T>(fF, fG);
         if (a < F.m || b < G.m) {
-            const double xa = a < F.m ? F.X(a) : INF, xb = b < G.m ? G.X(b) : INF;
-            double P1;
-            if (xa < xb) { P1 = xa; a++; }
-            else if (xb < xa) { P1 = xb; b++; }
-            else { P1 = xa; a++; b++; }
+            const double xa = a < F.m ? val(F.X(a)) : INF, xb = b < G.m ? val(G.X(b)) : INF;
+            T P1;
+            if (xa < xb) { P1 = F.X(a); a++; }
+            else if (xb < xa) { P1 = G.X(b); b++; }
+            else { P1 = F.X(a); a++; b++; }
             const int iF1 = a, iG1 = b;
-            const double fF1 = eval_at(F, iF1, P1), fG1 = eval_at(G, iG1, P1);
-            const double d1 = fF1 - fG1;
-            const Slot o = slot_interval<OP>(F, G, P, iF, iG, fF, fG, d, P1, d1);
-            e.push(P, val, o.rs);
+            const T fF1 = eval_at<T>(F, iF1, P1), fG1 = eval_at<T>(G, iG1, P1);
+            const Slot<T> o = slot_interval<OP, T>(F, G, P, iF, iG, fF, fG, P1, val(fF1) - val(fG1));
+            e.push(P, vv, o.rs);
             if (o.hc) e.push(o.cy, o.cv, o.crs);
-            P = P1; iF = iF1; iG = iG1; fF = fF1; fG = fG1; d = d1;
+            P = P1; iF = iF1; iG = iG1; fF = fF1; fG = fG1;
         } else {
-            const Slot o = slot_right<OP>(F, G, P, fF, fG, d);
-            e.push(P, val, o.rs);
+            const Slot<T> o = slot_right<OP, T>(F, G, P, fF, fG);
+            e.push(P, vv, o.rs);
             if (o.hc) e.push(o.cy, o.cv, o.crs);
             break;
         }
@@ -314,7 +365,8 @@ BTD int merge(const View &F, const View &G, const Arr &out)
 }
 
 // SCALE by rho in place, then CANON.
-BTD int scale(const Arr &f, int m, double rho)
+template <typename T>
+BTD int scale(const Arr<T> &f, int m, const T &rho)
 {
     for (int j = 0; j < m; j++) f.V(j) = f.V(j) * rho;
     for (int j = 0; j <= m; j++) f.S(j) = f.S(j) * rho;
@@ -324,39 +376,43 @@ BTD int scale(const Arr &f, int m, double rho)
 // CLIP(F, a, b) in place (seller, F convex).  a < b: clamp every slope into
 // [a, b], then CANON.  a == b: the line of slope a through x[q],
 // q = clamp(i0 - 1, 0, m - 1), i0 = min{j : s[j] >= a}.
-BTD int clip(const Arr &f, int m, double a, double b)
+template <typename T>
+BTD int clip(const Arr<T> &f, int m, const T &a, const T &b)
 {
-    if (a == b) {
+    if (val(a) == val(b)) {
         int i0 = 0;
-        while (i0 <= m && f.S(i0) < a) i0++;
+        while (i0 <= m && val(f.S(i0)) < val(a)) i0++;
         int q = i0 - 1;
         if (q < 0) q = 0;
         if (q > m - 1) q = m - 1;
-        double xq = f.X(q), vq = f.V(q);
+        const T xq = f.X(q), vq = f.V(q);
         f.X(0) = xq; f.V(0) = vq; f.S(0) = a; f.S(1) = a;
         return 1;
     }
     for (int j = 0; j <= m; j++) {
-        double s = f.S(j);
-        if (s < a) f.S(j) = a;
-        else if (s > b) f.S(j) = b;
+        const double s = val(f.S(j));
+        if (s < val(a)) f.S(j) = a;
+        else if (s > val(b)) f.S(j) = b;
     }
     return canon(f, m);
 }
 
 // Accessors of F or of its mirror image y -> -y.
-template <bool MIR> struct Src {
-    View f;
-    BTD double X(int j) const { return MIR ? -f.X(f.m - 1 - j) : f.X(j); }
-    BTD double V(int j) const { return MIR ? f.V(f.m - 1 - j) : f.V(j); }
-    BTD double S(int j) const { return MIR ? -f.S(f.m - j) : f.S(j); }
+template <bool MIR, typename T>
+struct Src {
+    View<T> f;
+    int m;
+    BTD T X(int j) const { return MIR ? -f.X(f.m - 1 - j) : f.X(j); }
+    BTD T V(int j) const { return MIR ? f.V(f.m - 1 - j) : f.V(j); }
+    BTD T S(int j) const { return MIR ? -f.S(f.m - j) : f.S(j); }
 };
 
 // Reverse points [0, n) and slopes [0, n) in place.
-BTD void reverse_pts(const Arr &o, int n)
+template <typename T>
+BTD void reverse_pts(const Arr<T> &o, int n)
 {
     for (int i = 0, j = n - 1; i < j; i++, j--) {
-        double t;
+        T t;
         t = o.X(i); o.X(i) = o.X(j); o.X(j) = t;
         t = o.V(i); o.V(i) = o.V(j); o.V(j) = t;
         t = o.S(i); o.S(i) = o.S(j); o.S(j) = t;
@@ -378,31 +434,31 @@ BTD void reverse_pts(const Arr &o, int n)
 // right to left with a running minimum (ties keep the nearer index), written
 // in reverse and flipped.  Requires s_0 < a < s_m.  Returns the count or -1
 // on overflow.
-template <bool MIR>
-BTD int sweep_a(const View &F, double a, const Arr &o)
+template <bool MIR, typename T>
+BTD int sweep_a(const View<T> &F, const T &a, const Arr<T> &o)
 {
-    Src<MIR> f{F};
+    Src<MIR, T> f{F, F.m};
     const int m = F.m;
     int n = 0;
-    double SMc = 0.0, xq = 0.0, vq = 0.0;
+    T SMc = mk<T>(0.0), xq = mk<T>(0.0), vq = mk<T>(0.0);
     int Qc = -1;
-    double xr = 0.0;  // x_{j+1}
+    double xr = 0.0;  // value of x_{j+1}
     for (int j = m - 1; j >= 0; j--) {
-        const double xj = f.X(j), vj = f.V(j);
-        const double hj = vj - a * xj;
-        double rs;
+        const T xj = f.X(j), vj = f.V(j);
+        const T hj = vj - a * xj;
+        T rs;
         if (j == m - 1) {
             rs = f.S(m);
         } else {
-            const double sp = f.S(j + 1);
+            const T sp = f.S(j + 1);
             int kind = 0;  // 0 FLAT, 1 FOLLOW, 2 SPLIT
-            double y = 0.0;
+            T y = mk<T>(0.0);
             if (Qc == j + 1) {
-                if (sp >= a) kind = 1;
-            } else if (hj < SMc && sp > a) {
+                if (val(sp) >= val(a)) kind = 1;
+            } else if (val(hj) < val(SMc) && val(sp) > val(a)) {
                 y = xj + (SMc - hj) / (sp - a);
-                if (!(y < xr)) kind = 1;
-                else if (y > xj) kind = 2;
+                if (!(val(y) < xr)) kind = 1;
+                else if (val(y) > val(xj)) kind = 2;
             }
             if (kind == 2) {
                 if (n >= o.cap) return -1;
@@ -414,8 +470,8 @@ BTD int sweep_a(const View &F, double a, const Arr &o)
         if (n >= o.cap) return -1;
         o.X(n) = xj; o.V(n) = vj; o.S(n) = rs;
         n++;
-        if (j == m - 1 || hj <= SMc) { SMc = hj; Qc = j; xq = xj; vq = vj; }
-        xr = xj;
+        if (j == m - 1 || val(hj) <= val(SMc)) { SMc = hj; Qc = j; xq = xj; vq = vj; }
+        xr = val(xj);
     }
     reverse_pts(o, n);
     // s[i] now holds the right slope of point i: shift to s[i+1], left tail a
@@ -425,16 +481,17 @@ BTD int sweep_a(const View &F, double a, const Arr &o)
 }
 
 // Mirror in place: x_j <- -x_{n-1-j}, v_j <- v_{n-1-j}, s_j <- -s_{n-j}.
-BTD void mirror_inplace(const Arr &o, int n)
+template <typename T>
+BTD void mirror_inplace(const Arr<T> &o, int n)
 {
     for (int i = 0, j = n - 1; i < j; i++, j--) {
-        double t;
+        T t;
         t = o.X(i); o.X(i) = o.X(j); o.X(j) = t;
         t = o.V(i); o.V(i) = o.V(j); o.V(j) = t;
     }
     for (int i = 0; i < n; i++) o.X(i) = -o.X(i);
     for (int i = 0, j = n; i < j; i++, j--) {
-        double t = o.S(i); o.S(i) = o.S(j); o.S(j) = t;
+        T t = o.S(i); o.S(i) = o.S(j); o.S(j) = t;
     }
     for (int i = 0; i <= n; i++) o.S(i) = -o.S(i);
 }

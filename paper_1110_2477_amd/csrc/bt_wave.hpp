@@ -40,18 +40,25 @@ __device__ __forceinline__ void wave_sync()
 struct WaveTmp {
     double *base;
     int64_t cap, used;
+#ifdef BT_HOST_DEBUG
+    int64_t peak = 0;   // high-water mark, for sizing studies on the host
+#endif
     BTD double *dbl(int64_t n)
     {
         if (n < 1) n = 1;
         if (used + n > cap) return nullptr;
         double *p = base + used;
         used += (n + 1) & ~(int64_t)1;  // keep 16-byte alignment
+#ifdef BT_HOST_DEBUG
+        if (used > peak) peak = used;
+#endif
         return p;
     }
     BTD int *ints(int64_t n) { return (int *)dbl((n + 1) / 2); }
-    BTD bool arr(int cap_pts, Arr *a)
+    template <typename T> BTD T *nums(int64_t n) { return (T *)dbl(n * (int64_t)(sizeof(T) / sizeof(double))); }
+    template <typename T> BTD bool arr(int cap_pts, Arr<T> *a)
     {
-        double *p = dbl(3 * (int64_t)cap_pts + 1);
+        T *p = nums<T>(3 * (int64_t)cap_pts + 1);
         if (!p) return false;
         a->x = p; a->v = p + cap_pts; a->s = p + 2 * (int64_t)cap_pts;
         a->st = 1; a->cap = cap_pts;
@@ -92,13 +99,14 @@ BTD void argmin_pick(double &h, int &q, double h2, int q2)
     if (h2 < h || (h2 == h && q2 < q)) { h = h2; q = q2; }
 }
 
-// Inclusive suffix minima of h[0..n) with the smallest index attaining each:
-// SM[j] = min_{i >= j} h[i], Q[j] = that index.
-BTD void wave_suffix_min(const double *h, double *SM, int *Q, int n)
+// Inclusive suffix minima of the values of h[0..n) with the smallest index
+// attaining each: SM[j] = min_{i >= j} h[i], Q[j] = that index.
+template <typename T>
+BTD void wave_suffix_min(const T *h, double *SM, int *Q, int n)
 {
 #ifdef BT_HOST_DEBUG
     for (int j = n - 1; j >= 0; j--) {
-        if (j == n - 1 || h[j] <= SM[j + 1]) { SM[j] = h[j]; Q[j] = j; }
+        if (j == n - 1 || val(h[j]) <= SM[j + 1]) { SM[j] = val(h[j]); Q[j] = j; }
         else { SM[j] = SM[j + 1]; Q[j] = Q[j + 1]; }
     }
 #else
@@ -107,7 +115,7 @@ BTD void wave_suffix_min(const double *h, double *SM, int *Q, int n)
     int cq = 0x7fffffff;
     for (int base = ((n - 1) / 64) * 64; base >= 0; base -= 64) {
         const int i = base + lane;
-        double x = i < n ? h[i] : __builtin_huge_val();
+        double x = i < n ? val(h[i]) : __builtin_huge_val();
         int qi = i < n ? i : 0x7fffffff;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
@@ -144,12 +152,13 @@ BTD int wave_min_int(const int *c, int n, int init)
 }
 
 // #{j : f.X(j) < y}
-BTD int lower_count(const View &f, double y)
+template <typename N>
+BTD int lower_count(const View<N> &f, double y)
 {
     int lo = 0, hi = f.m;
     while (lo < hi) {
         int mid = (lo + hi) >> 1;
-        if (f.X(mid) < y) lo = mid + 1; else hi = mid;
+        if (val(f.X(mid)) < y) lo = mid + 1; else hi = mid;
     }
     return lo;
 }
@@ -162,12 +171,13 @@ BTD int lower_count(const View &f, double y)
 #endif
 
 // CANON of A (m points) into out; returns the count or -1 on overflow.
-BTD int wave_canon(const Arr &A, int m, const Arr &out, WaveTmp &T)
+template <typename N>
+BTD int wave_canon(const Arr<N> &A, int m, const Arr<N> &out, WaveTmp &T)
 {
     const int64_t mark = T.used;
     int *c = T.ints(m + 1);
     if (!c) return -1;
-    PAR_FOR(j, m) c[j] = A.S(j) != A.S(j + 1) ? 1 : 0;
+    PAR_FOR(j, m) c[j] = val(A.S(j)) != val(A.S(j + 1)) ? 1 : 0;
     WSYNC();
     const int k = wave_scan(c, m);
     int r;
@@ -178,7 +188,7 @@ BTD int wave_canon(const Arr &A, int m, const Arr &out, WaveTmp &T)
     } else {
         if (k > out.cap) { T.used = mark; return -1; }
         PAR_FOR(j, m) {
-            if (A.S(j) != A.S(j + 1)) {
+            if (val(A.S(j)) != val(A.S(j + 1))) {
                 const int p = c[j];
                 out.X(p) = A.X(j); out.V(p) = A.V(j); out.S(p + 1) = A.S(j + 1);
             }
@@ -192,8 +202,8 @@ BTD int wave_canon(const Arr &A, int m, const Arr &out, WaveTmp &T)
 }
 
 // MERGE(F, G, op) into out (same result as merge<OP>).
-template <int OP>
-BTD int wave_merge(const View &F, const View &G, const Arr &out, WaveTmp &T)
+template <int OP, typename N>
+BTD int wave_merge(const View<N> &F, const View<N> &G, const Arr<N> &out, WaveTmp &T)
 {
     const int mF = F.m, mG = G.m;
     const int64_t mark = T.used;
@@ -201,17 +211,17 @@ BTD int wave_merge(const View &F, const View &G, const Arr &out, WaveTmp &T)
     int *rF = T.ints(mG);
     if (!dup || !rF) return -1;
     PAR_FOR(b, mG) {
-        const double xb = G.X(b);
+        const double xb = val(G.X(b));
         const int r = lower_count(F, xb);
         rF[b] = r;
-        dup[b] = (r < mF && F.X(r) == xb) ? 1 : 0;
+        dup[b] = (r < mF && val(F.X(r)) == xb) ? 1 : 0;
     }
     WSYNC();
     const int ndup = wave_scan(dup, mG);
     const int K = mF + mG - ndup;
-    double *P = T.dbl(K), *fF = T.dbl(K), *fG = T.dbl(K);
+    N *P = T.nums<N>(K), *fF = T.nums<N>(K), *fG = T.nums<N>(K);
     int *IF = T.ints(K), *IG = T.ints(K);
-    double *rs = T.dbl(K), *cy = T.dbl(K), *cv = T.dbl(K), *crs = T.dbl(K);
+    N *rs = T.nums<N>(K), *cy = T.nums<N>(K), *cv = T.nums<N>(K), *crs = T.nums<N>(K);
     int *hc = T.ints(K), *cnt = T.ints(K + 1);
     if (!P || !fF || !fG || !IF || !IG || !rs || !cy || !cv || !crs || !hc || !cnt) { T.used = mark; return -1; }
     // dup[] is now the exclusive count of duplicated G points before b;
@@ -219,11 +229,11 @@ BTD int wave_merge(const View &F, const View &G, const Arr &out, WaveTmp &T)
     LANE0(dup[mG] = ndup);
     WSYNC();
     PAR_FOR(a, mF) {
-        const double xa = F.X(a);
+        const double xa = val(F.X(a));
         const int r = lower_count(G, xa);
-        const bool eq = r < mG && G.X(r) == xa;
+        const bool eq = r < mG && val(G.X(r)) == xa;
         const int k = a + r - dup[r];
-        P[k] = xa; IF[k] = a + 1; IG[k] = r + (eq ? 1 : 0);
+        P[k] = F.X(a); IF[k] = a + 1; IG[k] = r + (eq ? 1 : 0);
     }
     PAR_FOR(b, mG) {
         if (dup[b + 1] == dup[b]) {
@@ -233,26 +243,27 @@ BTD int wave_merge(const View &F, const View &G, const Arr &out, WaveTmp &T)
     }
     WSYNC();
     PAR_FOR(k, K) {
-        fF[k] = eval_at(F, IF[k], P[k]);
-        fG[k] = eval_at(G, IG[k], P[k]);
+        fF[k] = eval_at<N>(F, IF[k], P[k]);
+        fG[k] = eval_at<N>(G, IG[k], P[k]);
     }
     WSYNC();
     PAR_FOR(k, K) {
-        const double d = fF[k] - fG[k];
-        Slot o;
-        if (k < K - 1) o = slot_interval<OP>(F, G, P[k], IF[k], IG[k], fF[k], fG[k], d, P[k + 1], fF[k + 1] - fG[k + 1]);
-        else o = slot_right<OP>(F, G, P[k], fF[k], fG[k], d);
-        rs[k] = o.rs; hc[k] = o.hc ? 1 : 0; cy[k] = o.cy; cv[k] = o.cv; crs[k] = o.crs;
+        Slot<N> o;
+        if (k < K - 1) o = slot_interval<OP, N>(F, G, P[k], IF[k], IG[k], fF[k], fG[k], P[k + 1],
+                                               val(fF[k + 1]) - val(fG[k + 1]));
+        else o = slot_right<OP, N>(F, G, P[k], fF[k], fG[k]);
+        rs[k] = o.rs; hc[k] = o.hc ? 1 : 0;
+        if (o.hc) { cy[k] = o.cy; cv[k] = o.cv; crs[k] = o.crs; }
     }
-    const Slot L = slot_left<OP>(F, G, P[0], fF[0], fG[0], fF[0] - fG[0]);
+    const Slot<N> L = slot_left<OP, N>(F, G, P[0], fF[0], fG[0]);
     WSYNC();
     // CANON on the emitted sequence [L crossing], P_0, [c_0], P_1, [c_1], ...
     PAR_FOR(k, K) {
-        const double sl = k == 0 ? (L.hc ? L.crs : L.rs) : (hc[k - 1] ? crs[k - 1] : rs[k - 1]);
-        cnt[k] = (sl != rs[k] ? 1 : 0) + ((hc[k] && rs[k] != crs[k]) ? 1 : 0);
+        const double sl = k == 0 ? val(L.hc ? L.crs : L.rs) : val(hc[k - 1] ? crs[k - 1] : rs[k - 1]);
+        cnt[k] = (sl != val(rs[k]) ? 1 : 0) + ((hc[k] && val(rs[k]) != val(crs[k])) ? 1 : 0);
     }
     WSYNC();
-    const int keepL = (L.hc && L.rs != L.crs) ? 1 : 0;
+    const int keepL = (L.hc && val(L.rs) != val(L.crs)) ? 1 : 0;
     const int tot = wave_scan(cnt, K) + keepL;
     int r;
     if (tot > out.cap) {
@@ -260,7 +271,7 @@ BTD int wave_merge(const View &F, const View &G, const Arr &out, WaveTmp &T)
     } else if (tot == 0) {
         if (out.cap < 1) r = -1;
         else {
-            LANE0((out.X(0) = L.hc ? L.cy : P[0], out.V(0) = L.hc ? L.cv : pick<OP>(fF[0], fG[0]),
+            LANE0((out.X(0) = L.hc ? L.cy : P[0], out.V(0) = L.hc ? L.cv : pick<OP, N>(fF[0], fG[0]),
                    out.S(0) = L.rs, out.S(1) = L.rs));
             r = 1;
         }
@@ -268,13 +279,13 @@ BTD int wave_merge(const View &F, const View &G, const Arr &out, WaveTmp &T)
         LANE0(out.S(0) = L.rs);
         if (keepL) LANE0((out.X(0) = L.cy, out.V(0) = L.cv, out.S(1) = L.crs));
         PAR_FOR(k, K) {
-            const double sl = k == 0 ? (L.hc ? L.crs : L.rs) : (hc[k - 1] ? crs[k - 1] : rs[k - 1]);
+            const double sl = k == 0 ? val(L.hc ? L.crs : L.rs) : val(hc[k - 1] ? crs[k - 1] : rs[k - 1]);
             int p = keepL + cnt[k];
-            if (sl != rs[k]) {
-                out.X(p) = P[k]; out.V(p) = pick<OP>(fF[k], fG[k]); out.S(p + 1) = rs[k];
+            if (sl != val(rs[k])) {
+                out.X(p) = P[k]; out.V(p) = pick<OP, N>(fF[k], fG[k]); out.S(p + 1) = rs[k];
                 p++;
             }
-            if (hc[k] && rs[k] != crs[k]) { out.X(p) = cy[k]; out.V(p) = cv[k]; out.S(p + 1) = crs[k]; }
+            if (hc[k] && val(rs[k]) != val(crs[k])) { out.X(p) = cy[k]; out.V(p) = cv[k]; out.S(p + 1) = crs[k]; }
         }
         r = tot;
     }
@@ -284,11 +295,12 @@ BTD int wave_merge(const View &F, const View &G, const Arr &out, WaveTmp &T)
 }
 
 // SCALE by rho from A into B (then CANON into out).
-BTD int wave_scale(const Arr &A, int m, double rho, const Arr &out, WaveTmp &T)
+template <typename N>
+BTD int wave_scale(const Arr<N> &A, int m, const N &rho, const Arr<N> &out, WaveTmp &T)
 {
     const int64_t mark = T.used;
-    Arr B;
-    if (!T.arr(m, &B)) return -1;
+    Arr<N> B;
+    if (!T.arr<N>(m, &B)) return -1;
     PAR_FOR(j, m) { B.X(j) = A.X(j); B.V(j) = A.V(j) * rho; }
     PAR_FOR(j, m + 1) B.S(j) = A.S(j) * rho;
     WSYNC();
@@ -298,13 +310,14 @@ BTD int wave_scale(const Arr &A, int m, double rho, const Arr &out, WaveTmp &T)
 }
 
 // CLIP(A, a, b) into out (seller).
-BTD int wave_clip(const Arr &A, int m, double a, double b, const Arr &out, WaveTmp &T)
+template <typename N>
+BTD int wave_clip(const Arr<N> &A, int m, const N &a, const N &b, const Arr<N> &out, WaveTmp &T)
 {
     const int64_t mark = T.used;
-    if (a == b) {
+    if (val(a) == val(b)) {
         int *c = T.ints(m + 1);
         if (!c || out.cap < 1) { T.used = mark; return -1; }
-        PAR_FOR(j, m + 1) c[j] = A.S(j) >= a ? j : m + 1;
+        PAR_FOR(j, m + 1) c[j] = val(A.S(j)) >= val(a) ? j : m + 1;
         WSYNC();
         const int i0 = wave_min_int(c, m + 1, m + 1);
         int q = i0 - 1;
@@ -316,22 +329,23 @@ BTD int wave_clip(const Arr &A, int m, double a, double b, const Arr &out, WaveT
         return 1;
     }
     PAR_FOR(j, m + 1) {
-        const double s = A.S(j);
-        if (s < a) A.S(j) = a;
-        else if (s > b) A.S(j) = b;
+        const double s = val(A.S(j));
+        if (s < val(a)) A.S(j) = a;
+        else if (s > val(b)) A.S(j) = b;
     }
     WSYNC();
     return wave_canon(A, m, out, T);
 }
 
 // The buying half of ENV (same definition as sweep_a) into out.
-template <bool MIR>
-BTD int wave_sweep_a(const View &F, double a, const Arr &out, WaveTmp &T)
+template <bool MIR, typename N>
+BTD int wave_sweep_a(const View<N> &F, const N &a, const Arr<N> &out, WaveTmp &T)
 {
-    Src<MIR> f{F};
+    Src<MIR, N> f{F, F.m};
     const int m = F.m;
     const int64_t mark = T.used;
-    double *h = T.dbl(m), *SM = T.dbl(m), *rs = T.dbl(m), *y = T.dbl(m), *yv = T.dbl(m);
+    N *h = T.nums<N>(m), *rs = T.nums<N>(m), *y = T.nums<N>(m), *yv = T.nums<N>(m);
+    double *SM = T.dbl(m);
     int *Q = T.ints(m), *sp = T.ints(m), *cnt = T.ints(m + 1);
     if (!h || !SM || !rs || !y || !yv || !Q || !sp || !cnt) { T.used = mark; return -1; }
     PAR_FOR(j, m) h[j] = f.V(j) - a * f.X(j);
@@ -339,34 +353,34 @@ BTD int wave_sweep_a(const View &F, double a, const Arr &out, WaveTmp &T)
     wave_suffix_min(h, SM, Q, m);
     PAR_FOR(j, m) {
         int kind = 0;
-        double yy = 0.0, vv = 0.0;
         if (j == m - 1) {
             rs[j] = f.S(m);
         } else {
-            const double spj = f.S(j + 1);
-            const double SMj = SM[j + 1];
+            const N spj = f.S(j + 1);
             const int Qj = Q[j + 1];
-            const double hj = h[j];
+            const N hj = h[j];
             if (Qj == j + 1) {
-                if (spj >= a) kind = 1;
-            } else if (hj < SMj && spj > a) {
-                yy = f.X(j) + (SMj - hj) / (spj - a);
-                if (!(yy < f.X(j + 1))) kind = 1;
-                else if (yy > f.X(j)) {
+                if (val(spj) >= val(a)) kind = 1;
+            } else if (val(hj) < SM[j + 1] && val(spj) > val(a)) {
+                const N xj = f.X(j);
+                const N yy = xj + (h[Qj] - hj) / (spj - a);
+                if (!(val(yy) < val(f.X(j + 1)))) kind = 1;
+                else if (val(yy) > val(xj)) {
                     kind = 2;
-                    vv = f.V(Qj) + a * (yy - f.X(Qj));
+                    y[j] = yy;
+                    yv[j] = f.V(Qj) + a * (yy - f.X(Qj));
                 }
             }
             rs[j] = kind != 0 ? spj : a;
         }
         sp[j] = kind == 2 ? 1 : 0;
-        y[j] = yy; yv[j] = vv;
     }
     WSYNC();
     // CANON of x_0, [y_0], x_1, ... with left tail a; y_j leaves with a
+    const double av = val(a);
     PAR_FOR(j, m) {
-        const double sl = j == 0 ? a : (sp[j - 1] ? a : rs[j - 1]);
-        cnt[j] = (sl != rs[j] ? 1 : 0) + ((sp[j] && rs[j] != a) ? 1 : 0);
+        const double sl = j == 0 ? av : (sp[j - 1] ? av : val(rs[j - 1]));
+        cnt[j] = (sl != val(rs[j]) ? 1 : 0) + ((sp[j] && val(rs[j]) != av) ? 1 : 0);
     }
     WSYNC();
     const int tot = wave_scan(cnt, m);
@@ -379,10 +393,10 @@ BTD int wave_sweep_a(const View &F, double a, const Arr &out, WaveTmp &T)
     } else {
         LANE0(out.S(0) = a);
         PAR_FOR(j, m) {
-            const double sl = j == 0 ? a : (sp[j - 1] ? a : rs[j - 1]);
+            const double sl = j == 0 ? av : (sp[j - 1] ? av : val(rs[j - 1]));
             int p = cnt[j];
-            if (sl != rs[j]) { out.X(p) = f.X(j); out.V(p) = f.V(j); out.S(p + 1) = rs[j]; p++; }
-            if (sp[j] && rs[j] != a) { out.X(p) = y[j]; out.V(p) = yv[j]; out.S(p + 1) = a; }
+            if (sl != val(rs[j])) { out.X(p) = f.X(j); out.V(p) = f.V(j); out.S(p + 1) = rs[j]; p++; }
+            if (sp[j] && val(rs[j]) != av) { out.X(p) = y[j]; out.V(p) = yv[j]; out.S(p + 1) = a; }
         }
         r = tot;
     }
@@ -392,12 +406,14 @@ BTD int wave_sweep_a(const View &F, double a, const Arr &out, WaveTmp &T)
 }
 
 // ENV(F, a, b) into out (buyer).
-BTD int wave_env(const Arr &Fa, int m, double a, double b, const Arr &out, WaveTmp &T)
+template <typename N>
+BTD int wave_env(const Arr<N> &Fa, int m, const N &a, const N &b, const Arr<N> &out, WaveTmp &T)
 {
     const int64_t mark = T.used;
-    const View F = Fa.view(m);
-    if (a == b) {
-        double *h = T.dbl(m), *SM = T.dbl(m);
+    const View<N> F = Fa.view(m);
+    if (val(a) == val(b)) {
+        N *h = T.nums<N>(m);
+        double *SM = T.dbl(m);
         int *Q = T.ints(m);
         if (!h || !SM || !Q || out.cap < 1) { T.used = mark; return -1; }
         PAR_FOR(j, m) h[j] = F.V(j) - a * F.X(j);
@@ -409,54 +425,62 @@ BTD int wave_env(const Arr &Fa, int m, double a, double b, const Arr &out, WaveT
         T.used = mark;
         return 1;
     }
-    Arr A, RB, B;
-    if (!T.arr(2 * m, &A) || !T.arr(2 * m, &RB) || !T.arr(2 * m, &B)) { T.used = mark; return -1; }
-    const int ma = wave_sweep_a<false>(F, a, A, T);
-    const int mrb = ma < 0 ? -1 : wave_sweep_a<true>(F, -b, RB, T);
+    Arr<N> A, RB, B;
+    if (!T.arr<N>(2 * m, &A) || !T.arr<N>(2 * m, &RB) || !T.arr<N>(2 * m, &B)) { T.used = mark; return -1; }
+    const int ma = wave_sweep_a<false, N>(F, a, A, T);
+    const int mrb = ma < 0 ? -1 : wave_sweep_a<true, N>(F, -b, RB, T);
     if (ma < 0 || mrb < 0) { T.used = mark; return -1; }
     // B = mirror(RB), then CANON
-    Arr Bm;
-    if (!T.arr(mrb, &Bm)) { T.used = mark; return -1; }
+    Arr<N> Bm;
+    if (!T.arr<N>(mrb, &Bm)) { T.used = mark; return -1; }
     PAR_FOR(j, mrb) { Bm.X(j) = -RB.X(mrb - 1 - j); Bm.V(j) = RB.V(mrb - 1 - j); }
     PAR_FOR(j, mrb + 1) Bm.S(j) = -RB.S(mrb - j);
     WSYNC();
     const int mb = wave_canon(Bm, mrb, B, T);
-    const int mv = mb < 0 ? -1 : wave_merge<OPMIN>(A.view(ma), B.view(mb), out, T);
+    const int mv = mb < 0 ? -1 : wave_merge<OPMIN, N>(A.view(ma), B.view(mb), out, T);
     T.used = mark;
     return mv;
 }
 
 // One node update by a whole wave (see node_update).  The result is left in
 // *zout inside T's slice (valid until T is reset).
-template <int SIDE>
-BTD int wave_node_update(const View &Zu, const View &Zd, double S, double kt, double rho, double xi,
-                         double zeta, bool exercise, WaveTmp &T, Arr *zout)
+template <int SIDE, typename N>
+BTD int wave_node_update(const View<N> &Zu, const View<N> &Zd, const N &S, const N &kt, const N &rho,
+                         const N &xi, const N &zeta, bool exercise, WaveTmp &T, Arr<N> *zout)
 {
-    const double a = -((1.0 + kt) * S);
-    const double b = -((1.0 - kt) * S);
+    const N one = mk<N>(1.0);
+    const N a = -((one + kt) * S);
+    const N b = -((one - kt) * S);
     const int M = Zu.m + Zd.m;
-    Arr W, W2, V;
-    if (!T.arr(2 * M + 1, &W)) return -1;
-    int mw = wave_merge<OPMAX>(Zu, Zd, W, T);
-    if (mw < 0 || !T.arr(mw, &W2)) return -1;
+    Arr<N> W, W2, V;
+    if (!T.arr<N>(2 * M + 1, &W)) return -1;
+    int mw = wave_merge<OPMAX, N>(Zu, Zd, W, T);
+    if (mw < 0 || !T.arr<N>(mw, &W2)) return -1;
     mw = wave_scale(W, mw, rho, W2, T);
     if (mw < 0) return -1;
     int mv;
     if (SIDE == 0) {
-        if (!T.arr(mw, &V)) return -1;
+        if (!T.arr<N>(mw, &V)) return -1;
         mv = wave_clip(W2, mw, a, b, V, T);
     } else {
-        const int64_t capv = 8 * (int64_t)mw + 1;
-        if (!T.arr((int)capv, &V)) return -1;
+        // the output of ENV is bounded by 8 mw + 1 points but is about mw in
+        // practice: try a buffer of 2 mw + 8 first and fall back to the bound
+        const int64_t markv = T.used;
+        if (!T.arr<N>(2 * mw + 8, &V)) return -1;
         mv = wave_env(W2, mw, a, b, V, T);
+        if (mv < 0) {
+            T.used = markv;
+            if (!T.arr<N>(8 * mw + 1, &V)) return -1;
+            mv = wave_env(W2, mw, a, b, V, T);
+        }
     }
     if (mv < 0) return -1;
     if (!exercise) { *zout = V; return mv; }
-    Arr U, Z;
-    if (!T.arr(1, &U) || !T.arr(2 * mv + 3, &Z)) return -1;
+    Arr<N> U, Z;
+    if (!T.arr<N>(1, &U) || !T.arr<N>(2 * mv + 3, &Z)) return -1;
     LANE0((U.X(0) = SIDE == 0 ? zeta : -zeta, U.V(0) = SIDE == 0 ? xi : -xi, U.S(0) = a, U.S(1) = b));
     WSYNC();
-    const int mz = wave_merge<SIDE == 0 ? OPMAX : OPMIN>(U.view(1), V.view(mv), Z, T);
+    const int mz = wave_merge<SIDE == 0 ? OPMAX : OPMIN, N>(U.view(1), V.view(mv), Z, T);
     *zout = Z;
     return mz;
 }
