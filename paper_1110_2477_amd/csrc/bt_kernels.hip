@@ -187,7 +187,7 @@ __global__ void bt_init_kernel(KArgs A)
 // and reused by the wave's later big nodes; grown when a node needs more).
 template <int SIDE, typename T>
 __device__ void band_task(const KArgs &A, int r, int item, int blk, int64_t *sh, int *sflag,
-                          double **s_chunk, int64_t *s_chunk_cap)
+                          double **s_chunk, int64_t *s_chunk_cap, T *s_win)
 {
     constexpr int NT = sizeof(T) / sizeof(double);
     __shared__ int sbig[WG];
@@ -325,7 +325,8 @@ __device__ void band_task(const KArgs &A, int r, int item, int blk, int64_t *sh,
                         tcap = chunk_cap;
                     }
                     WaveTmp WT{tb, tcap, 0};
-                    mzb = wave_node_update<SIDE, T>(Zu2, Zd2, S2, kt, in.rho, xi2, ze2, exercise, WT, &Zb);
+                    mzb = wave_node_update<SIDE, T>(Zu2, Zd2, S2, kt, in.rho, xi2, ze2, exercise, WT,
+                                                    s_win + w * WaveLds<T>::NUMS, &Zb);
                 }
                 if (mzb < 0) {
                     if (lane == 0) *sflag = 1;
@@ -436,6 +437,7 @@ __global__ __launch_bounds__(WG) void bt_band_kernel(KArgs A, int r)
     __shared__ int64_t s_scan[NWAVE];
     __shared__ double *s_chunk[NWAVE];
     __shared__ int64_t s_chunk_cap[NWAVE];
+    __shared__ T s_win[NWAVE * WaveLds<T>::NUMS];   // MERGE windows of the cooperative path
     const int lo = A.task_off[2 * r + SIDE], hi = A.task_off[2 * r + SIDE + 1];
     if (threadIdx.x < NWAVE) {
         s_chunk[threadIdx.x] = nullptr;
@@ -457,7 +459,7 @@ __global__ __launch_bounds__(WG) void bt_band_kernel(KArgs A, int r)
         if (q >= hi) break;
         if (skip) continue;
         const Task tk = A.tasks[q];
-        band_task<SIDE, T>(A, r, tk.item, tk.block, s_scan, &s_flag, s_chunk, s_chunk_cap);
+        band_task<SIDE, T>(A, r, tk.item, tk.block, s_scan, &s_flag, s_chunk, s_chunk_cap, s_win);
     }
 }
 

@@ -117,11 +117,31 @@ struct Arr {
 enum { OPMAX = 0, OPMIN = 1 };
 enum { PNONE = -1, PF = 0, PG = 1 };
 
+// The piece of f holding abscissa y when i = #{points <= y}: the line
+// through (x, v) with slope s (the left tail through the first point for
+// i = 0).
+template <typename T>
+struct Seg {
+    T x, v, s;
+};
+
+template <typename T, typename F>
+BTD Seg<T> seg_at(const F &f, int i)
+{
+    if (i == 0) return Seg<T>{f.X(0), f.V(0), f.S(0)};
+    return Seg<T>{f.X(i - 1), f.V(i - 1), f.S(i)};
+}
+
+template <typename T>
+BTD T seg_eval(const Seg<T> &g, const T &y)
+{
+    return g.v + g.s * (y - g.x);
+}
+
 template <typename T, typename F>
 BTD T eval_at(const F &f, int i, const T &y)
 {
-    if (i == 0) return f.V(0) + f.S(0) * (y - f.X(0));
-    return f.V(i - 1) + f.S(i) * (y - f.X(i - 1));
+    return seg_eval<T>(seg_at<T>(f, i), y);
 }
 
 template <typename T>
@@ -216,14 +236,15 @@ struct Slot {
 };
 
 // Interval (P, P1) with F, G values fF, fG at P and d1 = F - G at P1;
-// iF, iG = #{points <= P} in F and G.
-template <int OP, typename T, typename FF, typename GG>
-BTD Slot<T> slot_interval(const FF &F, const GG &G, const T &P, int iF, int iG, const T &fF, const T &fG,
-                          const T &P1, double d1)
+// gF, gG: the pieces of F and G over the interval (seg_at with
+// #{points <= P}).
+template <int OP, typename T>
+BTD Slot<T> slot_interval_seg(const Seg<T> &gF, const Seg<T> &gG, const T &P, const T &fF, const T &fG,
+                              const T &P1, double d1)
 {
     Slot<T> o;
     o.hc = false;
-    const T sF = F.S(iF), sG = G.S(iG);
+    const T sF = gF.s, sG = gG.s;
     const int b0 = better<OP>(val(fF) - val(fG)), b1 = better<OP>(d1);
     if (val(sF) != val(sG) && b0 != PNONE && b1 != PNONE && b0 != b1) {
         const T y = P + (fF - fG) / (sG - sF);
@@ -235,7 +256,7 @@ BTD Slot<T> slot_interval(const FF &F, const GG &G, const T &P, int iF, int iG, 
             o.rs = b0 == PF ? sF : sG;
             o.hc = true;
             o.cy = y;
-            o.cv = pick<OP, T>(eval_at<T>(F, iF, y), eval_at<T>(G, iG, y));
+            o.cv = pick<OP, T>(seg_eval<T>(gF, y), seg_eval<T>(gG, y));
             o.crs = b1 == PF ? sF : sG;
         }
     } else {
@@ -247,6 +268,14 @@ BTD Slot<T> slot_interval(const FF &F, const GG &G, const T &P, int iF, int iG, 
         o.rs = act == PF ? sF : sG;
     }
     return o;
+}
+
+// iF, iG = #{points <= P} in F and G.
+template <int OP, typename T, typename FF, typename GG>
+BTD Slot<T> slot_interval(const FF &F, const GG &G, const T &P, int iF, int iG, const T &fF, const T &fG,
+                          const T &P1, double d1)
+{
+    return slot_interval_seg<OP, T>(seg_at<T>(F, iF), seg_at<T>(G, iG), P, fF, fG, P1, d1);
 }
 
 // Right tail after the last union point P.

@@ -1,17 +1,32 @@
 // bt_wave.hpp -- one node update of Section 3 computed cooperatively by the
 // 64 lanes of a wavefront, for nodes whose functions carry many
-// breakpoints.  Every operation is the same as in bt_pwl.hpp (same
-// per-element formulas, so the same bits); only the order in which elements
-// are produced changes:
-//   - MERGE ranks every breakpoint of each input in the other one by
-//     bisection to place it in the union, evaluates each union point and its
-//     interval independently (slot_interval), then keeps the points whose
-//     two slopes differ (CANON) with a prefix sum for their positions;
-//   - SCALE, CLIP and CANON work element by element plus a prefix sum;
-//   - the buying half of ENV takes its suffix minima from a wave-wide scan.
-// Work is written as phases "for every element i" (PAR_FOR) separated by
-// WSYNC, with scans as separate primitives, so that a host build can run
-// the same code with one lane.
+// breakpoints.  Every operation gives the same result as in bt_pwl.hpp (the
+// same per-element formulas, so the same bits); only the order in which
+// elements are produced changes.
+//
+// The work goes in tiles of 64 E consecutive elements (E per lane; 4 for
+// double, 1 for the dual numbers of the Greeks), so that a tile's loads are
+// issued together and its latency is paid once per tile:
+//   - CANON (and SCALE, CLIP, the mirror image taken by ENV, applied on the
+//     fly as accessors of its input) loads a tile into registers, counts the
+//     points each lane keeps, takes an exclusive scan over the lanes and
+//     writes at the running offset;
+//   - MERGE stages, per tile of the merged order of both breakpoint lists
+//     (F first on equal abscissae), the windows of F and G the tile touches
+//     in LDS with coalesced loads; each lane then finds its diagonal by
+//     merge-path bisection inside the windows and walks it once (with a
+//     lookbehind of two merged positions and a lookahead of one union
+//     point), staging the points it emits in LDS, from where they are
+//     copied to their place after a scan of the counts;
+//   - the buying half of ENV runs its tiles from right to left with the
+//     running suffix minimum of h carried between tiles, and writes its
+//     points from the right end of the output buffer (their number is only
+//     known at the end); the caller reads the result at the returned offset.
+// Lane-parallel code is written as LANES(l) { ... } blocks over per-lane
+// values LV<T>, with the cross-lane steps (scans, broadcasts) between the
+// blocks: on the GPU a block runs once per lane, in a host build
+// (BT_HOST_DEBUG) it runs for every emulated lane in turn, so the host
+// build checks the lane logic for any number of lanes.
 #pragma once
 
 #include "bt_pwl.hpp"
@@ -19,13 +34,27 @@
 namespace bt {
 
 #ifdef BT_HOST_DEBUG
-#define WLANE 0
-#define PAR_FOR(i, n) for (int i = 0; i < (n); i++)
+inline int bt_host_lanes = 64;   // lanes emulated by the host build (<= 256)
+#define NLANES (bt_host_lanes)
+#define LANES(l) for (int l = 0; l < bt_host_lanes; l++)
 #define WSYNC() do { } while (0)
+#define LANE0(stmt) do { stmt; } while (0)
+template <typename T>
+struct LV {
+    T *a;
+    LV() : a(new T[256]) {}
+    ~LV() { delete[] a; }
+    LV(const LV &) = delete;
+    LV &operator=(const LV &) = delete;
+    T &operator()(int l) { return a[l]; }
+    const T &operator()(int l) const { return a[l]; }
+};
 #else
 #define WLANE ((int)(threadIdx.x & 63))
-#define PAR_FOR(i, n) for (int i = WLANE; i < (n); i += 64)
+#define NLANES 64
+#define LANES(l) for (int l = WLANE, l##_once = 1; l##_once; l##_once = 0)
 #define WSYNC() wave_sync()
+#define LANE0(stmt) do { if (WLANE == 0) { stmt; } } while (0)
 __device__ __forceinline__ void wave_sync()
 {
     // stores of this wave visible to its own later loads from other lanes
@@ -33,7 +62,38 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
+template <typename T>
+struct LV {
+    T a;
+    __device__ __forceinline__ T &operator()(int) { return a; }
+    __device__ __forceinline__ const T &operator()(int) const { return a; }
+};
+__device__ __forceinline__ double shfl_num(double x, int src) { return __shfl(x, src, 64); }
+__device__ __forceinline__ int shfl_num(int x, int src) { return __shfl(x, src, 64); }
+__device__ __forceinline__ D4 shfl_num(const D4 &x, int src)
+{
+    D4 r;
+    r.v = __shfl(x.v, src, 64);
+    for (int i = 0; i < 4; i++) r.d[i] = __shfl(x.d[i], src, 64);
+    return r;
+}
 #endif
+
+// Elements per lane in a tile.
+template <typename N>
+struct TileE {
+    static constexpr int E = sizeof(N) == sizeof(double) ? 4 : 1;
+};
+
+// Numbers of LDS one wave's MERGE takes: two windows (x and v of W points
+// and s of W + 1 slopes each, W = 64 E + 9) and the staging of the points
+// the lanes emit (x, v, s of 2 E slots per lane).
+template <typename N>
+struct WaveLds {
+    static constexpr int W = 64 * TileE<N>::E + 9;
+    static constexpr int STAGE = 2 * TileE<N>::E * 64;
+    static constexpr int NUMS = 2 * (3 * W + 1) + 3 * STAGE;
+};
 
 // Bump allocator over a wave's slice of the pool (doubles).  All lanes make
 // the same calls, so the pointers are uniform.
@@ -54,7 +114,6 @@ struct WaveTmp {
 #endif
         return p;
     }
-    BTD int *ints(int64_t n) { return (int *)dbl((n + 1) / 2); }
     template <typename T> BTD T *nums(int64_t n) { return (T *)dbl(n * (int64_t)(sizeof(T) / sizeof(double))); }
     template <typename T> BTD bool arr(int cap_pts, Arr<T> *a)
     {
@@ -66,387 +125,935 @@ struct WaveTmp {
     }
 };
 
-// Exclusive prefix sum of c[0..n) in place; returns the total (all lanes).
-BTD int wave_scan(int *c, int n)
+// ---------------------------------------------------------------------------
+// Cross-lane steps.
+// ---------------------------------------------------------------------------
+
+// Exclusive prefix sums over the lanes in place; returns the total.
+BTD int lv_exscan(LV<int> &v)
 {
 #ifdef BT_HOST_DEBUG
     int acc = 0;
-    for (int i = 0; i < n; i++) { int v = c[i]; c[i] = acc; acc += v; }
+    for (int l = 0; l < bt_host_lanes; l++) { const int t = v(l); v(l) = acc; acc += t; }
     return acc;
 #else
-    const int lane = WLANE;
-    int carry = 0;
-    for (int base = 0; base < n; base += 64) {
-        const int i = base + lane;
-        const int v = i < n ? c[i] : 0;
-        int x = v;
+    const int lane = WLANE, x0 = v.a;
+    int x = x0;
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            int y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
-        }
-        if (i < n) c[i] = carry + x - v;
-        carry += __shfl(x, 63, 64);
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
     }
-    WSYNC();
-    return carry;
+    v.a = x - x0;
+    return __shfl(x, 63, 64);
 #endif
 }
 
-// Smallest of the values, with the smallest index among equal values.
+// Exclusive suffix sums (over the lanes to the right) in place; returns the
+// total.
+BTD int lv_rexscan(LV<int> &v)
+{
+#ifdef BT_HOST_DEBUG
+    int acc = 0;
+    for (int l = bt_host_lanes - 1; l >= 0; l--) { const int t = v(l); v(l) = acc; acc += t; }
+    return acc;
+#else
+    const int lane = WLANE, x0 = v.a;
+    int x = x0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_down(x, o, 64);
+        if (lane + o < 64) x += y;
+    }
+    v.a = x - x0;
+    return __shfl(x, 0, 64);
+#endif
+}
+
+// Smallest value, with the smallest index among equal values.
 BTD void argmin_pick(double &h, int &q, double h2, int q2)
 {
     if (h2 < h || (h2 == h && q2 < q)) { h = h2; q = q2; }
 }
 
-// Inclusive suffix minima of the values of h[0..n) with the smallest index
-// attaining each: SM[j] = min_{i >= j} h[i], Q[j] = that index.
-template <typename T>
-BTD void wave_suffix_min(const T *h, double *SM, int *Q, int n)
+// Per-lane (value, index) -> the minimum over the lanes to the right
+// ((+inf, INT_MAX) for the last lane), in place.
+BTD void lv_rexmin(LV<double> &h, LV<int> &q)
 {
 #ifdef BT_HOST_DEBUG
-    for (int j = n - 1; j >= 0; j--) {
-        if (j == n - 1 || val(h[j]) <= SM[j + 1]) { SM[j] = val(h[j]); Q[j] = j; }
-        else { SM[j] = SM[j + 1]; Q[j] = Q[j + 1]; }
+    double ch = __builtin_huge_val();
+    int cq = 0x7fffffff;
+    for (int l = bt_host_lanes - 1; l >= 0; l--) {
+        const double th = h(l);
+        const int tq = q(l);
+        h(l) = ch;
+        q(l) = cq;
+        argmin_pick(ch, cq, th, tq);
     }
 #else
     const int lane = WLANE;
-    double ch = __builtin_huge_val();
-    int cq = 0x7fffffff;
-    for (int base = ((n - 1) / 64) * 64; base >= 0; base -= 64) {
-        const int i = base + lane;
-        double x = i < n ? val(h[i]) : __builtin_huge_val();
-        int qi = i < n ? i : 0x7fffffff;
+    double x = h.a;
+    int qi = q.a;
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            double y = __shfl_down(x, o, 64);
-            int qy = __shfl_down(qi, o, 64);
-            if (lane + o < 64) argmin_pick(x, qi, y, qy);
-        }
-        argmin_pick(x, qi, ch, cq);
-        if (i < n) { SM[i] = x; Q[i] = qi; }
-        ch = __shfl(x, 0, 64);
-        cq = __shfl(qi, 0, 64);
+    for (int o = 1; o < 64; o <<= 1) {
+        const double y = __shfl_down(x, o, 64);
+        const int qy = __shfl_down(qi, o, 64);
+        if (lane + o < 64) argmin_pick(x, qi, y, qy);
     }
-    WSYNC();
+    const double xe = __shfl_down(x, 1, 64);
+    const int qe = __shfl_down(qi, 1, 64);
+    h.a = lane < 63 ? xe : __builtin_huge_val();
+    q.a = lane < 63 ? qe : 0x7fffffff;
 #endif
 }
 
-// Smallest value of c[0..n) (all lanes).
-BTD int wave_min_int(const int *c, int n, int init)
+// Per-lane values -> for every lane the value of the lane before it
+// (`fill` for lane 0), in place.
+BTD void lv_up1(LV<double> &v, double fill)
 {
 #ifdef BT_HOST_DEBUG
-    int r = init;
-    for (int i = 0; i < n; i++) r = c[i] < r ? c[i] : r;
+    for (int l = bt_host_lanes - 1; l > 0; l--) v(l) = v(l - 1);
+    v(0) = fill;
+#else
+    const double y = __shfl_up(v.a, 1, 64);
+    v.a = WLANE == 0 ? fill : y;
+#endif
+}
+
+// The value get(src) of lane src, for every lane.
+template <typename T, class G>
+BTD T from_lane(int src, G get)
+{
+#ifdef BT_HOST_DEBUG
+    return get(src);
+#else
+    return shfl_num(get(WLANE), src);
+#endif
+}
+
+// Overall minimum of per-lane integers, or first index of the overall
+// minimum of per-lane (value, index) pairs.
+BTD int lv_min_int(LV<int> &v)
+{
+#ifdef BT_HOST_DEBUG
+    int r = 0x7fffffff;
+    for (int l = 0; l < bt_host_lanes; l++) r = v(l) < r ? v(l) : r;
     return r;
 #else
-    int r = init;
-    PAR_FOR(i, n) r = c[i] < r ? c[i] : r;
+    int r = v.a;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
-        int y = __shfl_xor(r, o, 64);
+        const int y = __shfl_xor(r, o, 64);
         r = y < r ? y : r;
     }
     return r;
 #endif
 }
 
-// #{j : f.X(j) < y}
-template <typename N>
-BTD int lower_count(const View<N> &f, double y)
+BTD int lv_argmin(LV<double> &h, LV<int> &q)
 {
-    int lo = 0, hi = f.m;
+#ifdef BT_HOST_DEBUG
+    double ch = __builtin_huge_val();
+    int cq = 0x7fffffff;
+    for (int l = 0; l < bt_host_lanes; l++) argmin_pick(ch, cq, h(l), q(l));
+    return cq;
+#else
+    double x = h.a;
+    int qi = q.a;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double y = __shfl_xor(x, o, 64);
+        const int qy = __shfl_xor(qi, o, 64);
+        argmin_pick(x, qi, y, qy);
+    }
+    return qi;
+#endif
+}
+
+// ---------------------------------------------------------------------------
+// CANON over an accessor (X(j), V(j), S(j)).
+// ---------------------------------------------------------------------------
+
+// A with values and slopes multiplied by rho (SCALE).
+template <typename N>
+struct ScaleSrc {
+    View<N> A;
+    N rho;
+    BTD N X(int j) const { return A.X(j); }
+    BTD N V(int j) const { return A.V(j) * rho; }
+    BTD N S(int j) const { return A.S(j) * rho; }
+};
+
+// A with its slopes clamped into [a, b] (CLIP, a < b).
+template <typename N>
+struct ClampSrc {
+    View<N> A;
+    N a, b;
+    BTD N X(int j) const { return A.X(j); }
+    BTD N V(int j) const { return A.V(j); }
+    BTD N S(int j) const
+    {
+        const N s = A.S(j);
+        const double sv = val(s);
+        return sv < val(a) ? a : (sv > val(b) ? b : s);
+    }
+};
+
+// The mirror image y -> -y of a stored function with m points.
+template <typename N>
+struct MirSrc {
+    View<N> A;
+    int m;
+    BTD N X(int j) const { return -A.X(m - 1 - j); }
+    BTD N V(int j) const { return A.V(m - 1 - j); }
+    BTD N S(int j) const { return -A.S(m - j); }
+};
+
+// CANON of src (m points) into out; returns the count or -1 on overflow.
+template <typename N, typename SRC>
+BTD int wave_canon(const SRC &src, int m, const Arr<N> &out)
+{
+    constexpr int E = TileE<N>::E;
+    struct Ld {
+        N x[E], v[E], s1[E];
+        double s0[E];
+    };
+    const int tm = NLANES * E;
+    if (out.cap < 1) return -1;
+    int carry = 0;
+    for (int t0 = 0; t0 < m; t0 += tm) {
+        LV<Ld> ld;
+        LV<int> c;
+        LANES(l) {
+            Ld &q = ld(l);
+            const int j0 = t0 + l * E;
+#pragma unroll
+            for (int u = 0; u < E; u++) {
+                const int j = j0 + u;
+                if (j < m) {
+                    q.x[u] = src.X(j);
+                    q.v[u] = src.V(j);
+                    q.s1[u] = src.S(j + 1);
+                    q.s0[u] = val(src.S(j));
+                }
+            }
+            int cc = 0;
+#pragma unroll
+            for (int u = 0; u < E; u++)
+                if (j0 + u < m && q.s0[u] != val(q.s1[u])) cc++;
+            c(l) = cc;
+        }
+        const int tot = lv_exscan(c);
+        if (carry + tot > out.cap) return -1;
+        LANES(l) {
+            const Ld &q = ld(l);
+            const int j0 = t0 + l * E;
+            int p = carry + c(l);
+#pragma unroll
+            for (int u = 0; u < E; u++) {
+                if (j0 + u < m && q.s0[u] != val(q.s1[u])) {
+                    out.X(p) = q.x[u]; out.V(p) = q.v[u]; out.S(p + 1) = q.s1[u];
+                    p++;
+                }
+            }
+        }
+        carry += tot;
+    }
+    if (carry == 0) {
+        LANE0((out.X(0) = src.X(0), out.V(0) = src.V(0), out.S(0) = src.S(0), out.S(1) = src.S(0)));
+        WSYNC();
+        return 1;
+    }
+    LANE0(out.S(0) = src.S(0));
+    WSYNC();
+    return carry;
+}
+
+// ---------------------------------------------------------------------------
+// MERGE(F, G, op) (same result as merge<OP>).
+// ---------------------------------------------------------------------------
+
+// A window of a function's points [base, base + W) (and slopes up to
+// base + W) staged in LDS; indices are those of the whole function.
+template <typename N>
+struct Win {
+    N *x, *v, *s;
+    int base, m;
+    BTD const N &X(int j) const { return x[j - base]; }
+    BTD const N &V(int j) const { return v[j - base]; }
+    BTD const N &S(int j) const { return s[j - base]; }
+};
+
+template <typename N, typename FF>
+BTD Win<N> win_fill(const FF &F, N *buf, int W, int base)
+{
+    Win<N> w{buf, buf + W, buf + 2 * W, base, F.m};
+#ifdef BT_HOST_DEBUG
+    LANES(l) {
+        for (int i = l; i < W; i += NLANES) {
+            const int j = base + i;
+            if (j < F.m) { w.x[i] = F.X(j); w.v[i] = F.V(j); }
+        }
+        for (int i = l; i <= W; i += NLANES) {
+            const int j = base + i;
+            if (j <= F.m) w.s[i] = F.S(j);
+        }
+    }
+#else
+    // W = WaveLds<N>::W here: every load of the window is issued before the
+    // first store to LDS
+    constexpr int K = (WaveLds<N>::W + 1 + 63) / 64;
+    N tx[K], tv[K], ts[K];
+    const int l = WLANE;
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const int i = l + 64 * k, j = base + i;
+        if (i < W && j < F.m) { tx[k] = F.X(j); tv[k] = F.V(j); }
+        if (i <= W && j <= F.m) ts[k] = F.S(j);
+    }
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const int i = l + 64 * k, j = base + i;
+        if (i < W && j < F.m) { w.x[i] = tx[k]; w.v[i] = tv[k]; }
+        if (i <= W && j <= F.m) w.s[i] = ts[k];
+    }
+#endif
+    WSYNC();
+    return w;
+}
+
+// Number of F elements among the first d of the merged order, searched in
+// [lo, hi] (a bracket known to hold it).
+template <typename FF, typename GG>
+BTD int merge_path_in(const FF &F, const GG &G, int d, int lo, int hi)
+{
+    // quaternary steps (three independent probes per round trip), then binary
+    while (hi - lo > 3) {
+        const int w = (hi - lo) >> 2;
+        const int m1 = lo + w, m2 = lo + 2 * w, m3 = lo + 3 * w;
+        const bool p1 = val(F.X(m1)) <= val(G.X(d - m1 - 1));
+        const bool p2 = val(F.X(m2)) <= val(G.X(d - m2 - 1));
+        const bool p3 = val(F.X(m3)) <= val(G.X(d - m3 - 1));
+        if (p3) lo = m3 + 1;
+        else if (p2) { lo = m2 + 1; hi = m3; }
+        else if (p1) { lo = m1 + 1; hi = m2; }
+        else hi = m1;
+    }
     while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (val(f.X(mid)) < y) lo = mid + 1; else hi = mid;
+        const int a = (lo + hi) >> 1;
+        if (val(F.X(a)) <= val(G.X(d - a - 1))) lo = a + 1; else hi = a;
     }
     return lo;
 }
 
-// Broadcast-free single-lane write helper: only lane 0 executes `stmt`.
-#ifdef BT_HOST_DEBUG
-#define LANE0(stmt) do { stmt; } while (0)
-#else
-#define LANE0(stmt) do { if (WLANE == 0) { stmt; } } while (0)
-#endif
-
-// CANON of A (m points) into out; returns the count or -1 on overflow.
-template <typename N>
-BTD int wave_canon(const Arr<N> &A, int m, const Arr<N> &out, WaveTmp &T)
+// Bracket of the merge-path coordinate at d from the one at dt (at): it
+// moves by at most one per merged position.
+BTD void mp_bracket(int d, int dt, int at, int mF, int mG, int &lo, int &hi)
 {
-    const int64_t mark = T.used;
-    int *c = T.ints(m + 1);
-    if (!c) return -1;
-    PAR_FOR(j, m) c[j] = val(A.S(j)) != val(A.S(j + 1)) ? 1 : 0;
-    WSYNC();
-    const int k = wave_scan(c, m);
-    int r;
-    if (k == 0) {
-        if (out.cap < 1) { T.used = mark; return -1; }
-        LANE0((out.X(0) = A.X(0), out.V(0) = A.V(0), out.S(0) = A.S(0), out.S(1) = A.S(0)));
-        r = 1;
+    lo = d - mG > 0 ? d - mG : 0;
+    hi = d < mF ? d : mF;
+    if (d >= dt) {
+        lo = lo > at ? lo : at;
+        hi = hi < at + (d - dt) ? hi : at + (d - dt);
     } else {
-        if (k > out.cap) { T.used = mark; return -1; }
-        PAR_FOR(j, m) {
-            if (val(A.S(j)) != val(A.S(j + 1))) {
-                const int p = c[j];
-                out.X(p) = A.X(j); out.V(p) = A.V(j); out.S(p + 1) = A.S(j + 1);
-            }
-        }
-        LANE0(out.S(0) = A.S(0));
-        r = k;
+        lo = lo > at - (dt - d) ? lo : at - (dt - d);
+        hi = hi < at ? hi : at;
     }
-    WSYNC();
-    T.used = mark;
-    return r;
 }
 
-// MERGE(F, G, op) into out (same result as merge<OP>).
-template <int OP, typename N>
-BTD int wave_merge(const View<N> &F, const View<N> &G, const Arr<N> &out, WaveTmp &T)
+// Walks the merged order from position d0 - 2 (lookbehind) producing union
+// points (a G point equal to the F point before it is the same union point);
+// the union points found at merged positions [d0, d1) belong to this lane.
+// (dt, at): a merged position and its merge-path coordinate, for the
+// bracket of the starting search.  The points they emit (at most two per
+// union point) go to the lane's staging slots sx/sv/ss[k * stride]; returns
+// their number.
+template <int OP, typename N, typename FF, typename GG>
+BTD int merge_lane(const FF &F, const GG &G, double psl0, int d0, int d1, int dt, int at, N *sx, N *sv,
+                   N *ss, int stride)
 {
-    const int mF = F.m, mG = G.m;
-    const int64_t mark = T.used;
-    int *dup = T.ints(mG + 1);
-    int *rF = T.ints(mG);
-    if (!dup || !rF) return -1;
-    PAR_FOR(b, mG) {
-        const double xb = val(G.X(b));
-        const int r = lower_count(F, xb);
-        rF[b] = r;
-        dup[b] = (r < mF && val(F.X(r)) == xb) ? 1 : 0;
-    }
-    WSYNC();
-    const int ndup = wave_scan(dup, mG);
-    const int K = mF + mG - ndup;
-    N *P = T.nums<N>(K), *fF = T.nums<N>(K), *fG = T.nums<N>(K);
-    int *IF = T.ints(K), *IG = T.ints(K);
-    N *rs = T.nums<N>(K), *cy = T.nums<N>(K), *cv = T.nums<N>(K), *crs = T.nums<N>(K);
-    int *hc = T.ints(K), *cnt = T.ints(K + 1);
-    if (!P || !fF || !fG || !IF || !IG || !rs || !cy || !cv || !crs || !hc || !cnt) { T.used = mark; return -1; }
-    // dup[] is now the exclusive count of duplicated G points before b;
-    // G[b] itself is a duplicate when dup[b+1] > dup[b] (dup[mG] = ndup).
-    LANE0(dup[mG] = ndup);
-    WSYNC();
-    PAR_FOR(a, mF) {
-        const double xa = val(F.X(a));
-        const int r = lower_count(G, xa);
-        const bool eq = r < mG && val(G.X(r)) == xa;
-        const int k = a + r - dup[r];
-        P[k] = F.X(a); IF[k] = a + 1; IG[k] = r + (eq ? 1 : 0);
-    }
-    PAR_FOR(b, mG) {
-        if (dup[b + 1] == dup[b]) {
-            const int k = b - dup[b] + rF[b];
-            P[k] = G.X(b); IF[k] = rF[b]; IG[k] = b + 1;
+    if (d0 >= d1) return 0;
+    const int mF = F.m, mG = G.m, Lt = mF + mG;
+    const int ds = d0 >= 2 ? d0 - 2 : 0;
+    int lo, hi;
+    mp_bracket(ds, dt, at, mF, mG, lo, hi);
+    int a = merge_path_in(F, G, ds, lo, hi);
+    int b = ds - a;
+    int d = ds;
+    // the union point waiting for its successor: abscissa, point counts,
+    // values and merged position
+    N cP = mk<N>(0.0), cfF = mk<N>(0.0), cfG = mk<N>(0.0);
+    int ciF = 0, ciG = 0, cpos = -1;
+    bool have = false;
+    // slope arriving at the waiting point (the left tail's for the first
+    // union point; walks that start later skip their first point)
+    double psl = psl0;
+    int cnt = 0;
+    for (;;) {
+        bool nxt = false;
+        N nP = mk<N>(0.0);
+        int niF = 0, niG = 0, npos = 0;
+        while (d < Lt) {
+            const int pos = d;
+            if (a < mF && (b >= mG || val(F.X(a)) <= val(G.X(b)))) {
+                nP = F.X(a);
+                a++; d++;
+                niF = a;
+                niG = b + ((b < mG && val(G.X(b)) == val(nP)) ? 1 : 0);
+                npos = pos;
+                nxt = true;
+                break;
+            }
+            const N xg = G.X(b);
+            const bool dup = a > 0 && val(F.X(a - 1)) == val(xg);
+            b++; d++;
+            if (dup) continue;
+            nP = xg;
+            niF = a;
+            niG = b;
+            npos = pos;
+            nxt = true;
+            break;
         }
-    }
-    WSYNC();
-    PAR_FOR(k, K) {
-        fF[k] = eval_at<N>(F, IF[k], P[k]);
-        fG[k] = eval_at<N>(G, IG[k], P[k]);
-    }
-    WSYNC();
-    PAR_FOR(k, K) {
+        if (!have) {
+            if (!nxt) break;
+            cP = nP; ciF = niF; ciG = niG; cpos = npos;
+            cfF = eval_at<N>(F, ciF, cP);
+            cfG = eval_at<N>(G, ciG, cP);
+            have = true;
+            continue;
+        }
         Slot<N> o;
-        if (k < K - 1) o = slot_interval<OP, N>(F, G, P[k], IF[k], IG[k], fF[k], fG[k], P[k + 1],
-                                               val(fF[k + 1]) - val(fG[k + 1]));
-        else o = slot_right<OP, N>(F, G, P[k], fF[k], fG[k]);
-        rs[k] = o.rs; hc[k] = o.hc ? 1 : 0;
-        if (o.hc) { cy[k] = o.cy; cv[k] = o.cv; crs[k] = o.crs; }
-    }
-    const Slot<N> L = slot_left<OP, N>(F, G, P[0], fF[0], fG[0]);
-    WSYNC();
-    // CANON on the emitted sequence [L crossing], P_0, [c_0], P_1, [c_1], ...
-    PAR_FOR(k, K) {
-        const double sl = k == 0 ? val(L.hc ? L.crs : L.rs) : val(hc[k - 1] ? crs[k - 1] : rs[k - 1]);
-        cnt[k] = (sl != val(rs[k]) ? 1 : 0) + ((hc[k] && val(rs[k]) != val(crs[k])) ? 1 : 0);
-    }
-    WSYNC();
-    const int keepL = (L.hc && val(L.rs) != val(L.crs)) ? 1 : 0;
-    const int tot = wave_scan(cnt, K) + keepL;
-    int r;
-    if (tot > out.cap) {
-        r = -1;
-    } else if (tot == 0) {
-        if (out.cap < 1) r = -1;
-        else {
-            LANE0((out.X(0) = L.hc ? L.cy : P[0], out.V(0) = L.hc ? L.cv : pick<OP, N>(fF[0], fG[0]),
-                   out.S(0) = L.rs, out.S(1) = L.rs));
-            r = 1;
+        N nfF = mk<N>(0.0), nfG = mk<N>(0.0);
+        if (nxt) {
+            nfF = eval_at<N>(F, niF, nP);
+            nfG = eval_at<N>(G, niG, nP);
+            o = slot_interval<OP, N>(F, G, cP, ciF, ciG, cfF, cfG, nP, val(nfF) - val(nfG));
+        } else {
+            o = slot_right<OP, N>(F, G, cP, cfF, cfG);
         }
-    } else {
-        LANE0(out.S(0) = L.rs);
-        if (keepL) LANE0((out.X(0) = L.cy, out.V(0) = L.cv, out.S(1) = L.crs));
-        PAR_FOR(k, K) {
-            const double sl = k == 0 ? val(L.hc ? L.crs : L.rs) : val(hc[k - 1] ? crs[k - 1] : rs[k - 1]);
-            int p = keepL + cnt[k];
-            if (sl != val(rs[k])) {
-                out.X(p) = P[k]; out.V(p) = pick<OP, N>(fF[k], fG[k]); out.S(p + 1) = rs[k];
-                p++;
+        if (cpos >= d0 && cpos < d1) {
+            if (psl != val(o.rs)) {
+                sx[cnt * stride] = cP; sv[cnt * stride] = pick<OP, N>(cfF, cfG); ss[cnt * stride] = o.rs;
+                cnt++;
             }
-            if (hc[k] && val(rs[k]) != val(crs[k])) { out.X(p) = cy[k]; out.V(p) = cv[k]; out.S(p + 1) = crs[k]; }
+            if (o.hc && val(o.rs) != val(o.crs)) {
+                sx[cnt * stride] = o.cy; sv[cnt * stride] = o.cv; ss[cnt * stride] = o.crs;
+                cnt++;
+            }
         }
-        r = tot;
+        psl = val(o.hc ? o.crs : o.rs);
+        if (!nxt || npos >= d1) break;
+        cP = nP; ciF = niF; ciG = niG; cfF = nfF; cfG = nfG; cpos = npos;
     }
-    WSYNC();
-    T.used = mark;
-    return r;
+    return cnt;
 }
 
-// SCALE by rho from A into B (then CANON into out).
-template <typename N>
-BTD int wave_scale(const Arr<N> &A, int m, const N &rho, const Arr<N> &out, WaveTmp &T)
+// Same result as merge_lane, in three steps so that the latencies of the
+// elements overlap: (1) walk the K = E + 4 merged positions [d0 - 2, d1 + 2)
+// recording for each the point counts (iF, iG) after it and whether it
+// starts a union point and from which list (one load per step: the next
+// abscissa of the list that advanced); (2) evaluate every recorded union
+// point independently; (3) settle intervals and CANON decisions in order.
+template <int OP, int E, typename N, typename FF, typename GG>
+BTD int merge_lane_phased(const FF &F, const GG &G, double psl0, int d0, int d1, int dt, int at, N *sx, N *sv,
+                          N *ss, int stride)
 {
-    const int64_t mark = T.used;
-    Arr<N> B;
-    if (!T.arr<N>(m, &B)) return -1;
-    PAR_FOR(j, m) { B.X(j) = A.X(j); B.V(j) = A.V(j) * rho; }
-    PAR_FOR(j, m + 1) B.S(j) = A.S(j) * rho;
+    constexpr int K = E + 4;
+    if (d0 >= d1) return 0;
+    const int mF = F.m, mG = G.m, Lt = mF + mG;
+    const int ds = d0 >= 2 ? d0 - 2 : 0;
+    const int pe = d1 + 2 < Lt ? d1 + 2 : Lt;
+    int lo, hi;
+    mp_bracket(ds, dt, at, mF, mG, lo, hi);
+    int a = merge_path_in(F, G, ds, lo, hi);
+    int b = ds - a;
+    // the next two abscissae of each list are kept loaded, so a step's load
+    // is needed only two steps later
+    double xa = a < mF ? val(F.X(a)) : 0.0, xb = b < mG ? val(G.X(b)) : 0.0;
+    double xa1 = a + 1 < mF ? val(F.X(a + 1)) : 0.0, xb1 = b + 1 < mG ? val(G.X(b + 1)) : 0.0;
+    double xpf = a > 0 ? val(F.X(a - 1)) : -__builtin_huge_val();
+    int iFk[K], iGk[K], src[K];   // src: 0 none (past the end or a duplicate), 1 F, 2 G
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        src[k] = 0;
+        iFk[k] = 0;
+        iGk[k] = 0;
+        if (ds + k < pe) {
+            if (a < mF && (b >= mG || xa <= xb)) {
+                iFk[k] = a + 1;
+                iGk[k] = b + ((b < mG && xb == xa) ? 1 : 0);
+                src[k] = 1;
+                xpf = xa;
+                a++;
+                xa = xa1;
+                xa1 = a + 1 < mF ? val(F.X(a + 1)) : 0.0;
+            } else {
+                iFk[k] = a;
+                iGk[k] = b + 1;
+                src[k] = xpf == xb ? 0 : 2;
+                b++;
+                xb = xb1;
+                xb1 = b + 1 < mG ? val(G.X(b + 1)) : 0.0;
+            }
+        }
+    }
+    // pieces of F and G at each recorded point, loaded two elements ahead of
+    // their use (before the stores of the element being settled)
+    constexpr int PD = 2;
+    Seg<N> gFk[K], gGk[K];
+#pragma unroll
+    for (int k = 0; k < PD && k < K; k++) {
+        if (src[k] != 0) { gFk[k] = seg_at<N>(F, iFk[k]); gGk[k] = seg_at<N>(G, iGk[k]); }
+    }
+    N cP = mk<N>(0.0), cfF = mk<N>(0.0), cfG = mk<N>(0.0);
+    Seg<N> cgF{}, cgG{};
+    int cpos = -1;
+    bool have = false;
+    double psl = psl0;
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        if (k + PD < K && src[k + PD] != 0) {
+            gFk[k + PD] = seg_at<N>(F, iFk[k + PD]);
+            gGk[k + PD] = seg_at<N>(G, iGk[k + PD]);
+        }
+        if (src[k] != 0) {
+            const N x = src[k] == 1 ? gFk[k].x : gGk[k].x;
+            const N fF = seg_eval<N>(gFk[k], x), fG = seg_eval<N>(gGk[k], x);
+            if (have) {
+                const Slot<N> o = slot_interval_seg<OP, N>(cgF, cgG, cP, cfF, cfG, x, val(fF) - val(fG));
+                if (cpos >= d0 && cpos < d1) {
+                    if (psl != val(o.rs)) {
+                        sx[cnt * stride] = cP; sv[cnt * stride] = pick<OP, N>(cfF, cfG); ss[cnt * stride] = o.rs;
+                        cnt++;
+                    }
+                    if (o.hc && val(o.rs) != val(o.crs)) {
+                        sx[cnt * stride] = o.cy; sv[cnt * stride] = o.cv; ss[cnt * stride] = o.crs;
+                        cnt++;
+                    }
+                }
+                psl = val(o.hc ? o.crs : o.rs);
+            }
+            cP = x; cfF = fF; cfG = fG; cgF = gFk[k]; cgG = gGk[k]; cpos = ds + k;
+            have = true;
+        }
+    }
+    // the last union point of the whole merge has the right tail after it
+    if (have && pe == Lt && cpos >= d0 && cpos < d1) {
+        const Slot<N> o = slot_right<OP, N>(F, G, cP, cfF, cfG);
+        if (psl != val(o.rs)) {
+            sx[cnt * stride] = cP; sv[cnt * stride] = pick<OP, N>(cfF, cfG); ss[cnt * stride] = o.rs;
+            cnt++;
+        }
+        if (o.hc && val(o.rs) != val(o.crs)) {
+            sx[cnt * stride] = o.cy; sv[cnt * stride] = o.cv; ss[cnt * stride] = o.crs;
+            cnt++;
+        }
+    }
+    return cnt;
+}
+
+// Both windows of a tile, every load issued before the first store (double
+// numbers; the dual numbers fill one window after the other).
+template <typename N, typename FF, typename GG>
+BTD void win_fill2(const FF &F, const GG &G, N *buf, int W, int fb, int gb, Win<N> *wf, Win<N> *wg)
+{
+#ifdef BT_HOST_DEBUG
+    *wf = win_fill<N>(F, buf, W, fb);
+    *wg = win_fill<N>(G, buf + 3 * W + 1, W, gb);
+#else
+    if constexpr (sizeof(N) != sizeof(double)) {
+        *wf = win_fill<N>(F, buf, W, fb);
+        *wg = win_fill<N>(G, buf + 3 * W + 1, W, gb);
+    } else {
+        constexpr int KW = (WaveLds<N>::W + 1 + 63) / 64;
+        N *gbuf = buf + 3 * W + 1;
+        *wf = Win<N>{buf, buf + W, buf + 2 * W, fb, F.m};
+        *wg = Win<N>{gbuf, gbuf + W, gbuf + 2 * W, gb, G.m};
+        N fx[KW], fv[KW], fs[KW], gx[KW], gv[KW], gs[KW];
+        const int l = WLANE;
+#pragma unroll
+        for (int k = 0; k < KW; k++) {
+            const int i = l + 64 * k, jf = fb + i, jg = gb + i;
+            if (i < W && jf < F.m) { fx[k] = F.X(jf); fv[k] = F.V(jf); }
+            if (i <= W && jf <= F.m) fs[k] = F.S(jf);
+            if (i < W && jg < G.m) { gx[k] = G.X(jg); gv[k] = G.V(jg); }
+            if (i <= W && jg <= G.m) gs[k] = G.S(jg);
+        }
+#pragma unroll
+        for (int k = 0; k < KW; k++) {
+            const int i = l + 64 * k, jf = fb + i, jg = gb + i;
+            if (i < W && jf < F.m) { wf->x[i] = fx[k]; wf->v[i] = fv[k]; }
+            if (i <= W && jf <= F.m) wf->s[i] = fs[k];
+            if (i < W && jg < G.m) { wg->x[i] = gx[k]; wg->v[i] = gv[k]; }
+            if (i <= W && jg <= G.m) wg->s[i] = gs[k];
+        }
+        WSYNC();
+    }
+#endif
+}
+
+// lds: WaveLds<N>::NUMS numbers of this wave's LDS (in a host build, windows
+// of NLANES E + 9 points and staging of 2 E NLANES slots).
+template <int OP, typename N, typename FF, typename GG>
+BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds)
+{
+    constexpr int E = TileE<N>::E;
+    const int tm = NLANES * E, W = tm + 9;
+    const int mF = F.m, mG = G.m, Lt = mF + mG;
+    if (out.cap < 1) return -1;
+    N P0;
+    int iF0, iG0;
+    {
+        const double xa = val(F.X(0)), xb = val(G.X(0));
+        if (xa < xb) { P0 = F.X(0); iF0 = 1; iG0 = 0; }
+        else if (xb < xa) { P0 = G.X(0); iF0 = 0; iG0 = 1; }
+        else { P0 = F.X(0); iF0 = 1; iG0 = 1; }
+    }
+    const N fF0 = eval_at<N>(F, iF0, P0), fG0 = eval_at<N>(G, iG0, P0);
+    const Slot<N> L = slot_left<OP, N>(F, G, P0, fF0, fG0);
+    const int keepL = (L.hc && val(L.rs) != val(L.crs)) ? 1 : 0;
+    const double psl0 = val(L.hc ? L.crs : L.rs);
+    // staging in LDS after the windows: slot k of lane l at k * NLANES + l
+    const int SZ = 2 * E * NLANES;
+    N *stg = lds + 2 * (3 * W + 1);
+    int at = 0, carry = keepL;
+    for (int dt = 0; dt < Lt; dt += tm) {
+        const int bt = dt - at;
+        WSYNC();   // the previous tile's reads of the windows and staging are done
+        Win<N> wf, wg;
+        win_fill2<N>(F, G, lds, W, at >= 3 ? at - 3 : 0, bt >= 3 ? bt - 3 : 0, &wf, &wg);
+        const int dend = dt + tm < Lt ? dt + tm : Lt;
+        LV<int> c, own;
+        LANES(l) {
+            const int d0 = dt + l * E;
+            const int d1 = d0 + E < dend ? d0 + E : dend;
+            if constexpr (sizeof(N) == sizeof(double))
+                own(l) = c(l) = merge_lane_phased<OP, E, N>(wf, wg, psl0, d0, d1, dt, at, stg + l, stg + SZ + l,
+                                                            stg + 2 * SZ + l, NLANES);
+            else
+                own(l) = c(l) = merge_lane<OP, N>(wf, wg, psl0, d0, d1, dt, at, stg + l, stg + SZ + l,
+                                                 stg + 2 * SZ + l, NLANES);
+        }
+        const int tot = lv_exscan(c);
+        if (carry + tot > out.cap) return -1;
+        LANES(l) {
+            const int p = carry + c(l), n = own(l);
+#pragma unroll
+            for (int k = 0; k < 2 * E; k++) {
+                if (k < n) {
+                    const int q = k * NLANES + l;
+                    out.X(p + k) = stg[q]; out.V(p + k) = stg[SZ + q]; out.S(p + k + 1) = stg[2 * SZ + q];
+                }
+            }
+        }
+        carry += tot;
+        if (dend < Lt) {
+            int lo, hi;
+            mp_bracket(dend, dt, at, mF, mG, lo, hi);
+            at = merge_path_in(wf, wg, dend, lo, hi);
+        }
+    }
+    if (carry == 0) {
+        LANE0((out.X(0) = L.hc ? L.cy : P0, out.V(0) = L.hc ? L.cv : pick<OP, N>(fF0, fG0),
+               out.S(0) = L.rs, out.S(1) = L.rs));
+        WSYNC();
+        return 1;
+    }
+    LANE0(out.S(0) = L.rs);
+    if (keepL) LANE0((out.X(0) = L.cy, out.V(0) = L.cv, out.S(1) = L.crs));
     WSYNC();
-    const int r = wave_canon(B, m, out, T);
-    T.used = mark;
-    return r;
+    return carry;
+}
+
+// SCALE by rho from A into out (then CANON).
+template <typename N>
+BTD int wave_scale(const Arr<N> &A, int m, const N &rho, const Arr<N> &out)
+{
+    return wave_canon<N>(ScaleSrc<N>{A.view(m), rho}, m, out);
 }
 
 // CLIP(A, a, b) into out (seller).
 template <typename N>
-BTD int wave_clip(const Arr<N> &A, int m, const N &a, const N &b, const Arr<N> &out, WaveTmp &T)
+BTD int wave_clip(const Arr<N> &A, int m, const N &a, const N &b, const Arr<N> &out)
 {
-    const int64_t mark = T.used;
     if (val(a) == val(b)) {
-        int *c = T.ints(m + 1);
-        if (!c || out.cap < 1) { T.used = mark; return -1; }
-        PAR_FOR(j, m + 1) c[j] = val(A.S(j)) >= val(a) ? j : m + 1;
-        WSYNC();
-        const int i0 = wave_min_int(c, m + 1, m + 1);
+        if (out.cap < 1) return -1;
+        // i0 = min{j in [0, m] : s[j] >= a}
+        LV<int> f;
+        LANES(l) {
+            int r = m + 1;
+            for (int j = l; j <= m; j += NLANES)
+                if (val(A.S(j)) >= val(a)) { r = j; break; }
+            f(l) = r;
+        }
+        const int i0 = lv_min_int(f);
         int q = i0 - 1;
         if (q < 0) q = 0;
         if (q > m - 1) q = m - 1;
         LANE0((out.X(0) = A.X(q), out.V(0) = A.V(q), out.S(0) = a, out.S(1) = a));
         WSYNC();
-        T.used = mark;
         return 1;
     }
-    PAR_FOR(j, m + 1) {
-        const double s = val(A.S(j));
-        if (s < val(a)) A.S(j) = a;
-        else if (s > val(b)) A.S(j) = b;
-    }
-    WSYNC();
-    return wave_canon(A, m, out, T);
+    return wave_canon<N>(ClampSrc<N>{A.view(m), a, b}, m, out);
 }
 
-// The buying half of ENV (same definition as sweep_a) into out.
+// ---------------------------------------------------------------------------
+// The buying half of ENV (same definition as sweep_a).
+// h_j = V_j - a X_j; SM_j, Q_j = the minimum of h over i >= j and the
+// smallest index attaining it.  Piece j (j < m - 1) leaves x_j with slope
+// s_{j+1} (FOLLOW) or a (FLAT), or splits at y_j (SPLIT: s_{j+1} up to y_j,
+// then a); the last piece keeps the right tail s_m.  The points of piece j
+// depend on the slope arriving at x_j, i.e. on piece j - 1 (a for j = 0).
+// ---------------------------------------------------------------------------
+
+template <typename N>
+struct SweepElem {
+    N rs, y, yv;
+    bool sp;
+};
+
+// Piece j from x_j, v_j, s_{j+1}, x_{j+1} and (SMn, Qn) = (SM_{j+1}, Q_{j+1}).
 template <bool MIR, typename N>
-BTD int wave_sweep_a(const View<N> &F, const N &a, const Arr<N> &out, WaveTmp &T)
+BTD SweepElem<N> sweep_elem(const Src<MIR, N> &f, const N &a, int j, int m, const N &xj, const N &vj,
+                            const N &spj, const N &xj1, double SMn, int Qn)
 {
-    Src<MIR, N> f{F, F.m};
-    const int m = F.m;
-    const int64_t mark = T.used;
-    N *h = T.nums<N>(m), *rs = T.nums<N>(m), *y = T.nums<N>(m), *yv = T.nums<N>(m);
-    double *SM = T.dbl(m);
-    int *Q = T.ints(m), *sp = T.ints(m), *cnt = T.ints(m + 1);
-    if (!h || !SM || !rs || !y || !yv || !Q || !sp || !cnt) { T.used = mark; return -1; }
-    PAR_FOR(j, m) h[j] = f.V(j) - a * f.X(j);
-    WSYNC();
-    wave_suffix_min(h, SM, Q, m);
-    PAR_FOR(j, m) {
-        int kind = 0;
-        if (j == m - 1) {
-            rs[j] = f.S(m);
-        } else {
-            const N spj = f.S(j + 1);
-            const int Qj = Q[j + 1];
-            const N hj = h[j];
-            if (Qj == j + 1) {
-                if (val(spj) >= val(a)) kind = 1;
-            } else if (val(hj) < SM[j + 1] && val(spj) > val(a)) {
-                const N xj = f.X(j);
-                const N yy = xj + (h[Qj] - hj) / (spj - a);
-                if (!(val(yy) < val(f.X(j + 1)))) kind = 1;
-                else if (val(yy) > val(xj)) {
-                    kind = 2;
-                    y[j] = yy;
-                    yv[j] = f.V(Qj) + a * (yy - f.X(Qj));
+    SweepElem<N> e;
+    e.sp = false;
+    e.y = mk<N>(0.0);
+    e.yv = mk<N>(0.0);
+    if (j == m - 1) {
+        e.rs = spj;
+        return e;
+    }
+    int kind = 0;
+    const N hj = vj - a * xj;
+    if (Qn == j + 1) {
+        if (val(spj) >= val(a)) kind = 1;
+    } else if (val(hj) < SMn && val(spj) > val(a)) {
+        const N xq = f.X(Qn), vq = f.V(Qn);
+        const N hq = vq - a * xq;
+        const N yy = xj + (hq - hj) / (spj - a);
+        if (!(val(yy) < val(xj1))) {
+            kind = 1;
+        } else if (val(yy) > val(xj)) {
+            kind = 2;
+            e.y = yy;
+            e.yv = vq + a * (yy - xq);
+        }
+    }
+    e.rs = kind != 0 ? spj : a;
+    e.sp = kind == 2;
+    return e;
+}
+
+// Writes the buying half of ENV of F into out, packed against the right end
+// of the buffer: the result is at offset *off (points [*off, *off + count),
+// slopes [*off, *off + count]).  Returns the count or -1 on overflow.
+template <bool MIR, typename N>
+BTD int wave_sweep_a(const View<N> &F, const N &a, const Arr<N> &out, int *off)
+{
+    constexpr int E = TileE<N>::E;
+    struct St {
+        N x[E], v[E], s1[E], x1[E], rs[E], y[E], yv[E];
+        double h[E];
+        bool sp[E];
+    };
+    const Src<MIR, N> f{F, F.m};
+    const int m = F.m, tm = NLANES * E, cap = out.cap;
+    const double av = val(a);
+    if (cap < 1) return -1;
+    // minimum of h over the tiles already done, on the right
+    double SMc = __builtin_huge_val();
+    int Qc = 0x7fffffff;
+    // the first piece of the tile on the right, settled by the next tile
+    bool havep = false, p_sp = false;
+    N p_x = mk<N>(0.0), p_v = mk<N>(0.0), p_rs = mk<N>(0.0), p_y = mk<N>(0.0), p_yv = mk<N>(0.0);
+    int rc = 0;   // points written so far, from the right end
+    for (int t1 = m; t1 > 0; t1 -= tm) {
+        const int t0 = t1 - tm > 0 ? t1 - tm : 0;
+        LV<St> st;
+        LV<double> hm;
+        LV<int> qm;
+        LANES(l) {
+            St &q = st(l);
+            const int j0 = t0 + l * E;
+#pragma unroll
+            for (int u = 0; u < E; u++) {
+                const int j = j0 + u;
+                if (j < t1) {
+                    q.x[u] = f.X(j);
+                    q.v[u] = f.V(j);
+                    q.s1[u] = f.S(j + 1);
+                    q.x1[u] = j + 1 < m ? f.X(j + 1) : mk<N>(0.0);
                 }
             }
-            rs[j] = kind != 0 ? spj : a;
+            double hmin = __builtin_huge_val();
+            int qmin = 0x7fffffff;
+#pragma unroll
+            for (int u = E - 1; u >= 0; u--) {
+                const int j = j0 + u;
+                if (j < t1) {
+                    q.h[u] = val(q.v[u] - a * q.x[u]);
+                    if (q.h[u] <= hmin) { hmin = q.h[u]; qmin = j; }
+                }
+            }
+            hm(l) = hmin;
+            qm(l) = qmin;
         }
-        sp[j] = kind == 2 ? 1 : 0;
-    }
-    WSYNC();
-    // CANON of x_0, [y_0], x_1, ... with left tail a; y_j leaves with a
-    const double av = val(a);
-    PAR_FOR(j, m) {
-        const double sl = j == 0 ? av : (sp[j - 1] ? av : val(rs[j - 1]));
-        cnt[j] = (sl != val(rs[j]) ? 1 : 0) + ((sp[j] && val(rs[j]) != av) ? 1 : 0);
-    }
-    WSYNC();
-    const int tot = wave_scan(cnt, m);
-    int r;
-    if (tot > out.cap || out.cap < 1) {
-        r = -1;
-    } else if (tot == 0) {
-        LANE0((out.X(0) = f.X(0), out.V(0) = f.V(0), out.S(0) = a, out.S(1) = a));
-        r = 1;
-    } else {
-        LANE0(out.S(0) = a);
-        PAR_FOR(j, m) {
-            const double sl = j == 0 ? av : (sp[j - 1] ? av : val(rs[j - 1]));
-            int p = cnt[j];
-            if (sl != val(rs[j])) { out.X(p) = f.X(j); out.V(p) = f.V(j); out.S(p + 1) = rs[j]; p++; }
-            if (sp[j] && val(rs[j]) != av) { out.X(p) = y[j]; out.V(p) = yv[j]; out.S(p + 1) = a; }
+        lv_rexmin(hm, qm);
+        LV<double> lastc;
+        LANES(l) {
+            St &q = st(l);
+            const int j0 = t0 + l * E;
+            double SM = hm(l);
+            int Q = qm(l);
+            argmin_pick(SM, Q, SMc, Qc);
+            double lc = av;
+#pragma unroll
+            for (int u = E - 1; u >= 0; u--) {
+                const int j = j0 + u;
+                if (j < t1) {
+                    const SweepElem<N> e = sweep_elem<MIR, N>(f, a, j, m, q.x[u], q.v[u], q.s1[u], q.x1[u], SM, Q);
+                    q.rs[u] = e.rs; q.y[u] = e.y; q.yv[u] = e.yv; q.sp[u] = e.sp;
+                    if (q.h[u] <= SM) { SM = q.h[u]; Q = j; }
+                }
+            }
+            // what the lane's last piece leaves to its right neighbour
+#pragma unroll
+            for (int u = 0; u < E; u++)
+                if (j0 + u < t1) lc = q.sp[u] ? av : val(q.rs[u]);
+            lastc(l) = lc;
+            hm(l) = SM;
+            qm(l) = Q;
         }
-        r = tot;
+        // minimum over i >= t0 (lane 0 holds element t0)
+        const double SMn = from_lane<double>(0, [&](int l) { return hm(l); });
+        const int Qn = from_lane<int>(0, [&](int l) { return qm(l); });
+        // the pending piece t1 settles with the contribution of piece t1 - 1
+        const int lt = (t1 - 1 - t0) / E;
+        const double cl = from_lane<double>(lt, [&](int l) { return lastc(l); });
+        int pc1 = 0, pc2 = 0;
+        if (havep) {
+            pc1 = cl != val(p_rs) ? 1 : 0;
+            pc2 = (p_sp && val(p_rs) != av) ? 1 : 0;
+        }
+        lv_up1(lastc, av);
+        LV<int> c;
+        LANES(l) {
+            const St &q = st(l);
+            const int j0 = t0 + l * E;
+            int cc = 0;
+#pragma unroll
+            for (int u = 0; u < E; u++) {
+                const int j = j0 + u;
+                if (j < t1 && !(j == t0 && t0 > 0)) {
+                    const double sl = j == 0 ? av : (u == 0 ? lastc(l) : (q.sp[u - 1] ? av : val(q.rs[u - 1])));
+                    cc += (sl != val(q.rs[u]) ? 1 : 0) + ((q.sp[u] && val(q.rs[u]) != av) ? 1 : 0);
+                }
+            }
+            c(l) = cc;
+        }
+        const int tot = lv_rexscan(c);
+        if (rc + pc1 + pc2 + tot > cap) return -1;
+        if (havep) {
+            LANE0({
+                int s = cap - (rc + pc1 + pc2);
+                if (pc1) { out.X(s) = p_x; out.V(s) = p_v; out.S(s + 1) = p_rs; s++; }
+                if (pc2) { out.X(s) = p_y; out.V(s) = p_yv; out.S(s + 1) = a; }
+            });
+        }
+        LANES(l) {
+            const St &q = st(l);
+            const int j0 = t0 + l * E;
+            int r = rc + pc1 + pc2 + c(l);   // points to the right of this lane's
+#pragma unroll
+            for (int u = E - 1; u >= 0; u--) {
+                const int j = j0 + u;
+                if (j < t1 && !(j == t0 && t0 > 0)) {
+                    const double sl = j == 0 ? av : (u == 0 ? lastc(l) : (q.sp[u - 1] ? av : val(q.rs[u - 1])));
+                    const int c1 = sl != val(q.rs[u]) ? 1 : 0;
+                    const int c2 = (q.sp[u] && val(q.rs[u]) != av) ? 1 : 0;
+                    r += c1 + c2;
+                    int s = cap - r;
+                    if (c1) { out.X(s) = q.x[u]; out.V(s) = q.v[u]; out.S(s + 1) = q.rs[u]; s++; }
+                    if (c2) { out.X(s) = q.y[u]; out.V(s) = q.yv[u]; out.S(s + 1) = a; }
+                }
+            }
+        }
+        rc += pc1 + pc2 + tot;
+        SMc = SMn;
+        Qc = Qn;
+        havep = t0 > 0;
+        if (havep) {
+            p_x = from_lane<N>(0, [&](int l) { return st(l).x[0]; });
+            p_v = from_lane<N>(0, [&](int l) { return st(l).v[0]; });
+            p_rs = from_lane<N>(0, [&](int l) { return st(l).rs[0]; });
+            p_y = from_lane<N>(0, [&](int l) { return st(l).y[0]; });
+            p_yv = from_lane<N>(0, [&](int l) { return st(l).yv[0]; });
+            p_sp = from_lane<int>(0, [&](int l) { return st(l).sp[0] ? 1 : 0; }) != 0;
+        }
     }
+    if (rc == 0) {
+        LANE0((out.X(cap - 1) = f.X(0), out.V(cap - 1) = f.V(0), out.S(cap - 1) = a, out.S(cap) = a));
+        *off = cap - 1;
+        WSYNC();
+        return 1;
+    }
+    LANE0(out.S(cap - rc) = a);
+    *off = cap - rc;
     WSYNC();
-    T.used = mark;
-    return r;
+    return rc;
 }
 
 // ENV(F, a, b) into out (buyer).
 template <typename N>
-BTD int wave_env(const Arr<N> &Fa, int m, const N &a, const N &b, const Arr<N> &out, WaveTmp &T)
+BTD int wave_env(const Arr<N> &Fa, int m, const N &a, const N &b, const Arr<N> &out, WaveTmp &T, N *lds)
 {
     const int64_t mark = T.used;
     const View<N> F = Fa.view(m);
     if (val(a) == val(b)) {
-        N *h = T.nums<N>(m);
-        double *SM = T.dbl(m);
-        int *Q = T.ints(m);
-        if (!h || !SM || !Q || out.cap < 1) { T.used = mark; return -1; }
-        PAR_FOR(j, m) h[j] = F.V(j) - a * F.X(j);
-        WSYNC();
-        wave_suffix_min(h, SM, Q, m);
-        const int js = Q[0];
+        if (out.cap < 1) return -1;
+        // the line of slope a through the first minimiser of V_j - a X_j
+        LV<double> h;
+        LV<int> q;
+        LANES(l) {
+            double hb = __builtin_huge_val();
+            int qb = 0x7fffffff;
+            for (int j = l; j < m; j += NLANES) {
+                const double hv = val(F.V(j) - a * F.X(j));
+                if (hv < hb) { hb = hv; qb = j; }
+            }
+            h(l) = hb;
+            q(l) = qb;
+        }
+        const int js = lv_argmin(h, q);
         LANE0((out.X(0) = F.X(js), out.V(0) = F.V(js), out.S(0) = a, out.S(1) = a));
         WSYNC();
-        T.used = mark;
         return 1;
     }
     Arr<N> A, RB, B;
-    if (!T.arr<N>(2 * m, &A) || !T.arr<N>(2 * m, &RB) || !T.arr<N>(2 * m, &B)) { T.used = mark; return -1; }
-    const int ma = wave_sweep_a<false, N>(F, a, A, T);
-    const int mrb = ma < 0 ? -1 : wave_sweep_a<true, N>(F, -b, RB, T);
-    if (ma < 0 || mrb < 0) { T.used = mark; return -1; }
-    // B = mirror(RB), then CANON
-    Arr<N> Bm;
-    if (!T.arr<N>(mrb, &Bm)) { T.used = mark; return -1; }
-    PAR_FOR(j, mrb) { Bm.X(j) = -RB.X(mrb - 1 - j); Bm.V(j) = RB.V(mrb - 1 - j); }
-    PAR_FOR(j, mrb + 1) Bm.S(j) = -RB.S(mrb - j);
-    WSYNC();
-    const int mb = wave_canon(Bm, mrb, B, T);
-    const int mv = mb < 0 ? -1 : wave_merge<OPMIN, N>(A.view(ma), B.view(mb), out, T);
+    if (!T.arr<N>(2 * m, &A) || !T.arr<N>(2 * m, &RB)) { T.used = mark; return -1; }
+    int offA = 0, offR = 0;
+    const int ma = wave_sweep_a<false, N>(F, a, A, &offA);
+    const int mrb = ma < 0 ? -1 : wave_sweep_a<true, N>(F, -b, RB, &offR);
+    if (ma < 0 || mrb < 0 || !T.arr<N>(mrb, &B)) { T.used = mark; return -1; }
+    const View<N> Av{A.x + offA, A.v + offA, A.s + offA, ma, 1};
+    const View<N> Rv{RB.x + offR, RB.v + offR, RB.s + offR, mrb, 1};
+    // B = CANON(mirror image of RB)
+    const int mb = wave_canon<N>(MirSrc<N>{Rv, mrb}, mrb, B);
+    const int mv = mb < 0 ? -1 : wave_merge<OPMIN, N>(Av, B.view(mb), out, lds);
     T.used = mark;
     return mv;
 }
 
 // One node update by a whole wave (see node_update).  The result is left in
-// *zout inside T's slice (valid until T is reset).
+// *zout inside T's slice (valid until T is reset).  lds: this wave's
+// WaveLds<N>::NUMS numbers of LDS.
 template <int SIDE, typename N>
 BTD int wave_node_update(const View<N> &Zu, const View<N> &Zd, const N &S, const N &kt, const N &rho,
-                         const N &xi, const N &zeta, bool exercise, WaveTmp &T, Arr<N> *zout)
+                         const N &xi, const N &zeta, bool exercise, WaveTmp &T, N *lds, Arr<N> *zout)
 {
     const N one = mk<N>(1.0);
     const N a = -((one + kt) * S);
@@ -454,24 +1061,24 @@ BTD int wave_node_update(const View<N> &Zu, const View<N> &Zd, const N &S, const
     const int M = Zu.m + Zd.m;
     Arr<N> W, W2, V;
     if (!T.arr<N>(2 * M + 1, &W)) return -1;
-    int mw = wave_merge<OPMAX, N>(Zu, Zd, W, T);
+    int mw = wave_merge<OPMAX, N>(Zu, Zd, W, lds);
     if (mw < 0 || !T.arr<N>(mw, &W2)) return -1;
-    mw = wave_scale(W, mw, rho, W2, T);
+    mw = wave_scale(W, mw, rho, W2);
     if (mw < 0) return -1;
     int mv;
     if (SIDE == 0) {
         if (!T.arr<N>(mw, &V)) return -1;
-        mv = wave_clip(W2, mw, a, b, V, T);
+        mv = wave_clip(W2, mw, a, b, V);
     } else {
         // the output of ENV is bounded by 8 mw + 1 points but is about mw in
         // practice: try a buffer of 2 mw + 8 first and fall back to the bound
         const int64_t markv = T.used;
         if (!T.arr<N>(2 * mw + 8, &V)) return -1;
-        mv = wave_env(W2, mw, a, b, V, T);
+        mv = wave_env(W2, mw, a, b, V, T, lds);
         if (mv < 0) {
             T.used = markv;
             if (!T.arr<N>(8 * mw + 1, &V)) return -1;
-            mv = wave_env(W2, mw, a, b, V, T);
+            mv = wave_env(W2, mw, a, b, V, T, lds);
         }
     }
     if (mv < 0) return -1;
@@ -480,7 +1087,7 @@ BTD int wave_node_update(const View<N> &Zu, const View<N> &Zd, const N &S, const
     if (!T.arr<N>(1, &U) || !T.arr<N>(2 * mv + 3, &Z)) return -1;
     LANE0((U.X(0) = SIDE == 0 ? zeta : -zeta, U.V(0) = SIDE == 0 ? xi : -xi, U.S(0) = a, U.S(1) = b));
     WSYNC();
-    const int mz = wave_merge<SIDE == 0 ? OPMAX : OPMIN, N>(U.view(1), V.view(mv), Z, T);
+    const int mz = wave_merge<SIDE == 0 ? OPMAX : OPMIN, N>(U.view(1), V.view(mv), Z, lds);
     *zout = Z;
     return mz;
 }
