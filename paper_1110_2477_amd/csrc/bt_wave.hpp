@@ -549,37 +549,53 @@ BTD int merge_lane(const FF &F, const GG &G, double psl0, int d0, int d1, int dt
     return cnt;
 }
 
-// Same result as merge_lane, in three steps so that the latencies of the
-// elements overlap: (1) walk the K = E + 4 merged positions [d0 - 2, d1 + 2)
-// recording for each the point counts (iF, iG) after it and whether it
-// starts a union point and from which list (one load per step: the next
-// abscissa of the list that advanced); (2) evaluate every recorded union
-// point independently; (3) settle intervals and CANON decisions in order.
+// The first union point a lane owns, held back until the slope arriving
+// from the lane before is known.
+template <typename N>
+struct LaneFirst {
+    N x, v, rs, cy, cv, crs;
+    bool hc, have;
+};
+
+// Same result as merge_lane without its lookbehind, in three steps so that
+// the latencies of the elements overlap: (1) walk the K = E + 2 merged
+// positions [d0, d1 + 2) recording for each the point counts (iF, iG) after
+// it and whether it starts a union point and from which list (one load per
+// step: the next abscissa of the list that advanced); (2) evaluate every
+// recorded union point independently; (3) settle intervals and CANON
+// decisions in order.  The lane's first union point is returned in *first
+// (its CANON decision needs the slope arriving from the lane before, which
+// the caller passes along); the points after it go to the staging slots;
+// *psl_out is the slope arriving at the first union point after the lane's
+// and *a_end the number of F points among merged positions < d1.
 template <int OP, int E, typename N, typename FF, typename GG>
-BTD int merge_lane_phased(const FF &F, const GG &G, double psl0, int d0, int d1, int dt, int at, N *sx, N *sv,
-                          N *ss, int stride)
+BTD int merge_lane_nlb(const FF &F, const GG &G, int d0, int d1, int dt, int at, N *sx, N *sv, N *ss, int stride,
+                       LaneFirst<N> *first, double *psl_out, int *a_end)
 {
-    constexpr int K = E + 4;
+    constexpr int K = E + 2;
+    first->have = false;
+    *psl_out = 0.0;
+    *a_end = at;
     if (d0 >= d1) return 0;
     const int mF = F.m, mG = G.m, Lt = mF + mG;
-    const int ds = d0 >= 2 ? d0 - 2 : 0;
     const int pe = d1 + 2 < Lt ? d1 + 2 : Lt;
     int lo, hi;
-    mp_bracket(ds, dt, at, mF, mG, lo, hi);
-    int a = merge_path_in(F, G, ds, lo, hi);
-    int b = ds - a;
+    mp_bracket(d0, dt, at, mF, mG, lo, hi);
+    int a = merge_path_in(F, G, d0, lo, hi);
+    int b = d0 - a;
     // the next two abscissae of each list are kept loaded, so a step's load
     // is needed only two steps later
     double xa = a < mF ? val(F.X(a)) : 0.0, xb = b < mG ? val(G.X(b)) : 0.0;
     double xa1 = a + 1 < mF ? val(F.X(a + 1)) : 0.0, xb1 = b + 1 < mG ? val(G.X(b + 1)) : 0.0;
     double xpf = a > 0 ? val(F.X(a - 1)) : -__builtin_huge_val();
     int iFk[K], iGk[K], src[K];   // src: 0 none (past the end or a duplicate), 1 F, 2 G
+    int aend = a;
 #pragma unroll
     for (int k = 0; k < K; k++) {
         src[k] = 0;
         iFk[k] = 0;
         iGk[k] = 0;
-        if (ds + k < pe) {
+        if (d0 + k < pe) {
             if (a < mF && (b >= mG || xa <= xb)) {
                 iFk[k] = a + 1;
                 iGk[k] = b + ((b < mG && xb == xa) ? 1 : 0);
@@ -596,8 +612,10 @@ BTD int merge_lane_phased(const FF &F, const GG &G, double psl0, int d0, int d1,
                 xb = xb1;
                 xb1 = b + 1 < mG ? val(G.X(b + 1)) : 0.0;
             }
+            if (d0 + k == d1 - 1) aend = a;
         }
     }
+    *a_end = aend;
     // pieces of F and G at each recorded point, loaded two elements ahead of
     // their use (before the stores of the element being settled)
     constexpr int PD = 2;
@@ -610,7 +628,7 @@ BTD int merge_lane_phased(const FF &F, const GG &G, double psl0, int d0, int d1,
     Seg<N> cgF{}, cgG{};
     int cpos = -1;
     bool have = false;
-    double psl = psl0;
+    double psl = 0.0;
     int cnt = 0;
 #pragma unroll
     for (int k = 0; k < K; k++) {
@@ -621,9 +639,11 @@ BTD int merge_lane_phased(const FF &F, const GG &G, double psl0, int d0, int d1,
         if (src[k] != 0) {
             const N x = src[k] == 1 ? gFk[k].x : gGk[k].x;
             const N fF = seg_eval<N>(gFk[k], x), fG = seg_eval<N>(gGk[k], x);
-            if (have) {
+            if (have && cpos < d1) {
                 const Slot<N> o = slot_interval_seg<OP, N>(cgF, cgG, cP, cfF, cfG, x, val(fF) - val(fG));
-                if (cpos >= d0 && cpos < d1) {
+                if (!first->have) {
+                    *first = LaneFirst<N>{cP, pick<OP, N>(cfF, cfG), o.rs, o.cy, o.cv, o.crs, o.hc, true};
+                } else {
                     if (psl != val(o.rs)) {
                         sx[cnt * stride] = cP; sv[cnt * stride] = pick<OP, N>(cfF, cfG); ss[cnt * stride] = o.rs;
                         cnt++;
@@ -635,22 +655,28 @@ BTD int merge_lane_phased(const FF &F, const GG &G, double psl0, int d0, int d1,
                 }
                 psl = val(o.hc ? o.crs : o.rs);
             }
-            cP = x; cfF = fF; cfG = fG; cgF = gFk[k]; cgG = gGk[k]; cpos = ds + k;
+            cP = x; cfF = fF; cfG = fG; cgF = gFk[k]; cgG = gGk[k]; cpos = d0 + k;
             have = true;
         }
     }
     // the last union point of the whole merge has the right tail after it
-    if (have && pe == Lt && cpos >= d0 && cpos < d1) {
+    if (have && pe == Lt && cpos < d1) {
         const Slot<N> o = slot_right<OP, N>(F, G, cP, cfF, cfG);
-        if (psl != val(o.rs)) {
-            sx[cnt * stride] = cP; sv[cnt * stride] = pick<OP, N>(cfF, cfG); ss[cnt * stride] = o.rs;
-            cnt++;
+        if (!first->have) {
+            *first = LaneFirst<N>{cP, pick<OP, N>(cfF, cfG), o.rs, o.cy, o.cv, o.crs, o.hc, true};
+        } else {
+            if (psl != val(o.rs)) {
+                sx[cnt * stride] = cP; sv[cnt * stride] = pick<OP, N>(cfF, cfG); ss[cnt * stride] = o.rs;
+                cnt++;
+            }
+            if (o.hc && val(o.rs) != val(o.crs)) {
+                sx[cnt * stride] = o.cy; sv[cnt * stride] = o.cv; ss[cnt * stride] = o.crs;
+                cnt++;
+            }
         }
-        if (o.hc && val(o.rs) != val(o.crs)) {
-            sx[cnt * stride] = o.cy; sv[cnt * stride] = o.cv; ss[cnt * stride] = o.crs;
-            cnt++;
-        }
+        psl = val(o.hc ? o.crs : o.rs);
     }
+    *psl_out = psl;
     return cnt;
 }
 
@@ -715,6 +741,7 @@ BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds)
     const Slot<N> L = slot_left<OP, N>(F, G, P0, fF0, fG0);
     const int keepL = (L.hc && val(L.rs) != val(L.crs)) ? 1 : 0;
     const double psl0 = val(L.hc ? L.crs : L.rs);
+    double psl = psl0;   // slope arriving at the next tile's first union point
     // staging in LDS after the windows: slot k of lane l at k * NLANES + l
     const int SZ = 2 * E * NLANES;
     N *stg = lds + 2 * (3 * W + 1);
@@ -725,34 +752,79 @@ BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds)
         Win<N> wf, wg;
         win_fill2<N>(F, G, lds, W, at >= 3 ? at - 3 : 0, bt >= 3 ? bt - 3 : 0, &wf, &wg);
         const int dend = dt + tm < Lt ? dt + tm : Lt;
-        LV<int> c, own;
-        LANES(l) {
-            const int d0 = dt + l * E;
-            const int d1 = d0 + E < dend ? d0 + E : dend;
-            if constexpr (sizeof(N) == sizeof(double))
-                own(l) = c(l) = merge_lane_phased<OP, E, N>(wf, wg, psl0, d0, d1, dt, at, stg + l, stg + SZ + l,
-                                                            stg + 2 * SZ + l, NLANES);
-            else
-                own(l) = c(l) = merge_lane<OP, N>(wf, wg, psl0, d0, d1, dt, at, stg + l, stg + SZ + l,
-                                                 stg + 2 * SZ + l, NLANES);
-        }
-        const int tot = lv_exscan(c);
-        if (carry + tot > out.cap) return -1;
-        LANES(l) {
-            const int p = carry + c(l), n = own(l);
+        if constexpr (sizeof(N) == sizeof(double)) {
+            LV<int> c, own, aend;
+            LV<double> pso;
+            LV<LaneFirst<N>> fst;
+            LANES(l) {
+                const int d0 = dt + l * E;
+                const int d1 = d0 + E < dend ? d0 + E : dend;
+                double po;
+                int ae;
+                own(l) = merge_lane_nlb<OP, E, N>(wf, wg, d0, d1, dt, at, stg + l, stg + SZ + l, stg + 2 * SZ + l,
+                                                  NLANES, &fst(l), &po, &ae);
+                pso(l) = po;
+                aend(l) = ae;
+            }
+            // the slope arriving at each lane's first union point comes from
+            // the lane before (the tile before, for lane 0)
+            const double pnext = from_lane<double>(NLANES - 1, [&](int l) { return pso(l); });
+            lv_up1(pso, psl);
+            LANES(l) {
+                const LaneFirst<N> &f = fst(l);
+                const int cf = f.have ? (pso(l) != val(f.rs) ? 1 : 0) + ((f.hc && val(f.rs) != val(f.crs)) ? 1 : 0) : 0;
+                c(l) = cf + own(l);
+            }
+            const int tot = lv_exscan(c);
+            if (carry + tot > out.cap) return -1;
+            LANES(l) {
+                const LaneFirst<N> &f = fst(l);
+                int p = carry + c(l);
+                if (f.have) {
+                    if (pso(l) != val(f.rs)) { out.X(p) = f.x; out.V(p) = f.v; out.S(p + 1) = f.rs; p++; }
+                    if (f.hc && val(f.rs) != val(f.crs)) { out.X(p) = f.cy; out.V(p) = f.cv; out.S(p + 1) = f.crs; p++; }
+                }
+                const int n = own(l);
 #pragma unroll
-            for (int k = 0; k < 2 * E; k++) {
-                if (k < n) {
-                    const int q = k * NLANES + l;
-                    out.X(p + k) = stg[q]; out.V(p + k) = stg[SZ + q]; out.S(p + k + 1) = stg[2 * SZ + q];
+                for (int k = 0; k < 2 * E; k++) {
+                    if (k < n) {
+                        const int q = k * NLANES + l;
+                        out.X(p + k) = stg[q]; out.V(p + k) = stg[SZ + q]; out.S(p + k + 1) = stg[2 * SZ + q];
+                    }
                 }
             }
-        }
-        carry += tot;
-        if (dend < Lt) {
-            int lo, hi;
-            mp_bracket(dend, dt, at, mF, mG, lo, hi);
-            at = merge_path_in(wf, wg, dend, lo, hi);
+            carry += tot;
+            psl = pnext;
+            if (dend < Lt) {
+                // merge-path coordinate at dend: the walk of the lane ending there
+                at = from_lane<int>((dend - dt - 1) / E, [&](int l) { return aend(l); });
+            }
+        } else {
+            LV<int> c, own;
+            LANES(l) {
+                const int d0 = dt + l * E;
+                const int d1 = d0 + E < dend ? d0 + E : dend;
+                own(l) = c(l) = merge_lane<OP, N>(wf, wg, psl0, d0, d1, dt, at, stg + l, stg + SZ + l,
+                                                 stg + 2 * SZ + l, NLANES);
+            }
+            const int tot = lv_exscan(c);
+            if (carry + tot > out.cap) return -1;
+            LANES(l) {
+                const int p = carry + c(l), n = own(l);
+#pragma unroll
+                for (int k = 0; k < 2 * E; k++) {
+                    if (k < n) {
+                        const int q = k * NLANES + l;
+                        out.X(p + k) = stg[q]; out.V(p + k) = stg[SZ + q]; out.S(p + k + 1) = stg[2 * SZ + q];
+                    }
+                }
+            }
+            carry += tot;
+            if (dend < Lt) {
+                int lo, hi;
+                mp_bracket(dend, dt, at, mF, mG, lo, hi);
+                at = merge_path_in(wf, wg, dend, lo, hi);
+            }
         }
     }
     if (carry == 0) {
