@@ -839,6 +839,58 @@ BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds)
     return carry;
 }
 
+// MERGE(F, G, op) of a one-point F when G is strictly better than F at
+// every union point (G's points and F's point) and both tails stay with G
+// without a crossing (the decisions slot_left and slot_right would take).
+// Then every interval keeps G's slope, F's point is dropped by CANON unless
+// it equals a point of G (whose abscissa the merge then takes from F), and
+// the output is G's points with the values the merge evaluates.  The pass
+// writes that output into out while it checks the conditions; it returns
+// the count, or -1 when a condition fails (out is then to be overwritten by
+// the full merge).  A line G is left to the full merge.
+template <int OP, typename N>
+BTD int wave_merge_point(const View<N> &F, const View<N> &G, const Arr<N> &out)
+{
+    const int m = G.m;
+    if (out.cap < m || (m == 1 && val(G.S(0)) == val(G.S(1)))) return -1;
+    const double sF0 = val(F.S(0)), sG0 = val(G.S(0)), sF1 = val(F.S(1)), sGm = val(G.S(m));
+    const bool tails = OP == OPMAX ? (sF0 >= sG0 && sF1 <= sGm) : (sF0 <= sG0 && sF1 >= sGm);
+    if (!tails) return -1;
+    const N xF = F.X(0);
+    const double xf = val(xF);
+    LV<int> bad;
+    LANES(l) {
+        int nb = 0;
+#pragma unroll 4
+        for (int j = l; j < m; j += NLANES) {
+            const N xj = G.X(j);
+            const bool dup = val(xj) == xf;
+            const N P = dup ? xF : xj;
+            // union point P: #{F points <= P} = [P >= x_F], #{G points <= P} = j + 1
+            const N fF = eval_at<N>(F, val(P) >= xf ? 1 : 0, P);
+            const N fG = eval_at<N>(G, j + 1, P);
+            if (better<OP>(val(fF) - val(fG)) != PG) nb++;
+            out.X(j) = P;
+            out.V(j) = fG;
+            out.S(j + 1) = G.S(j + 1);
+            // F's point inside G's piece after x_j
+            if (val(xj) < xf && (j + 1 == m || val(G.X(j + 1)) > xf)) {
+                const N gF = eval_at<N>(F, 1, xF), gG = eval_at<N>(G, j + 1, xF);
+                if (better<OP>(val(gF) - val(gG)) != PG) nb++;
+            }
+        }
+        // F's point before every point of G
+        if (l == 0 && xf < val(G.X(0))) {
+            const N gF = eval_at<N>(F, 1, xF), gG = eval_at<N>(G, 0, xF);
+            if (better<OP>(val(gF) - val(gG)) != PG) nb++;
+        }
+        bad(l) = nb;
+    }
+    LANE0(out.S(0) = G.S(0));
+    WSYNC();
+    return lv_exscan(bad) == 0 ? m : -1;
+}
+
 // SCALE by rho from A into out (then CANON).
 template <typename N>
 BTD int wave_scale(const Arr<N> &A, int m, const N &rho, const Arr<N> &out)
@@ -1159,7 +1211,9 @@ BTD int wave_node_update(const View<N> &Zu, const View<N> &Zd, const N &S, const
     if (!T.arr<N>(1, &U) || !T.arr<N>(2 * mv + 3, &Z)) return -1;
     LANE0((U.X(0) = SIDE == 0 ? zeta : -zeta, U.V(0) = SIDE == 0 ? xi : -xi, U.S(0) = a, U.S(1) = b));
     WSYNC();
-    const int mz = wave_merge<SIDE == 0 ? OPMAX : OPMIN, N>(U.view(1), V.view(mv), Z, lds);
+    // no exercise at or near this node: the merge keeps V's points
+    int mz = wave_merge_point<SIDE == 0 ? OPMAX : OPMIN, N>(U.view(1), V.view(mv), Z);
+    if (mz < 0) mz = wave_merge<SIDE == 0 ? OPMAX : OPMIN, N>(U.view(1), V.view(mv), Z, lds);
     *zout = Z;
     return mz;
 }
