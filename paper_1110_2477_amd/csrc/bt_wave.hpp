@@ -557,57 +557,54 @@ struct LaneFirst {
     bool hc, have;
 };
 
-// Same result as merge_lane without its lookbehind, in three steps so that
-// the latencies of the elements overlap: (1) walk the K = E + 2 merged
-// positions [d0, d1 + 2) recording for each the point counts (iF, iG) after
-// it and whether it starts a union point and from which list (one load per
-// step: the next abscissa of the list that advanced); (2) evaluate every
-// recorded union point independently; (3) settle intervals and CANON
-// decisions in order.  The lane's first union point is returned in *first
-// (its CANON decision needs the slope arriving from the lane before, which
-// the caller passes along); the points after it go to the staging slots;
-// *psl_out is the slope arriving at the first union point after the lane's
-// and *a_end the number of F points among merged positions < d1.
-template <int OP, int E, typename N, typename FF, typename GG>
-BTD int merge_lane_nlb(const FF &F, const GG &G, int d0, int d1, int dt, int at, N *sx, N *sv, N *ss, int stride,
-                       LaneFirst<N> *first, double *psl_out, int *a_end)
+// The decisions of a lane's walk over its K = E + 2 merged positions
+// [d0, d1 + 2): the point counts after each position and whether it starts
+// a union point and from which list (0 none: past the end or a duplicate;
+// 1 F; 2 G); aend = the number of F points among positions < d1.
+template <int E>
+struct LaneWalk {
+    int iF[E + 2], iG[E + 2], src[E + 2];
+    int d0, d1, pe, aend;
+};
+
+// First step of merge_lane without its lookbehind: walk the merged order
+// (one load per step: the next abscissa of the list that advanced, kept two
+// steps ahead).
+template <int E, typename FF, typename GG>
+BTD void merge_walk(const FF &F, const GG &G, int d0, int d1, int dt, int at, LaneWalk<E> &w)
 {
     constexpr int K = E + 2;
-    first->have = false;
-    *psl_out = 0.0;
-    *a_end = at;
-    if (d0 >= d1) return 0;
+    w.d0 = d0;
+    w.d1 = d1;
+    w.aend = at;
+#pragma unroll
+    for (int k = 0; k < K; k++) { w.src[k] = 0; w.iF[k] = 0; w.iG[k] = 0; }
     const int mF = F.m, mG = G.m, Lt = mF + mG;
-    const int pe = d1 + 2 < Lt ? d1 + 2 : Lt;
+    w.pe = d1 + 2 < Lt ? d1 + 2 : Lt;
+    if (d0 >= d1) return;
     int lo, hi;
     mp_bracket(d0, dt, at, mF, mG, lo, hi);
     int a = merge_path_in(F, G, d0, lo, hi);
     int b = d0 - a;
-    // the next two abscissae of each list are kept loaded, so a step's load
-    // is needed only two steps later
     double xa = a < mF ? val(F.X(a)) : 0.0, xb = b < mG ? val(G.X(b)) : 0.0;
     double xa1 = a + 1 < mF ? val(F.X(a + 1)) : 0.0, xb1 = b + 1 < mG ? val(G.X(b + 1)) : 0.0;
     double xpf = a > 0 ? val(F.X(a - 1)) : -__builtin_huge_val();
-    int iFk[K], iGk[K], src[K];   // src: 0 none (past the end or a duplicate), 1 F, 2 G
     int aend = a;
 #pragma unroll
     for (int k = 0; k < K; k++) {
-        src[k] = 0;
-        iFk[k] = 0;
-        iGk[k] = 0;
-        if (d0 + k < pe) {
+        if (d0 + k < w.pe) {
             if (a < mF && (b >= mG || xa <= xb)) {
-                iFk[k] = a + 1;
-                iGk[k] = b + ((b < mG && xb == xa) ? 1 : 0);
-                src[k] = 1;
+                w.iF[k] = a + 1;
+                w.iG[k] = b + ((b < mG && xb == xa) ? 1 : 0);
+                w.src[k] = 1;
                 xpf = xa;
                 a++;
                 xa = xa1;
                 xa1 = a + 1 < mF ? val(F.X(a + 1)) : 0.0;
             } else {
-                iFk[k] = a;
-                iGk[k] = b + 1;
-                src[k] = xpf == xb ? 0 : 2;
+                w.iF[k] = a;
+                w.iG[k] = b + 1;
+                w.src[k] = xpf == xb ? 0 : 2;
                 b++;
                 xb = xb1;
                 xb1 = b + 1 < mG ? val(G.X(b + 1)) : 0.0;
@@ -615,14 +612,31 @@ BTD int merge_lane_nlb(const FF &F, const GG &G, int d0, int d1, int dt, int at,
             if (d0 + k == d1 - 1) aend = a;
         }
     }
-    *a_end = aend;
-    // pieces of F and G at each recorded point, loaded two elements ahead of
-    // their use (before the stores of the element being settled)
+    w.aend = aend;
+}
+
+
+// Second step: evaluate every recorded union point (the pieces of F and G
+// loaded two elements ahead of their use) and settle intervals and CANON
+// decisions in order.  Same result as merge_lane for the union points at
+// positions [d0, d1): the first one is returned in *first (its CANON
+// decision needs the slope arriving from the lane before), the points after
+// it go to the staging slots; *psl_out is the slope arriving at the first
+// union point after the lane's.  Returns the number of staged points.
+template <int OP, int E, typename N, typename FF, typename GG>
+BTD int merge_settle(const FF &F, const GG &G, const LaneWalk<E> &w, N *sx, N *sv, N *ss, int stride,
+                     LaneFirst<N> *first, double *psl_out)
+{
+    constexpr int K = E + 2;
+    first->have = false;
+    *psl_out = 0.0;
+    const int d0 = w.d0, d1 = w.d1, pe = w.pe, Lt = F.m + G.m;
+    if (d0 >= d1) return 0;
     constexpr int PD = 2;
     Seg<N> gFk[K], gGk[K];
 #pragma unroll
     for (int k = 0; k < PD && k < K; k++) {
-        if (src[k] != 0) { gFk[k] = seg_at<N>(F, iFk[k]); gGk[k] = seg_at<N>(G, iGk[k]); }
+        if (w.src[k] != 0) { gFk[k] = seg_at<N>(F, w.iF[k]); gGk[k] = seg_at<N>(G, w.iG[k]); }
     }
     N cP = mk<N>(0.0), cfF = mk<N>(0.0), cfG = mk<N>(0.0);
     Seg<N> cgF{}, cgG{};
@@ -632,12 +646,12 @@ BTD int merge_lane_nlb(const FF &F, const GG &G, int d0, int d1, int dt, int at,
     int cnt = 0;
 #pragma unroll
     for (int k = 0; k < K; k++) {
-        if (k + PD < K && src[k + PD] != 0) {
-            gFk[k + PD] = seg_at<N>(F, iFk[k + PD]);
-            gGk[k + PD] = seg_at<N>(G, iGk[k + PD]);
+        if (k + PD < K && w.src[k + PD] != 0) {
+            gFk[k + PD] = seg_at<N>(F, w.iF[k + PD]);
+            gGk[k + PD] = seg_at<N>(G, w.iG[k + PD]);
         }
-        if (src[k] != 0) {
-            const N x = src[k] == 1 ? gFk[k].x : gGk[k].x;
+        if (w.src[k] != 0) {
+            const N x = w.src[k] == 1 ? gFk[k].x : gGk[k].x;
             const N fF = seg_eval<N>(gFk[k], x), fG = seg_eval<N>(gGk[k], x);
             if (have && cpos < d1) {
                 const Slot<N> o = slot_interval_seg<OP, N>(cgF, cgG, cP, cfF, cfG, x, val(fF) - val(fG));
@@ -679,6 +693,49 @@ BTD int merge_lane_nlb(const FF &F, const GG &G, int d0, int d1, int dt, int at,
     *psl_out = psl;
     return cnt;
 }
+
+#ifndef BT_HOST_DEBUG
+// The windows of a tile held in registers (loads issued early, stores to
+// LDS later).
+template <typename N>
+struct WinRegs {
+    static constexpr int KW = (WaveLds<N>::W + 1 + 63) / 64;
+    N fx[KW], fv[KW], fs[KW], gx[KW], gv[KW], gs[KW];
+    int fb, gb, fm, gm;
+};
+
+template <typename N, typename FF, typename GG>
+__device__ __forceinline__ void win_load(const FF &F, const GG &G, int W, int fb, int gb, WinRegs<N> &r)
+{
+    r.fb = fb; r.gb = gb; r.fm = F.m; r.gm = G.m;
+    const int l = WLANE;
+#pragma unroll
+    for (int k = 0; k < WinRegs<N>::KW; k++) {
+        const int i = l + 64 * k, jf = fb + i, jg = gb + i;
+        if (i < W && jf < F.m) { r.fx[k] = F.X(jf); r.fv[k] = F.V(jf); }
+        if (i <= W && jf <= F.m) r.fs[k] = F.S(jf);
+        if (i < W && jg < G.m) { r.gx[k] = G.X(jg); r.gv[k] = G.V(jg); }
+        if (i <= W && jg <= G.m) r.gs[k] = G.S(jg);
+    }
+}
+
+template <typename N>
+__device__ __forceinline__ void win_store(N *buf, int W, const WinRegs<N> &r, Win<N> *wf, Win<N> *wg)
+{
+    N *gbuf = buf + 3 * W + 1;
+    *wf = Win<N>{buf, buf + W, buf + 2 * W, r.fb, r.fm};
+    *wg = Win<N>{gbuf, gbuf + W, gbuf + 2 * W, r.gb, r.gm};
+    const int l = WLANE;
+#pragma unroll
+    for (int k = 0; k < WinRegs<N>::KW; k++) {
+        const int i = l + 64 * k, jf = r.fb + i, jg = r.gb + i;
+        if (i < W && jf < r.fm) { wf->x[i] = r.fx[k]; wf->v[i] = r.fv[k]; }
+        if (i <= W && jf <= r.fm) wf->s[i] = r.fs[k];
+        if (i < W && jg < r.gm) { wg->x[i] = r.gx[k]; wg->v[i] = r.gv[k]; }
+        if (i <= W && jg <= r.gm) wg->s[i] = r.gs[k];
+    }
+}
+#endif
 
 // Both windows of a tile, every load issued before the first store (double
 // numbers; the dual numbers fill one window after the other).
@@ -742,6 +799,10 @@ BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds)
     const int keepL = (L.hc && val(L.rs) != val(L.crs)) ? 1 : 0;
     const double psl0 = val(L.hc ? L.crs : L.rs);
     double psl = psl0;   // slope arriving at the next tile's first union point
+#ifndef BT_HOST_DEBUG
+    WinRegs<N> pre;      // the next tile's windows (double numbers)
+    bool pre_ok = false;
+#endif
     // staging in LDS after the windows: slot k of lane l at k * NLANES + l
     const int SZ = 2 * E * NLANES;
     N *stg = lds + 2 * (3 * W + 1);
@@ -750,21 +811,40 @@ BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds)
         const int bt = dt - at;
         WSYNC();   // the previous tile's reads of the windows and staging are done
         Win<N> wf, wg;
-        win_fill2<N>(F, G, lds, W, at >= 3 ? at - 3 : 0, bt >= 3 ? bt - 3 : 0, &wf, &wg);
+#ifndef BT_HOST_DEBUG
+        if (pre_ok) {
+            win_store<N>(lds, W, pre, &wf, &wg);
+            WSYNC();
+            pre_ok = false;
+        } else
+#endif
+            win_fill2<N>(F, G, lds, W, at >= 3 ? at - 3 : 0, bt >= 3 ? bt - 3 : 0, &wf, &wg);
         const int dend = dt + tm < Lt ? dt + tm : Lt;
         if constexpr (sizeof(N) == sizeof(double)) {
-            LV<int> c, own, aend;
-            LV<double> pso;
-            LV<LaneFirst<N>> fst;
+            LV<LaneWalk<E>> wk;
             LANES(l) {
                 const int d0 = dt + l * E;
                 const int d1 = d0 + E < dend ? d0 + E : dend;
+                merge_walk<E>(wf, wg, d0, d1, dt, at, wk(l));
+            }
+            // merge-path coordinate at dend: the walk of the lane ending there
+            int at_next = at;
+            if (dend < Lt) {
+                at_next = from_lane<int>((dend - dt - 1) / E, [&](int l) { return wk(l).aend; });
+#ifndef BT_HOST_DEBUG
+                // the next tile's windows, loaded while this tile settles
+                win_load<N>(F, G, W, at_next >= 3 ? at_next - 3 : 0, dend - at_next >= 3 ? dend - at_next - 3 : 0, pre);
+                pre_ok = true;
+#endif
+            }
+            LV<int> c, own;
+            LV<double> pso;
+            LV<LaneFirst<N>> fst;
+            LANES(l) {
                 double po;
-                int ae;
-                own(l) = merge_lane_nlb<OP, E, N>(wf, wg, d0, d1, dt, at, stg + l, stg + SZ + l, stg + 2 * SZ + l,
-                                                  NLANES, &fst(l), &po, &ae);
+                own(l) = merge_settle<OP, E, N>(wf, wg, wk(l), stg + l, stg + SZ + l, stg + 2 * SZ + l, NLANES,
+                                               &fst(l), &po);
                 pso(l) = po;
-                aend(l) = ae;
             }
             // the slope arriving at each lane's first union point comes from
             // the lane before (the tile before, for lane 0)
@@ -795,10 +875,7 @@ BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds)
             }
             carry += tot;
             psl = pnext;
-            if (dend < Lt) {
-                // merge-path coordinate at dend: the walk of the lane ending there
-                at = from_lane<int>((dend - dt - 1) / E, [&](int l) { return aend(l); });
-            }
+            at = at_next;
         } else {
             LV<int> c, own;
             LANES(l) {
