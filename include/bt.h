@@ -108,12 +108,19 @@ typedef struct {
  *                under graph capture);
  *                BT_TUNE_GREEKS: size the book's buffers for
  *                bt_book_price_grad (values with four tangents, 5x the
- *                memory of a price-only book)                              */
+ *                memory of a price-only book);
+ *                BT_TUNE_GRAPH: the first pricing call with given output
+ *                buffers captures the book's whole launch sequence into a
+ *                HIP graph (on a stream of the book's own); that call and
+ *                the later ones with the same buffers launch the graph on
+ *                the caller's stream.  New buffers re-capture.  No HIP
+ *                events are recorded in this mode (BT_TUNE_TIMING is
+ *                ignored)                                                  */
 typedef struct {
     int32_t wgs_per_cu, level_factor, pool_points, flags;
 } bt_tune;
 
-enum { BT_TUNE_TIMING = 1, BT_TUNE_GREEKS = 2 };
+enum { BT_TUNE_TIMING = 1, BT_TUNE_GREEKS = 2, BT_TUNE_GRAPH = 4 };
 
 /* Number of kernels one pricing call launches, in launch order:
  * 0 = result/queue reset, 1 = buyer (bid), 2 = seller (ask), 3 = zero-cost. */
@@ -139,8 +146,10 @@ int bt_book_info(const bt_book *book, int32_t *n, int32_t *n_max, int64_t *nodes
 
 /* Prices every option of the book: ask, bid (Section 3 recursions) and
  * price0 (zero-cost recursion).  d_out: device pointer to n bt_result, in
- * book order.  Asynchronous on `stream`; the book's buffers are shared by
- * all calls on it, so calls on one book must not overlap. */
+ * book order.  Asynchronous on `stream` (the three recursions run on two
+ * streams of the book's own as well, forked from `stream` and joined back
+ * to it before the call's work ends there); the book's buffers are shared
+ * by all calls on it, so calls on one book must not overlap. */
 int bt_book_price(bt_book *book, bt_result *d_out, void *stream);
 
 /* As bt_book_price, and also the Greeks of ask and bid: d_grad is a device
@@ -166,8 +175,11 @@ int bt_book_resolve_overflow(bt_book *book, bt_result *d_out, bt_grad *d_grad, v
 
 /* For a book created with BT_TUNE_TIMING: waits for every pricing call
  * made since the previous bt_book_timings call, writes into ms[0..3] the
- * total milliseconds each kernel took over those calls (HIP events on the
- * call's stream) and into *calls their number.  BT_ENOSUPP without the flag. */
+ * total milliseconds of each group of kernels over those calls -- setup
+ * (reset and level N+1), the buyer's bands, the seller's bands, the
+ * zero-cost recursion; the last three run concurrently, each on a stream of
+ * its own, forked from and joined back to the call's stream -- and into
+ * *calls their number.  BT_ENOSUPP without the flag. */
 int bt_book_timings(bt_book *book, double *ms, int32_t *calls);
 
 /* Frees the book's device memory (synchronises the device first). */

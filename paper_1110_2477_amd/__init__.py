@@ -35,6 +35,7 @@ class BtError(RuntimeError):
 
 BT_TUNE_TIMING = 1
 BT_TUNE_GREEKS = 2
+BT_TUNE_GRAPH = 4
 KERNEL_NAMES = ("setup", "bid", "ask", "price0")
 
 
@@ -189,13 +190,15 @@ class Book:
     ``greeks=True`` the book can also run ``price_grad()`` (ask/bid Greeks
     into a GRAD_DTYPE buffer)."""
 
-    def __init__(self, params, tune=None, greeks=False):
+    def __init__(self, params, tune=None, greeks=False, graph=False):
         import torch
         self.params = _params(params)
         self.n = len(self.params)
         tune = dict(tune or {})
         if greeks:
             tune["flags"] = int(tune.get("flags", 0)) | BT_TUNE_GREEKS
+        if graph:
+            tune["flags"] = int(tune.get("flags", 0)) | BT_TUNE_GRAPH
         self.handle = bt_book_create(self.params, tune if tune else None)
         self.out = torch.empty(self.n * RESULT_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
         self.grad = None

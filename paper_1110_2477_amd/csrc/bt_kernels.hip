@@ -74,6 +74,9 @@ struct KArgs {
     int64_t ws_doubles;
     int *wsi;               // per workgroup: private level index arrays
     int64_t wsi_ints;
+    int64_t ws_side, wsi_side;  // offset of the seller's (0) and buyer's (1) workspaces
+    double *wsp;            // per workgroup of the zero-cost kernel: stock table, two levels
+    int64_t p0_doubles, p0_stab;
     int64_t pcap;           // doubles per private level buffer
     int64_t pool;           // doubles in the pool
     int64_t oStab, oP0, oP1, oSmall, oPool;
@@ -82,7 +85,7 @@ struct KArgs {
     int n_p0;
     bt_grad *grad;          // Greeks output (dual-number launches only)
     double *arena;          // temporaries of big nodes that outgrow a wave's pool slice
-    int64_t arena_cap;      // doubles
+    int64_t arena_cap;      // doubles per party (the buyer's half follows the seller's)
     unsigned long long *arena_ctr;  // bump counters, one per (band, party) launch
 };
 
@@ -102,7 +105,7 @@ __device__ __forceinline__ double *arena_take(const KArgs &A, int ctr, int64_t n
     if ((threadIdx.x & 63) == 0) pos = atomicAdd(A.arena_ctr + ctr, (unsigned long long)n);
     pos = __shfl(pos, 0, 64);
     if ((int64_t)pos + n > A.arena_cap) return nullptr;
-    return A.arena + pos;
+    return A.arena + (int64_t)(ctr & 1) * A.arena_cap + pos;
 }
 
 // Exclusive prefix sum over the workgroup; *total gets the sum.
@@ -204,8 +207,9 @@ __device__ void band_task(const KArgs &A, int r, int item, int blk, int64_t *sh,
     const int c1 = min(c0 + BLOCK_COLS, t_bot + 1);
     const bool last = c1 == t_bot + 1;
 
-    double *ws = A.ws + (int64_t)blockIdx.x * A.ws_doubles;
-    int *wsi = A.wsi + (int64_t)blockIdx.x * A.wsi_ints;
+    // the two parties run concurrently, each on a workspace of its own
+    double *ws = A.ws + SIDE * A.ws_side + (int64_t)blockIdx.x * A.ws_doubles;
+    int *wsi = A.wsi + SIDE * A.wsi_side + (int64_t)blockIdx.x * A.wsi_ints;
     T *Stab = (T *)(ws + A.oStab);
     T *Pb[2] = {(T *)(ws + A.oP0), (T *)(ws + A.oP1)};
     const int64_t pcap = A.pcap / NT;        // numbers per private level
@@ -469,8 +473,8 @@ __global__ __launch_bounds__(WG) void bt_band_kernel(KArgs A, int r)
 __device__ void price0_item(const KArgs &A, const Model &md, int opt, double *ws)
 {
     const int N = md.N;
-    double *Stab = ws + A.oStab;
-    double *V0 = ws + A.oPool, *V1 = ws + A.oPool + (N + 1);
+    double *Stab = ws;
+    double *V0 = ws + A.p0_stab, *V1 = ws + A.p0_stab + (N + 1);
     const Inputs<double> in = inputs_of(md, 0.0);
     stock_table(md, Stab);
     __syncthreads();
@@ -503,7 +507,7 @@ __device__ void price0_item(const KArgs &A, const Model &md, int opt, double *ws
 __global__ __launch_bounds__(WG) void bt_price0_kernel(KArgs A)
 {
     __shared__ int s_item;
-    double *ws = A.ws + (int64_t)blockIdx.x * A.ws_doubles;
+    double *ws = A.wsp + (int64_t)blockIdx.x * A.p0_doubles;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(A.p0_queue, 1);
         __syncthreads();
@@ -614,9 +618,23 @@ struct bt_book {
     int *d_wsi = nullptr;
     double *d_arena = nullptr;
     unsigned long long *d_arena_ctr = nullptr;
+    double *d_wsp = nullptr;
+    // the seller's bands and the zero-cost recursion run on streams of
+    // their own, forked from and joined to the caller's stream
+    hipStream_t s_ask = nullptr, s_p0 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_ask = nullptr, ev_p0 = nullptr;
     KArgs args{};
     bool timing = false;
-    std::vector<hipEvent_t> events;  // BT_NUM_KERNELS + 1 per timed call
+    std::vector<hipEvent_t> events;  // NEV per timed call
+    // BT_TUNE_GRAPH: the launch sequence captured once per (output buffers,
+    // number type) on an internal stream, replayed on the caller's stream
+    bool use_graph = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bt_result *g_out = nullptr;
+    bt_grad *g_grad = nullptr;
+    int g_nt = 0;
     std::vector<bt_params> params;   // host copy, for re-pricing on overflow
     bt_tune tune{};
 };
@@ -626,15 +644,28 @@ namespace {
 void book_free(bt_book *b)
 {
     if (!b) return;
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_ask) (void)hipEventDestroy(b->ev_ask);
+    if (b->ev_p0) (void)hipEventDestroy(b->ev_p0);
+    if (b->s_ask) (void)hipStreamDestroy(b->s_ask);
+    if (b->s_p0) (void)hipStreamDestroy(b->s_p0);
+    b->ev_fork = b->ev_ask = b->ev_p0 = nullptr;
+    b->s_ask = b->s_p0 = nullptr;
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+    b->cap_stream = nullptr;
     for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
     b->events.clear();
     void *ptrs[] = {b->d_models, b->d_items, b->d_tasks, b->d_task_off, b->d_ints,
-                    b->d_fill, b->d_lvl, b->d_lvli, b->d_ws, b->d_wsi, b->d_arena, b->d_arena_ctr};
+                    b->d_fill, b->d_lvl, b->d_lvli, b->d_ws, b->d_wsi, b->d_arena, b->d_arena_ctr, b->d_wsp};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     b->d_models = nullptr; b->d_items = nullptr; b->d_tasks = nullptr; b->d_task_off = nullptr;
     b->d_ints = nullptr; b->d_fill = nullptr; b->d_lvl = nullptr; b->d_lvli = nullptr;
-    b->d_ws = nullptr; b->d_wsi = nullptr; b->d_arena = nullptr; b->d_arena_ctr = nullptr;
+    b->d_ws = nullptr; b->d_wsi = nullptr; b->d_arena = nullptr; b->d_arena_ctr = nullptr; b->d_wsp = nullptr;
 }
 
 template <typename T>
@@ -718,7 +749,7 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
     const int resident = prop.multiProcessorCount * wpc;
     const int grid = std::max(1, std::min(max_tasks, resident));
     const int grid_p0 = std::max(1, std::min((int)p0.size(), resident));
-    const int ws_wgs = std::max(grid, grid_p0);
+    const int ws_wgs = grid;
 
     KArgs a{};
     // a private level holds the records of WG + 1 columns: lf breakpoints per
@@ -734,6 +765,10 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
     a.oPool = a.oSmall + round_up(sc.total * WG * nt, 32);
     a.ws_doubles = a.oPool + round_up(std::max<int64_t>(pool, 2 * (int64_t)n_max + 4), 32);
     a.wsi_ints = round_up(4 * (int64_t)(WG + 1), 64);
+    a.ws_side = a.ws_doubles * ws_wgs;
+    a.wsi_side = a.wsi_ints * ws_wgs;
+    a.p0_stab = round_up(2 * (int64_t)n_max + 3, 32);
+    a.p0_doubles = a.p0_stab + round_up(2 * (int64_t)n_max + 2, 32);
     a.pcap = pcap;
     a.pool = pool;
     a.n_opts = n;
@@ -741,7 +776,8 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
     a.nbands_max = nbands_max;
     a.n_p0 = (int)p0.size();
 
-    b->timing = tune && (tune->flags & BT_TUNE_TIMING);
+    b->use_graph = tune && (tune->flags & BT_TUNE_GRAPH);
+    b->timing = tune && (tune->flags & BT_TUNE_TIMING) && !b->use_graph;
     b->greeks = greeks;
     b->params.assign(h, h + n);
     if (tune) b->tune = *tune;
@@ -758,8 +794,9 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
         (rc = dalloc(&b->d_tasks, tasks.size())) || (rc = dalloc(&b->d_task_off, task_off.size())) ||
         (rc = dalloc(&b->d_ints, nints)) || (rc = dalloc(&b->d_fill, ctr)) ||
         (rc = dalloc(&b->d_lvl, lbuf)) || (rc = dalloc(&b->d_lvli, ibuf)) ||
-        (rc = dalloc(&b->d_ws, a.ws_doubles * ws_wgs)) || (rc = dalloc(&b->d_wsi, a.wsi_ints * ws_wgs)) ||
-        (rc = dalloc(&b->d_arena, arena)) || (rc = dalloc(&b->d_arena_ctr, 2 * (size_t)nbands_max))) {
+        (rc = dalloc(&b->d_ws, 2 * a.ws_side)) || (rc = dalloc(&b->d_wsi, 2 * a.wsi_side)) ||
+        (rc = dalloc(&b->d_wsp, a.p0_doubles * grid_p0)) ||
+        (rc = dalloc(&b->d_arena, 2 * arena)) || (rc = dalloc(&b->d_arena_ctr, 2 * (size_t)nbands_max))) {
         book_free(b);
         return rc;
     }
@@ -783,12 +820,18 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
     a.lvli = b->d_lvli;
     a.ws = b->d_ws;
     a.wsi = b->d_wsi;
+    a.wsp = b->d_wsp;
     a.p0_queue = p0q;
     a.p0_sched = p0s;
     a.arena = b->d_arena;
     a.arena_cap = arena;
     a.arena_ctr = b->d_arena_ctr;
     b->args = a;
+    HIPCHK(hipStreamCreateWithFlags(&b->s_ask, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&b->s_p0, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&b->ev_ask, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&b->ev_p0, hipEventDisableTiming));
     return BT_OK;
 }
 
@@ -826,8 +869,14 @@ int bt_book_info(const bt_book *book, int32_t *n, int32_t *n_max, int64_t *nodes
 
 namespace {
 
-// Reset, level N+1, the buyer's bands, the seller's bands, the zero-cost
-// recursion; with events between the groups when the book times its calls.
+// Reset and level N+1 on the caller's stream, then three independent
+// recursions: the buyer's bands there, the seller's bands and the zero-cost
+// recursion on the book's own streams (forked from the caller's and joined
+// back to it).  When the book times its calls, events bracket the groups:
+// setup, buyer, seller, zero-cost (BT_NUM_KERNELS, kept per call as
+// NEV events).
+constexpr int NEV = 7;
+
 template <typename T>
 int launch_all(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream)
 {
@@ -835,10 +884,10 @@ int launch_all(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream)
     KArgs a = book->args;
     a.out = d_out;
     a.grad = d_grad;
-    hipEvent_t ev[BT_NUM_KERNELS + 1];
+    hipEvent_t ev[NEV];
     if (book->timing) {
-        for (int i = 0; i <= BT_NUM_KERNELS; i++) HIPCHK(hipEventCreate(&ev[i]));
-        for (int i = 0; i <= BT_NUM_KERNELS; i++) book->events.push_back(ev[i]);
+        for (int i = 0; i < NEV; i++) HIPCHK(hipEventCreate(&ev[i]));
+        for (int i = 0; i < NEV; i++) book->events.push_back(ev[i]);
         HIPCHK(hipEventRecord(ev[0], s));
     }
     const int64_t nr = std::max<int64_t>({(int64_t)book->n, 2 * (int64_t)book->nbands_max, book->n_fill,
@@ -851,23 +900,67 @@ int launch_all(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream)
         HIPCHK(hipGetLastError());
     }
     if (book->timing) HIPCHK(hipEventRecord(ev[1], s));
+    HIPCHK(hipEventRecord(book->ev_fork, s));
+    HIPCHK(hipStreamWaitEvent(book->s_ask, book->ev_fork, 0));
+    HIPCHK(hipStreamWaitEvent(book->s_p0, book->ev_fork, 0));
+    // buyer
     for (int r = 0; r < book->nbands_max; r++) {
         if (book->ntasks[2 * r + 1] == 0) continue;
         hipLaunchKernelGGL((bt_band_kernel<1, T>), dim3(std::min(book->grid, book->ntasks[2 * r + 1])), dim3(WG), 0, s, a, r);
         HIPCHK(hipGetLastError());
     }
     if (book->timing) HIPCHK(hipEventRecord(ev[2], s));
+    // seller
+    if (book->timing) HIPCHK(hipEventRecord(ev[3], book->s_ask));
     for (int r = 0; r < book->nbands_max; r++) {
         if (book->ntasks[2 * r] == 0) continue;
-        hipLaunchKernelGGL((bt_band_kernel<0, T>), dim3(std::min(book->grid, book->ntasks[2 * r])), dim3(WG), 0, s, a, r);
+        hipLaunchKernelGGL((bt_band_kernel<0, T>), dim3(std::min(book->grid, book->ntasks[2 * r])), dim3(WG), 0,
+                           book->s_ask, a, r);
         HIPCHK(hipGetLastError());
     }
-    if (book->timing) HIPCHK(hipEventRecord(ev[3], s));
+    if (book->timing) HIPCHK(hipEventRecord(ev[4], book->s_ask));
+    // zero-cost recursion
+    if (book->timing) HIPCHK(hipEventRecord(ev[5], book->s_p0));
     if (book->args.n_p0 > 0) {
-        hipLaunchKernelGGL(bt_price0_kernel, dim3(book->grid_p0), dim3(WG), 0, s, a);
+        hipLaunchKernelGGL(bt_price0_kernel, dim3(book->grid_p0), dim3(WG), 0, book->s_p0, a);
         HIPCHK(hipGetLastError());
     }
-    if (book->timing) HIPCHK(hipEventRecord(ev[4], s));
+    if (book->timing) HIPCHK(hipEventRecord(ev[6], book->s_p0));
+    HIPCHK(hipEventRecord(book->ev_ask, book->s_ask));
+    HIPCHK(hipEventRecord(book->ev_p0, book->s_p0));
+    HIPCHK(hipStreamWaitEvent(s, book->ev_ask, 0));
+    HIPCHK(hipStreamWaitEvent(s, book->ev_p0, 0));
+    return BT_OK;
+}
+
+// The launch sequence directly, or as a replay of its captured graph.
+template <typename T>
+int launch(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream)
+{
+    if (!book->use_graph) return launch_all<T>(book, d_out, d_grad, stream);
+    const int nt = (int)(sizeof(T) / sizeof(double));
+    if (!book->gexec || book->g_out != d_out || book->g_grad != d_grad || book->g_nt != nt) {
+        if (book->gexec) HIPCHK(hipGraphExecDestroy(book->gexec));
+        if (book->graph) HIPCHK(hipGraphDestroy(book->graph));
+        book->gexec = nullptr;
+        book->graph = nullptr;
+        if (!book->cap_stream) HIPCHK(hipStreamCreateWithFlags(&book->cap_stream, hipStreamNonBlocking));
+        HIPCHK(hipStreamBeginCapture(book->cap_stream, hipStreamCaptureModeThreadLocal));
+        const int rc = launch_all<T>(book, d_out, d_grad, book->cap_stream);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(book->cap_stream, &g);
+        if (rc != BT_OK) {
+            if (e == hipSuccess && g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        HIPCHK(e);
+        book->graph = g;
+        HIPCHK(hipGraphInstantiate(&book->gexec, g, nullptr, nullptr, 0));
+        book->g_out = d_out;
+        book->g_grad = d_grad;
+        book->g_nt = nt;
+    }
+    HIPCHK(hipGraphLaunch(book->gexec, (hipStream_t)stream));
     return BT_OK;
 }
 
@@ -878,14 +971,14 @@ extern "C" {
 int bt_book_price(bt_book *book, bt_result *d_out, void *stream)
 {
     if (!book || !d_out) return BT_EINVAL;
-    return launch_all<double>(book, d_out, nullptr, stream);
+    return launch<double>(book, d_out, nullptr, stream);
 }
 
 int bt_book_price_grad(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream)
 {
     if (!book || !d_out || !d_grad) return BT_EINVAL;
     if (!book->greeks) return BT_ENOSUPP;
-    return launch_all<D4>(book, d_out, d_grad, stream);
+    return launch<D4>(book, d_out, d_grad, stream);
 }
 
 int bt_book_resolve_overflow(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream,
@@ -966,15 +1059,17 @@ int bt_book_timings(bt_book *book, double *ms, int32_t *calls)
     if (!book || !ms) return BT_EINVAL;
     if (!book->timing) return BT_ENOSUPP;
     for (int i = 0; i < BT_NUM_KERNELS; i++) ms[i] = 0.0;
-    const size_t per = BT_NUM_KERNELS + 1;
-    const size_t nc = book->events.size() / per;
+    const size_t nc = book->events.size() / NEV;
+    // (start, end) events of setup, buyer, seller, zero-cost
+    const int pair[BT_NUM_KERNELS][2] = {{0, 1}, {1, 2}, {3, 4}, {5, 6}};
     int rc = BT_OK;
     for (size_t c = 0; c < nc; c++) {
-        hipEvent_t *e = &book->events[c * per];
-        if (hipEventSynchronize(e[BT_NUM_KERNELS]) != hipSuccess) rc = BT_EHIP;
+        hipEvent_t *e = &book->events[c * NEV];
+        for (int i = 0; i < NEV; i++)
+            if (hipEventSynchronize(e[i]) != hipSuccess) rc = BT_EHIP;
         for (int i = 0; i < BT_NUM_KERNELS && rc == BT_OK; i++) {
             float t = 0.0f;
-            hipError_t err = hipEventElapsedTime(&t, e[i], e[i + 1]);
+            hipError_t err = hipEventElapsedTime(&t, e[pair[i][0]], e[pair[i][1]]);
             if (err != hipSuccess) { g_last_hip = (int)err; rc = BT_EHIP; }
             ms[i] += t;
         }
