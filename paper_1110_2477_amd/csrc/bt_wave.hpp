@@ -820,7 +820,7 @@ BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds)
 #endif
             win_fill2<N>(F, G, lds, W, at >= 3 ? at - 3 : 0, bt >= 3 ? bt - 3 : 0, &wf, &wg);
         const int dend = dt + tm < Lt ? dt + tm : Lt;
-        if constexpr (sizeof(N) == sizeof(double)) {
+        if constexpr (true) {
             LV<LaneWalk<E>> wk;
             LANES(l) {
                 const int d0 = dt + l * E;
@@ -833,8 +833,12 @@ BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds)
                 at_next = from_lane<int>((dend - dt - 1) / E, [&](int l) { return wk(l).aend; });
 #ifndef BT_HOST_DEBUG
                 // the next tile's windows, loaded while this tile settles
-                win_load<N>(F, G, W, at_next >= 3 ? at_next - 3 : 0, dend - at_next >= 3 ? dend - at_next - 3 : 0, pre);
-                pre_ok = true;
+                // (double numbers; dual numbers would take too many registers)
+                if constexpr (sizeof(N) == sizeof(double)) {
+                    win_load<N>(F, G, W, at_next >= 3 ? at_next - 3 : 0, dend - at_next >= 3 ? dend - at_next - 3 : 0,
+                                pre);
+                    pre_ok = true;
+                }
 #endif
             }
             LV<int> c, own;
@@ -848,6 +852,17 @@ BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds)
             }
             // the slope arriving at each lane's first union point comes from
             // the lane before (the tile before, for lane 0)
+            if constexpr (E == 1) {
+                // a one-position lane holding a duplicate owns no union point
+                // and passes the slope on; the lane before it owns the equal
+                // F point (or is the tile before)
+                LV<double> sh;
+                LANES(l) { sh(l) = pso(l); }
+                lv_up1(sh, psl);
+                LANES(l) {
+                    if (!fst(l).have) pso(l) = sh(l);
+                }
+            }
             const double pnext = from_lane<double>(NLANES - 1, [&](int l) { return pso(l); });
             lv_up1(pso, psl);
             LANES(l) {
