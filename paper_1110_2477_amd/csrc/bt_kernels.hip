@@ -189,7 +189,7 @@ __global__ void bt_init_kernel(KArgs A)
 // s_chunk / s_chunk_cap: each wave's arena chunk (kept for the whole launch
 // and reused by the wave's later big nodes; grown when a node needs more).
 template <int SIDE, typename T>
-__device__ void band_task(const KArgs &A, int r, int item, int blk, int64_t *sh, int *sflag,
+__device__ __forceinline__ void band_task(const KArgs &A, int r, int item, int blk, int64_t *sh, int *sflag,
                           double **s_chunk, int64_t *s_chunk_cap, T *s_win)
 {
     constexpr int NT = sizeof(T) / sizeof(double);

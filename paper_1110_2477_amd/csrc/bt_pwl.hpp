@@ -37,6 +37,16 @@
 #define BTD __device__ __forceinline__
 #endif
 
+// Every View and Arr points into global memory (level buffers, workspace,
+// pool, arena).  Accessing them through a global-qualified pointer lets the
+// compiler emit global instead of flat loads and stores, which do not wait
+// on LDS traffic.
+#if defined(__HIP_DEVICE_COMPILE__) && !defined(BT_HOST_DEBUG)
+#define BT_GLOBAL __attribute__((address_space(1)))
+#else
+#define BT_GLOBAL
+#endif
+
 namespace bt {
 
 // A value and its four tangents (d/dS0, d/dsigma, d/dR, d/dk).
@@ -98,9 +108,9 @@ template <typename T>
 struct View {
     const T *x, *v, *s;
     int m, st;
-    BTD const T &X(int j) const { return x[(int64_t)j * st]; }
-    BTD const T &V(int j) const { return v[(int64_t)j * st]; }
-    BTD const T &S(int j) const { return s[(int64_t)j * st]; }
+    BTD const T &X(int j) const { return ((const BT_GLOBAL T *)x)[(int64_t)j * st]; }
+    BTD const T &V(int j) const { return ((const BT_GLOBAL T *)v)[(int64_t)j * st]; }
+    BTD const T &S(int j) const { return ((const BT_GLOBAL T *)s)[(int64_t)j * st]; }
 };
 
 // Writable storage with room for `cap` points (and cap + 1 slopes).
@@ -108,9 +118,9 @@ template <typename T>
 struct Arr {
     T *x, *v, *s;
     int st, cap;
-    BTD T &X(int j) const { return x[(int64_t)j * st]; }
-    BTD T &V(int j) const { return v[(int64_t)j * st]; }
-    BTD T &S(int j) const { return s[(int64_t)j * st]; }
+    BTD T &X(int j) const { return ((BT_GLOBAL T *)x)[(int64_t)j * st]; }
+    BTD T &V(int j) const { return ((BT_GLOBAL T *)v)[(int64_t)j * st]; }
+    BTD T &S(int j) const { return ((BT_GLOBAL T *)s)[(int64_t)j * st]; }
     BTD View<T> view(int m) const { return View<T>{x, v, s, m, st}; }
 };
 
@@ -128,8 +138,8 @@ struct Seg {
 template <typename T, typename F>
 BTD Seg<T> seg_at(const F &f, int i)
 {
-    if (i == 0) return Seg<T>{f.X(0), f.V(0), f.S(0)};
-    return Seg<T>{f.X(i - 1), f.V(i - 1), f.S(i)};
+    const int p = i > 0 ? i - 1 : 0;   // no branch: the loads issue together
+    return Seg<T>{f.X(p), f.V(p), f.S(i)};
 }
 
 template <typename T>

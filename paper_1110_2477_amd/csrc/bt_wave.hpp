@@ -68,13 +68,36 @@ struct LV {
     __device__ __forceinline__ T &operator()(int) { return a; }
     __device__ __forceinline__ const T &operator()(int) const { return a; }
 };
-__device__ __forceinline__ double shfl_num(double x, int src) { return __shfl(x, src, 64); }
-__device__ __forceinline__ int shfl_num(int x, int src) { return __shfl(x, src, 64); }
+// Cross-lane moves by DPP (row shifts and broadcasts, whole-wave shifts) and
+// v_readlane: no LDS round trip.  CTRL: 0x101-0x10f row_shl, 0x111-0x11f
+// row_shr, 0x130 wave_shl:1, 0x138 wave_shr:1, 0x142 row_bcast:15, 0x143
+// row_bcast:31.  Lanes without a source keep `old`.
+template <int CTRL, int RM = 0xf>
+__device__ __forceinline__ int dpp_i(int old, int src)
+{
+    return __builtin_amdgcn_update_dpp(old, src, CTRL, RM, 0xf, false);
+}
+template <int CTRL, int RM = 0xf>
+__device__ __forceinline__ double dpp_d(double old, double src)
+{
+    const long long o = __double_as_longlong(old), x = __double_as_longlong(src);
+    const int lo = __builtin_amdgcn_update_dpp((int)o, (int)x, CTRL, RM, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(x >> 32), CTRL, RM, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// value of lane src (src the same in every lane)
+__device__ __forceinline__ int shfl_num(int x, int src) { return __builtin_amdgcn_readlane(x, src); }
+__device__ __forceinline__ double shfl_num(double x, int src)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)b, src), hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 __device__ __forceinline__ D4 shfl_num(const D4 &x, int src)
 {
     D4 r;
-    r.v = __shfl(x.v, src, 64);
-    for (int i = 0; i < 4; i++) r.d[i] = __shfl(x.d[i], src, 64);
+    r.v = shfl_num(x.v, src);
+    for (int i = 0; i < 4; i++) r.d[i] = shfl_num(x.d[i], src);
     return r;
 }
 #endif
@@ -137,15 +160,16 @@ BTD int lv_exscan(LV<int> &v)
     for (int l = 0; l < bt_host_lanes; l++) { const int t = v(l); v(l) = acc; acc += t; }
     return acc;
 #else
-    const int lane = WLANE, x0 = v.a;
+    const int x0 = v.a;
     int x = x0;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
+    x += dpp_i<0x111>(0, x);
+    x += dpp_i<0x112>(0, x);
+    x += dpp_i<0x114>(0, x);
+    x += dpp_i<0x118>(0, x);
+    x += dpp_i<0x142, 0xa>(0, x);
+    x += dpp_i<0x143, 0xc>(0, x);
     v.a = x - x0;
-    return __shfl(x, 63, 64);
+    return __builtin_amdgcn_readlane(x, 63);
 #endif
 }
 
@@ -158,15 +182,17 @@ BTD int lv_rexscan(LV<int> &v)
     for (int l = bt_host_lanes - 1; l >= 0; l--) { const int t = v(l); v(l) = acc; acc += t; }
     return acc;
 #else
-    const int lane = WLANE, x0 = v.a;
-    int x = x0;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_down(x, o, 64);
-        if (lane + o < 64) x += y;
-    }
-    v.a = x - x0;
-    return __shfl(x, 0, 64);
+    // inclusive prefix sums; the lanes to the right hold total - prefix
+    int x = v.a;
+    x += dpp_i<0x111>(0, x);
+    x += dpp_i<0x112>(0, x);
+    x += dpp_i<0x114>(0, x);
+    x += dpp_i<0x118>(0, x);
+    x += dpp_i<0x142, 0xa>(0, x);
+    x += dpp_i<0x143, 0xc>(0, x);
+    const int tot = __builtin_amdgcn_readlane(x, 63);
+    v.a = tot - x;
+    return tot;
 #endif
 }
 
@@ -191,19 +217,26 @@ BTD void lv_rexmin(LV<double> &h, LV<int> &q)
         argmin_pick(ch, cq, th, tq);
     }
 #else
-    const int lane = WLANE;
+    // (the pick is a lexicographic minimum, so the order of combination
+    // does not matter) suffix minima within each row of 16 lanes ...
+    const double INF = __builtin_huge_val();
+    const int QMAX = 0x7fffffff;
     double x = h.a;
     int qi = q.a;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const double y = __shfl_down(x, o, 64);
-        const int qy = __shfl_down(qi, o, 64);
-        if (lane + o < 64) argmin_pick(x, qi, y, qy);
-    }
-    const double xe = __shfl_down(x, 1, 64);
-    const int qe = __shfl_down(qi, 1, 64);
-    h.a = lane < 63 ? xe : __builtin_huge_val();
-    q.a = lane < 63 ? qe : 0x7fffffff;
+    argmin_pick(x, qi, dpp_d<0x101>(INF, x), dpp_i<0x101>(QMAX, qi));
+    argmin_pick(x, qi, dpp_d<0x102>(INF, x), dpp_i<0x102>(QMAX, qi));
+    argmin_pick(x, qi, dpp_d<0x104>(INF, x), dpp_i<0x104>(QMAX, qi));
+    argmin_pick(x, qi, dpp_d<0x108>(INF, x), dpp_i<0x108>(QMAX, qi));
+    // ... then the rows to the right, whose first lanes hold their minima
+    const double r1 = shfl_num(x, 16), r2 = shfl_num(x, 32), r3 = shfl_num(x, 48);
+    const int q1 = shfl_num(qi, 16), q2 = shfl_num(qi, 32), q3 = shfl_num(qi, 48);
+    const int row = WLANE >> 4;
+    if (row < 3) argmin_pick(x, qi, r3, q3);
+    if (row < 2) argmin_pick(x, qi, r2, q2);
+    if (row < 1) argmin_pick(x, qi, r1, q1);
+    // exclusive: the next lane's inclusive minimum
+    h.a = dpp_d<0x130>(INF, x);
+    q.a = dpp_i<0x130>(QMAX, qi);
 #endif
 }
 
@@ -215,8 +248,7 @@ BTD void lv_up1(LV<double> &v, double fill)
     for (int l = bt_host_lanes - 1; l > 0; l--) v(l) = v(l - 1);
     v(0) = fill;
 #else
-    const double y = __shfl_up(v.a, 1, 64);
-    v.a = WLANE == 0 ? fill : y;
+    v.a = dpp_d<0x138>(fill, v.a);
 #endif
 }
 
@@ -427,21 +459,25 @@ BTD Win<N> win_fill(const FF &F, N *buf, int W, int base)
 template <typename FF, typename GG>
 BTD int merge_path_in(const FF &F, const GG &G, int d, int lo, int hi)
 {
-    // quaternary steps (three independent probes per round trip), then binary
+    // The predicate F.X(a) <= G.X(d - a - 1) holds for a below the answer
+    // and fails from it on, so the number of probes that hold places it.
+    // Quaternary steps: three probes whose loads issue together.
     while (hi - lo > 3) {
         const int w = (hi - lo) >> 2;
         const int m1 = lo + w, m2 = lo + 2 * w, m3 = lo + 3 * w;
-        const bool p1 = val(F.X(m1)) <= val(G.X(d - m1 - 1));
-        const bool p2 = val(F.X(m2)) <= val(G.X(d - m2 - 1));
-        const bool p3 = val(F.X(m3)) <= val(G.X(d - m3 - 1));
-        if (p3) lo = m3 + 1;
-        else if (p2) { lo = m2 + 1; hi = m3; }
-        else if (p1) { lo = m1 + 1; hi = m2; }
-        else hi = m1;
+        const int c = (val(F.X(m1)) <= val(G.X(d - m1 - 1)) ? 1 : 0) + (val(F.X(m2)) <= val(G.X(d - m2 - 1)) ? 1 : 0) +
+                      (val(F.X(m3)) <= val(G.X(d - m3 - 1)) ? 1 : 0);
+        const int nlo = c == 0 ? lo : (c == 1 ? m1 + 1 : (c == 2 ? m2 + 1 : m3 + 1));
+        hi = c == 0 ? m1 : (c == 1 ? m2 : (c == 2 ? m3 : hi));
+        lo = nlo;
     }
-    while (lo < hi) {
-        const int a = (lo + hi) >> 1;
-        if (val(F.X(a)) <= val(G.X(d - a - 1))) lo = a + 1; else hi = a;
+    // at most three candidates left: all probed at once
+    if (lo < hi) {
+        const int a1 = lo + 1 < hi ? lo + 1 : lo, a2 = lo + 2 < hi ? lo + 2 : lo;
+        const int c = (val(F.X(lo)) <= val(G.X(d - lo - 1)) ? 1 : 0) +
+                      ((val(F.X(a1)) <= val(G.X(d - a1 - 1)) && lo + 1 < hi) ? 1 : 0) +
+                      ((val(F.X(a2)) <= val(G.X(d - a2 - 1)) && lo + 2 < hi) ? 1 : 0);
+        lo += c;
     }
     return lo;
 }
@@ -586,29 +622,32 @@ BTD void merge_walk(const FF &F, const GG &G, int d0, int d1, int dt, int at, La
     mp_bracket(d0, dt, at, mF, mG, lo, hi);
     int a = merge_path_in(F, G, d0, lo, hi);
     int b = d0 - a;
-    double xa = a < mF ? val(F.X(a)) : 0.0, xb = b < mG ? val(G.X(b)) : 0.0;
-    double xa1 = a + 1 < mF ? val(F.X(a + 1)) : 0.0, xb1 = b + 1 < mG ? val(G.X(b + 1)) : 0.0;
-    double xpf = a > 0 ? val(F.X(a - 1)) : -__builtin_huge_val();
+    // abscissas past a list's end read as 0 and are never compared; every
+    // load is clamped into the list (and the window), so none needs a branch
+    const auto fx = [&](int j) { return val(F.X(j < mF ? j : mF - 1)); };
+    const auto gx = [&](int j) { return val(G.X(j < mG ? j : mG - 1)); };
+    double xa = fx(a), xb = gx(b), xa1 = fx(a + 1), xb1 = gx(b + 1);
+    double xpf = a > 0 ? fx(a - 1) : -__builtin_huge_val();
     int aend = a;
 #pragma unroll
     for (int k = 0; k < K; k++) {
+        // past the end: the last counts, so that the settle step's loads
+        // stay in range
+        w.iF[k] = a;
+        w.iG[k] = b;
         if (d0 + k < w.pe) {
-            if (a < mF && (b >= mG || xa <= xb)) {
-                w.iF[k] = a + 1;
-                w.iG[k] = b + ((b < mG && xb == xa) ? 1 : 0);
-                w.src[k] = 1;
-                xpf = xa;
-                a++;
-                xa = xa1;
-                xa1 = a + 1 < mF ? val(F.X(a + 1)) : 0.0;
-            } else {
-                w.iF[k] = a;
-                w.iG[k] = b + 1;
-                w.src[k] = xpf == xb ? 0 : 2;
-                b++;
-                xb = xb1;
-                xb1 = b + 1 < mG ? val(G.X(b + 1)) : 0.0;
-            }
+            const bool tf = a < mF && (b >= mG || xa <= xb);
+            const double xn = tf ? fx(a + 2) : gx(b + 2);   // the list that advances, two ahead
+            w.iF[k] = tf ? a + 1 : a;
+            w.iG[k] = tf ? b + ((b < mG && xb == xa) ? 1 : 0) : b + 1;
+            w.src[k] = tf ? 1 : (xpf == xb ? 0 : 2);
+            xpf = tf ? xa : xpf;
+            a += tf ? 1 : 0;
+            b += tf ? 0 : 1;
+            xa = tf ? xa1 : xa;
+            xa1 = tf ? xn : xa1;
+            xb = tf ? xb : xb1;
+            xb1 = tf ? xb1 : xn;
             if (d0 + k == d1 - 1) aend = a;
         }
     }
@@ -634,9 +673,11 @@ BTD int merge_settle(const FF &F, const GG &G, const LaneWalk<E> &w, N *sx, N *s
     if (d0 >= d1) return 0;
     constexpr int PD = 2;
     Seg<N> gFk[K], gGk[K];
+    // (every position's counts are in range, so the loads need no branch)
 #pragma unroll
     for (int k = 0; k < PD && k < K; k++) {
-        if (w.src[k] != 0) { gFk[k] = seg_at<N>(F, w.iF[k]); gGk[k] = seg_at<N>(G, w.iG[k]); }
+        gFk[k] = seg_at<N>(F, w.iF[k]);
+        gGk[k] = seg_at<N>(G, w.iG[k]);
     }
     N cP = mk<N>(0.0), cfF = mk<N>(0.0), cfG = mk<N>(0.0);
     Seg<N> cgF{}, cgG{};
@@ -646,7 +687,7 @@ BTD int merge_settle(const FF &F, const GG &G, const LaneWalk<E> &w, N *sx, N *s
     int cnt = 0;
 #pragma unroll
     for (int k = 0; k < K; k++) {
-        if (k + PD < K && w.src[k + PD] != 0) {
+        if (k + PD < K) {
             gFk[k + PD] = seg_at<N>(F, w.iF[k + PD]);
             gGk[k + PD] = seg_at<N>(G, w.iG[k + PD]);
         }
