@@ -58,6 +58,37 @@ def oracle_leg(sample, cores):
     return dict(seconds=dt, nodes=nodes, nodes_per_s=nodes / dt, options_per_s=len(sample) / dt)
 
 
+def kernel_source_digest():
+    """SHA-256 over the HIP sources of the kernels (the counters below are
+    valid only for the kernels they were taken on)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_1110_2477_amd", "csrc")
+    for name in sorted(os.listdir(src)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(src, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter's reading for
+    a plain copy of known size), or None when the summary is missing or was
+    taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "band_kernel_traffic_paper_grid.txt")
+    try:
+        with open(path) as f:
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("kernel_source_sha256") != kernel_source_digest() or kv.get("kernel") != kernel:
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,7 +96,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-extra", action="store_true", help="skip the mixed-book and plain legs")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB from one device buffer to another (the known-size "
+                         "reference for the FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration << 20
+        a = torch.ones(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copied {n} bytes")
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build prices on a single MI355X "
               "(options are independent; see DESIGN.md for how a book would shard). "
@@ -204,9 +248,10 @@ def main():
     achieved = flops / (kernel_ms[dom] * 1e-3) / 1e12
     # one launch per band of the longest tree: bands of 32 levels over N+1 levels
     n_launch = (int(grid["N"].max()) + 1 + 31) // 32
-    out["roofline"] = {"bound": "alu", "kernel": f"bt_band_kernel<{1 if dom == 'bid' else 0}, double>",
+    kernel = f"bt_band_kernel<{1 if dom == 'bid' else 0}, double>"
+    out["roofline"] = {"bound": "alu", "kernel": kernel,
                        "achieved": achieved, "peak": PEAK_FP64_NONFMA_TFLOPS, "unit": "TFLOP/s",
-                       "frac": achieved / PEAK_FP64_NONFMA_TFLOPS, "traffic": None,
+                       "frac": achieved / PEAK_FP64_NONFMA_TFLOPS, "traffic": measured_traffic(kernel),
                        "flops_per_step": flops, "launches_per_step": n_launch,
                        "flops_per_launch": flops / n_launch,
                        "ms_per_launch": kernel_ms[dom] / n_launch}
@@ -214,13 +259,14 @@ def main():
     cores = cpu_cores()
     if not args.no_cpu:
         g50 = W.paper_grid(5000)
-        sample = np.concatenate([W.paper_grid(1500), g50[g50["k"] <= 0.0025]])
+        light = g50[(g50["k"] <= 0.0025) | (g50["payoff"] == 0)]
+        sample = np.concatenate([W.paper_grid(1500), light])
         log(f"cpu oracle leg: {len(sample)} trees on {cores} threads")
         leg = oracle_leg(sample, cores)
         out["cpu_baseline"] = {"value": leg["nodes_per_s"], "unit": "tree nodes/s", "cores": cores,
                                "kind": "oracle",
-                               "sample": "the 24 N=1500 trees of the grid and its 12 N=5000 trees with "
-                                         "k in {0, 0.25%} (ask, bid, price0), one option per thread",
+                               "sample": "the 24 N=1500 trees of the grid and its 18 N=5000 trees other than "
+                                         "the calls with k >= 0.5% (ask, bid, price0), one option per thread",
                                "options_per_s": leg["options_per_s"], "seconds": leg["seconds"]}
     print(json.dumps(out), flush=True)
 
