@@ -262,12 +262,24 @@ def main():
         light = g50[(g50["k"] <= 0.0025) | (g50["payoff"] == 0)]
         sample = np.concatenate([W.paper_grid(1500), light])
         log(f"cpu oracle leg: {len(sample)} trees on {cores} threads")
+        # the same sample on the GPU, one book, for a like-for-like ratio
+        sb = bt.Book(sample)
+        sb.price()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sb.price()
+        torch.cuda.synchronize()
+        gpu_sample_s = time.perf_counter() - t0
+        sample_ok = sb.resolve_overflow() == 0 and bool(np.all(sb.results()["status"] == 0))
+        sb.close()
         leg = oracle_leg(sample, cores)
         out["cpu_baseline"] = {"value": leg["nodes_per_s"], "unit": "tree nodes/s", "cores": cores,
                                "kind": "oracle",
                                "sample": "the 24 N=1500 trees of the grid and its 18 N=5000 trees other than "
                                          "the calls with k >= 0.5% (ask, bid, price0), one option per thread",
-                               "options_per_s": leg["options_per_s"], "seconds": leg["seconds"]}
+                               "options_per_s": leg["options_per_s"], "seconds": leg["seconds"],
+                               "gpu_same_sample": {"value": W.nodes(sample) / gpu_sample_s,
+                                                   "seconds": gpu_sample_s, "ok": sample_ok}}
     print(json.dumps(out), flush=True)
 
 
