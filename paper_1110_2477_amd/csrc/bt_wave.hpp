@@ -497,94 +497,6 @@ BTD void mp_bracket(int d, int dt, int at, int mF, int mG, int &lo, int &hi)
     }
 }
 
-// Walks the merged order from position d0 - 2 (lookbehind) producing union
-// points (a G point equal to the F point before it is the same union point);
-// the union points found at merged positions [d0, d1) belong to this lane.
-// (dt, at): a merged position and its merge-path coordinate, for the
-// bracket of the starting search.  The points they emit (at most two per
-// union point) go to the lane's staging slots sx/sv/ss[k * stride]; returns
-// their number.
-template <int OP, typename N, typename FF, typename GG>
-BTD int merge_lane(const FF &F, const GG &G, double psl0, int d0, int d1, int dt, int at, N *sx, N *sv,
-                   N *ss, int stride)
-{
-    if (d0 >= d1) return 0;
-    const int mF = F.m, mG = G.m, Lt = mF + mG;
-    const int ds = d0 >= 2 ? d0 - 2 : 0;
-    int lo, hi;
-    mp_bracket(ds, dt, at, mF, mG, lo, hi);
-    int a = merge_path_in(F, G, ds, lo, hi);
-    int b = ds - a;
-    int d = ds;
-    // the union point waiting for its successor: abscissa, point counts,
-    // values and merged position
-    N cP = mk<N>(0.0), cfF = mk<N>(0.0), cfG = mk<N>(0.0);
-    int ciF = 0, ciG = 0, cpos = -1;
-    bool have = false;
-    // slope arriving at the waiting point (the left tail's for the first
-    // union point; walks that start later skip their first point)
-    double psl = psl0;
-    int cnt = 0;
-    for (;;) {
-        bool nxt = false;
-        N nP = mk<N>(0.0);
-        int niF = 0, niG = 0, npos = 0;
-        while (d < Lt) {
-            const int pos = d;
-            if (a < mF && (b >= mG || val(F.X(a)) <= val(G.X(b)))) {
-                nP = F.X(a);
-                a++; d++;
-                niF = a;
-                niG = b + ((b < mG && val(G.X(b)) == val(nP)) ? 1 : 0);
-                npos = pos;
-                nxt = true;
-                break;
-            }
-            const N xg = G.X(b);
-            const bool dup = a > 0 && val(F.X(a - 1)) == val(xg);
-            b++; d++;
-            if (dup) continue;
-            nP = xg;
-            niF = a;
-            niG = b;
-            npos = pos;
-            nxt = true;
-            break;
-        }
-        if (!have) {
-            if (!nxt) break;
-            cP = nP; ciF = niF; ciG = niG; cpos = npos;
-            cfF = eval_at<N>(F, ciF, cP);
-            cfG = eval_at<N>(G, ciG, cP);
-            have = true;
-            continue;
-        }
-        Slot<N> o;
-        N nfF = mk<N>(0.0), nfG = mk<N>(0.0);
-        if (nxt) {
-            nfF = eval_at<N>(F, niF, nP);
-            nfG = eval_at<N>(G, niG, nP);
-            o = slot_interval<OP, N>(F, G, cP, ciF, ciG, cfF, cfG, nP, val(nfF) - val(nfG));
-        } else {
-            o = slot_right<OP, N>(F, G, cP, cfF, cfG);
-        }
-        if (cpos >= d0 && cpos < d1) {
-            if (psl != val(o.rs)) {
-                sx[cnt * stride] = cP; sv[cnt * stride] = pick<OP, N>(cfF, cfG); ss[cnt * stride] = o.rs;
-                cnt++;
-            }
-            if (o.hc && val(o.rs) != val(o.crs)) {
-                sx[cnt * stride] = o.cy; sv[cnt * stride] = o.cv; ss[cnt * stride] = o.crs;
-                cnt++;
-            }
-        }
-        psl = val(o.hc ? o.crs : o.rs);
-        if (!nxt || npos >= d1) break;
-        cP = nP; ciF = niF; ciG = niG; cfF = nfF; cfG = nfG; cpos = npos;
-    }
-    return cnt;
-}
-
 // The first union point a lane owns, held back until the slope arriving
 // from the lane before is known.
 template <typename N>
@@ -662,10 +574,17 @@ BTD void merge_walk(const FF &F, const GG &G, int d0, int d1, int dt, int at, La
 // decision needs the slope arriving from the lane before), the points after
 // it go to the staging slots; *psl_out is the slope arriving at the first
 // union point after the lane's.  Returns the number of staged points.
-template <int OP, int E, typename N, typename FF, typename GG>
+// With SC the emitted values and slopes are multiplied by rho and the CANON
+// decisions compare the products (MERGE followed by SCALE: a point whose
+// scaled slopes are equal is the one SCALE's CANON would drop).
+template <int OP, int E, bool SC, typename N, typename FF, typename GG>
 BTD int merge_settle(const FF &F, const GG &G, const LaneWalk<E> &w, N *sx, N *sv, N *ss, int stride,
-                     LaneFirst<N> *first, double *psl_out)
+                     LaneFirst<N> *first, double *psl_out, const N &rho)
 {
+    const auto scl = [&](const N &x) -> N {
+        if constexpr (SC) return x * rho;
+        else return x;
+    };
     constexpr int K = E + 2;
     first->have = false;
     *psl_out = 0.0;
@@ -696,19 +615,20 @@ BTD int merge_settle(const FF &F, const GG &G, const LaneWalk<E> &w, N *sx, N *s
             const N fF = seg_eval<N>(gFk[k], x), fG = seg_eval<N>(gGk[k], x);
             if (have && cpos < d1) {
                 const Slot<N> o = slot_interval_seg<OP, N>(cgF, cgG, cP, cfF, cfG, x, val(fF) - val(fG));
+                const N rs = scl(o.rs), crs = o.hc ? scl(o.crs) : rs, cv = o.hc ? scl(o.cv) : rs;
                 if (!first->have) {
-                    *first = LaneFirst<N>{cP, pick<OP, N>(cfF, cfG), o.rs, o.cy, o.cv, o.crs, o.hc, true};
+                    *first = LaneFirst<N>{cP, scl(pick<OP, N>(cfF, cfG)), rs, o.cy, cv, crs, o.hc, true};
                 } else {
-                    if (psl != val(o.rs)) {
-                        sx[cnt * stride] = cP; sv[cnt * stride] = pick<OP, N>(cfF, cfG); ss[cnt * stride] = o.rs;
+                    if (psl != val(rs)) {
+                        sx[cnt * stride] = cP; sv[cnt * stride] = scl(pick<OP, N>(cfF, cfG)); ss[cnt * stride] = rs;
                         cnt++;
                     }
-                    if (o.hc && val(o.rs) != val(o.crs)) {
-                        sx[cnt * stride] = o.cy; sv[cnt * stride] = o.cv; ss[cnt * stride] = o.crs;
+                    if (o.hc && val(rs) != val(crs)) {
+                        sx[cnt * stride] = o.cy; sv[cnt * stride] = cv; ss[cnt * stride] = crs;
                         cnt++;
                     }
                 }
-                psl = val(o.hc ? o.crs : o.rs);
+                psl = val(o.hc ? crs : rs);
             }
             cP = x; cfF = fF; cfG = fG; cgF = gFk[k]; cgG = gGk[k]; cpos = d0 + k;
             have = true;
@@ -717,19 +637,20 @@ BTD int merge_settle(const FF &F, const GG &G, const LaneWalk<E> &w, N *sx, N *s
     // the last union point of the whole merge has the right tail after it
     if (have && pe == Lt && cpos < d1) {
         const Slot<N> o = slot_right<OP, N>(F, G, cP, cfF, cfG);
+        const N rs = scl(o.rs), crs = o.hc ? scl(o.crs) : rs, cv = o.hc ? scl(o.cv) : rs;
         if (!first->have) {
-            *first = LaneFirst<N>{cP, pick<OP, N>(cfF, cfG), o.rs, o.cy, o.cv, o.crs, o.hc, true};
+            *first = LaneFirst<N>{cP, scl(pick<OP, N>(cfF, cfG)), rs, o.cy, cv, crs, o.hc, true};
         } else {
-            if (psl != val(o.rs)) {
-                sx[cnt * stride] = cP; sv[cnt * stride] = pick<OP, N>(cfF, cfG); ss[cnt * stride] = o.rs;
+            if (psl != val(rs)) {
+                sx[cnt * stride] = cP; sv[cnt * stride] = scl(pick<OP, N>(cfF, cfG)); ss[cnt * stride] = rs;
                 cnt++;
             }
-            if (o.hc && val(o.rs) != val(o.crs)) {
-                sx[cnt * stride] = o.cy; sv[cnt * stride] = o.cv; ss[cnt * stride] = o.crs;
+            if (o.hc && val(rs) != val(crs)) {
+                sx[cnt * stride] = o.cy; sv[cnt * stride] = cv; ss[cnt * stride] = crs;
                 cnt++;
             }
         }
-        psl = val(o.hc ? o.crs : o.rs);
+        psl = val(o.hc ? crs : rs);
     }
     *psl_out = psl;
     return cnt;
@@ -820,9 +741,16 @@ BTD void win_fill2(const FF &F, const GG &G, N *buf, int W, int fb, int gb, Win<
 
 // lds: WaveLds<N>::NUMS numbers of this wave's LDS (in a host build, windows
 // of NLANES E + 9 points and staging of 2 E NLANES slots).
-template <int OP, typename N, typename FF, typename GG>
-BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds)
+// With SC (rho given) the result is SCALE(MERGE(F, G), rho) in one pass; a
+// scaled result that collapses to a line returns 0 (the caller then merges
+// and scales in two passes).
+template <int OP, typename N, bool SC = false, typename FF, typename GG>
+BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds, const N &rho = N{})
 {
+    const auto scl = [&](const N &x) -> N {
+        if constexpr (SC) return x * rho;
+        else return x;
+    };
     constexpr int E = TileE<N>::E;
     const int tm = NLANES * E, W = tm + 9;
     const int mF = F.m, mG = G.m, Lt = mF + mG;
@@ -837,9 +765,9 @@ BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds)
     }
     const N fF0 = eval_at<N>(F, iF0, P0), fG0 = eval_at<N>(G, iG0, P0);
     const Slot<N> L = slot_left<OP, N>(F, G, P0, fF0, fG0);
-    const int keepL = (L.hc && val(L.rs) != val(L.crs)) ? 1 : 0;
-    const double psl0 = val(L.hc ? L.crs : L.rs);
-    double psl = psl0;   // slope arriving at the next tile's first union point
+    const N Lrs = scl(L.rs), Lcrs = L.hc ? scl(L.crs) : Lrs;
+    const int keepL = (L.hc && val(Lrs) != val(Lcrs)) ? 1 : 0;
+    double psl = val(L.hc ? Lcrs : Lrs);   // slope arriving at the next tile's first union point
 #ifndef BT_HOST_DEBUG
     WinRegs<N> pre;      // the next tile's windows (double numbers)
     bool pre_ok = false;
@@ -861,7 +789,7 @@ BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds)
 #endif
             win_fill2<N>(F, G, lds, W, at >= 3 ? at - 3 : 0, bt >= 3 ? bt - 3 : 0, &wf, &wg);
         const int dend = dt + tm < Lt ? dt + tm : Lt;
-        if constexpr (true) {
+        {
             LV<LaneWalk<E>> wk;
             LANES(l) {
                 const int d0 = dt + l * E;
@@ -887,8 +815,8 @@ BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds)
             LV<LaneFirst<N>> fst;
             LANES(l) {
                 double po;
-                own(l) = merge_settle<OP, E, N>(wf, wg, wk(l), stg + l, stg + SZ + l, stg + 2 * SZ + l, NLANES,
-                                               &fst(l), &po);
+                own(l) = merge_settle<OP, E, SC, N>(wf, wg, wk(l), stg + l, stg + SZ + l, stg + 2 * SZ + l,
+                                                   NLANES, &fst(l), &po, rho);
                 pso(l) = po;
             }
             // the slope arriving at each lane's first union point comes from
@@ -932,42 +860,17 @@ BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds)
             carry += tot;
             psl = pnext;
             at = at_next;
-        } else {
-            LV<int> c, own;
-            LANES(l) {
-                const int d0 = dt + l * E;
-                const int d1 = d0 + E < dend ? d0 + E : dend;
-                own(l) = c(l) = merge_lane<OP, N>(wf, wg, psl0, d0, d1, dt, at, stg + l, stg + SZ + l,
-                                                 stg + 2 * SZ + l, NLANES);
-            }
-            const int tot = lv_exscan(c);
-            if (carry + tot > out.cap) return -1;
-            LANES(l) {
-                const int p = carry + c(l), n = own(l);
-#pragma unroll
-                for (int k = 0; k < 2 * E; k++) {
-                    if (k < n) {
-                        const int q = k * NLANES + l;
-                        out.X(p + k) = stg[q]; out.V(p + k) = stg[SZ + q]; out.S(p + k + 1) = stg[2 * SZ + q];
-                    }
-                }
-            }
-            carry += tot;
-            if (dend < Lt) {
-                int lo, hi;
-                mp_bracket(dend, dt, at, mF, mG, lo, hi);
-                at = merge_path_in(wf, wg, dend, lo, hi);
-            }
         }
     }
     if (carry == 0) {
+        if constexpr (SC) return 0;
         LANE0((out.X(0) = L.hc ? L.cy : P0, out.V(0) = L.hc ? L.cv : pick<OP, N>(fF0, fG0),
                out.S(0) = L.rs, out.S(1) = L.rs));
         WSYNC();
         return 1;
     }
-    LANE0(out.S(0) = L.rs);
-    if (keepL) LANE0((out.X(0) = L.cy, out.V(0) = L.cv, out.S(1) = L.crs));
+    LANE0(out.S(0) = Lrs);
+    if (keepL) LANE0((out.X(0) = L.cy, out.V(0) = scl(L.cv), out.S(1) = Lcrs));
     WSYNC();
     return carry;
 }
@@ -1290,17 +1193,18 @@ BTD int wave_env(const Arr<N> &Fa, int m, const N &a, const N &b, const Arr<N> &
         WSYNC();
         return 1;
     }
-    Arr<N> A, RB, B;
+    Arr<N> A, RB;
     if (!T.arr<N>(2 * m, &A) || !T.arr<N>(2 * m, &RB)) { T.used = mark; return -1; }
     int offA = 0, offR = 0;
     const int ma = wave_sweep_a<false, N>(F, a, A, &offA);
     const int mrb = ma < 0 ? -1 : wave_sweep_a<true, N>(F, -b, RB, &offR);
-    if (ma < 0 || mrb < 0 || !T.arr<N>(mrb, &B)) { T.used = mark; return -1; }
+    if (ma < 0 || mrb < 0) { T.used = mark; return -1; }
     const View<N> Av{A.x + offA, A.v + offA, A.s + offA, ma, 1};
     const View<N> Rv{RB.x + offR, RB.v + offR, RB.s + offR, mrb, 1};
-    // B = CANON(mirror image of RB)
-    const int mb = wave_canon<N>(MirSrc<N>{Rv, mrb}, mrb, B);
-    const int mv = mb < 0 ? -1 : wave_merge<OPMIN, N>(Av, B.view(mb), out, lds);
+    // B = CANON(mirror image of RB) is the mirror image itself: the sweep
+    // emits a point only where its slope changes (and a one-point line stays
+    // one point), so the merge reads RB through the mirror
+    const int mv = wave_merge<OPMIN, N>(Av, MirSrc<N>{Rv, mrb}, out, lds);
     T.used = mark;
     return mv;
 }
@@ -1318,24 +1222,29 @@ BTD int wave_node_update(const View<N> &Zu, const View<N> &Zd, const N &S, const
     const int M = Zu.m + Zd.m;
     Arr<N> W, W2, V;
     if (!T.arr<N>(2 * M + 1, &W)) return -1;
-    int mw = wave_merge<OPMAX, N>(Zu, Zd, W, lds);
-    if (mw < 0 || !T.arr<N>(mw, &W2)) return -1;
-    mw = wave_scale(W, mw, rho, W2);
+    // f = SCALE(MERGE(Zu, Zd), rho), in one pass unless the result is a line
+    int mw = wave_merge<OPMAX, N, true>(Zu, Zd, W, lds, rho);
+    if (mw == 0) {
+        mw = wave_merge<OPMAX, N>(Zu, Zd, W, lds);
+        if (mw < 0 || !T.arr<N>(mw, &W2)) return -1;
+        mw = wave_scale(W, mw, rho, W2);
+        W = W2;
+    }
     if (mw < 0) return -1;
     int mv;
     if (SIDE == 0) {
         if (!T.arr<N>(mw, &V)) return -1;
-        mv = wave_clip(W2, mw, a, b, V);
+        mv = wave_clip(W, mw, a, b, V);
     } else {
         // the output of ENV is bounded by 8 mw + 1 points but is about mw in
         // practice: try a buffer of 2 mw + 8 first and fall back to the bound
         const int64_t markv = T.used;
         if (!T.arr<N>(2 * mw + 8, &V)) return -1;
-        mv = wave_env(W2, mw, a, b, V, T, lds);
+        mv = wave_env(W, mw, a, b, V, T, lds);
         if (mv < 0) {
             T.used = markv;
             if (!T.arr<N>(8 * mw + 1, &V)) return -1;
-            mv = wave_env(W2, mw, a, b, V, T, lds);
+            mv = wave_env(W, mw, a, b, V, T, lds);
         }
     }
     if (mv < 0) return -1;
