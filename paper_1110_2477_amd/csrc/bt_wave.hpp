@@ -35,6 +35,7 @@ namespace bt {
 
 #ifdef BT_HOST_DEBUG
 inline int bt_host_lanes = 64;   // lanes emulated by the host build (<= 256)
+inline long long bt_host_env_sched[2];   // scheduled envelope merges, and fallbacks to the walk
 #define NLANES (bt_host_lanes)
 #define LANES(l) for (int l = 0; l < bt_host_lanes; l++)
 #define WSYNC() do { } while (0)
@@ -1011,9 +1012,14 @@ BTD SweepElem<N> sweep_elem(const Src<MIR, N> &f, const N &a, int j, int m, cons
 // Writes the buying half of ENV of F into out, packed against the right end
 // of the buffer: the result is at offset *off (points [*off, *off + count),
 // slopes [*off, *off + count]).  Returns the count or -1 on overflow.
+// codes (m ints, global memory): for every piece j, bit 0 = the point x_j is
+// emitted, bit 1 = the split point y_j is emitted.  *line: the result is the
+// one-point line that no piece emits.
 template <bool MIR, typename N>
-BTD int wave_sweep_a(const View<N> &F, const N &a, const Arr<N> &out, int *off)
+BTD int wave_sweep_a(const View<N> &F, const N &a, const Arr<N> &out, int *off, int *codes, bool *line)
 {
+    BT_GLOBAL int *const gcodes = (BT_GLOBAL int *)codes;
+    *line = false;
     constexpr int E = TileE<N>::E;
     struct St {
         N x[E], v[E], s1[E], x1[E], rs[E], y[E], yv[E];
@@ -1122,6 +1128,7 @@ BTD int wave_sweep_a(const View<N> &F, const N &a, const Arr<N> &out, int *off)
                 int s = cap - (rc + pc1 + pc2);
                 if (pc1) { out.X(s) = p_x; out.V(s) = p_v; out.S(s + 1) = p_rs; s++; }
                 if (pc2) { out.X(s) = p_y; out.V(s) = p_yv; out.S(s + 1) = a; }
+                gcodes[t1] = pc1 | (pc2 << 1);
             });
         }
         LANES(l) {
@@ -1139,6 +1146,7 @@ BTD int wave_sweep_a(const View<N> &F, const N &a, const Arr<N> &out, int *off)
                     int s = cap - r;
                     if (c1) { out.X(s) = q.x[u]; out.V(s) = q.v[u]; out.S(s + 1) = q.rs[u]; s++; }
                     if (c2) { out.X(s) = q.y[u]; out.V(s) = q.yv[u]; out.S(s + 1) = a; }
+                    gcodes[j] = c1 | (c2 << 1);
                 }
             }
         }
@@ -1158,6 +1166,7 @@ BTD int wave_sweep_a(const View<N> &F, const N &a, const Arr<N> &out, int *off)
     if (rc == 0) {
         LANE0((out.X(cap - 1) = f.X(0), out.V(cap - 1) = f.V(0), out.S(cap - 1) = a, out.S(cap) = a));
         *off = cap - 1;
+        *line = true;
         WSYNC();
         return 1;
     }
@@ -1165,6 +1174,210 @@ BTD int wave_sweep_a(const View<N> &F, const N &a, const Arr<N> &out, int *off)
     *off = cap - rc;
     WSYNC();
     return rc;
+}
+
+// ---------------------------------------------------------------------------
+// MERGE_MIN(A, B) of the envelope's two halves without a merge-path search.
+// Every point of A and of B = mirror(RB) lies in some interval [x_j, x_j+1)
+// of F: at x_j itself, or strictly inside (a split point).  A's points of
+// interval j come from piece j of A's sweep, B's from pieces m-1-j (the point
+// x_j) and m-2-j (the split inside) of RB's sweep.  The merged order is
+// therefore interval by interval: x_j (A's first when both have it, B's then
+// being a duplicate), then the split points in increasing order (A's first on
+// a tie).  The schedule lists, for every merged position, the point counts of
+// A and B after it and whether it starts a union point from A (1), from B (2)
+// or not (0: a duplicate), exactly as the merge-path walk records them.
+// ---------------------------------------------------------------------------
+
+// Builds the schedule (sF[d] = 4 iF + src, sG[d] = iG for merged positions d
+// of the ma + mb points); returns false when the counts do not add up.
+template <typename N, typename FA, typename FB>
+BTD bool env_schedule(const FA &A, const FB &B, int ma, int mb, const int *codesA, const int *codesR, int m,
+                      int *sF, int *sG)
+{
+    constexpr int ES = 4;
+    const BT_GLOBAL int *cA = (const BT_GLOBAL int *)codesA;
+    const BT_GLOBAL int *cR = (const BT_GLOBAL int *)codesR;
+    BT_GLOBAL int *gF = (BT_GLOBAL int *)sF;
+    BT_GLOBAL int *gG = (BT_GLOBAL int *)sG;
+    int carryA = 0, carryB = 0;
+    for (int t0 = 0; t0 < m; t0 += NLANES * ES) {
+        LV<int> na, nb;
+        LV<int> code[ES];
+        LANES(l) {
+            int a = 0, b = 0;
+#pragma unroll
+            for (int u = 0; u < ES; u++) {
+                const int j = t0 + l * ES + u;
+                int c = 0;
+                if (j < m) {
+                    const int ca = cA[j];
+                    const int cb1 = cR[m - 1 - j] & 1;
+                    const int cb2 = j <= m - 2 ? (cR[m - 2 - j] >> 1) & 1 : 0;
+                    c = (ca & 3) | (cb1 << 2) | (cb2 << 3);
+                }
+                code[u](l) = c;
+                a += (c & 1) + ((c >> 1) & 1);
+                b += ((c >> 2) & 1) + ((c >> 3) & 1);
+            }
+            na(l) = a;
+            nb(l) = b;
+        }
+        const int totA = lv_exscan(na), totB = lv_exscan(nb);
+        LANES(l) {
+            int a = carryA + na(l), b = carryB + nb(l);
+#pragma unroll
+            for (int u = 0; u < ES; u++) {
+                const int c = code[u](l);
+                int d = a + b;
+                const bool a1 = c & 1, a2 = (c >> 1) & 1, b1 = (c >> 2) & 1, b2 = (c >> 3) & 1;
+                // x_j
+                if (a1 && b1) {
+                    gF[d] = 4 * (a + 1) + 1; gG[d] = b + 1; d++;
+                    gF[d] = 4 * (a + 1) + 0; gG[d] = b + 1; d++;
+                    a++; b++;
+                } else if (a1) {
+                    gF[d] = 4 * (a + 1) + 1; gG[d] = b; d++;
+                    a++;
+                } else if (b1) {
+                    gF[d] = 4 * a + 2; gG[d] = b + 1; d++;
+                    b++;
+                }
+                // the split points
+                if (a2 && b2) {
+                    const double ya = a < ma ? val(A.X(a)) : 0.0, yb = b < mb ? val(B.X(b)) : 0.0;
+                    if (ya < yb) {
+                        gF[d] = 4 * (a + 1) + 1; gG[d] = b; d++;
+                        gF[d] = 4 * (a + 1) + 2; gG[d] = b + 1; d++;
+                    } else if (ya == yb) {
+                        gF[d] = 4 * (a + 1) + 1; gG[d] = b + 1; d++;
+                        gF[d] = 4 * (a + 1) + 0; gG[d] = b + 1; d++;
+                    } else {
+                        gF[d] = 4 * a + 2; gG[d] = b + 1; d++;
+                        gF[d] = 4 * (a + 1) + 1; gG[d] = b + 1; d++;
+                    }
+                    a++; b++;
+                } else if (a2) {
+                    gF[d] = 4 * (a + 1) + 1; gG[d] = b; d++;
+                    a++;
+                } else if (b2) {
+                    gF[d] = 4 * a + 2; gG[d] = b + 1; d++;
+                    b++;
+                }
+            }
+        }
+        carryA += totA;
+        carryB += totB;
+    }
+    WSYNC();
+    return carryA == ma && carryB == mb;
+}
+
+// MERGE(F, G, op) driven by a schedule instead of the merge-path walk (same
+// result as wave_merge); F and G are read from global memory, LDS holds only
+// the staging of the emitted points.
+template <int OP, typename N, typename FF, typename GG>
+BTD int wave_merge_sched(const FF &F, const GG &G, const int *sF, const int *sG, const Arr<N> &out, N *lds)
+{
+    constexpr int E = sizeof(N) == sizeof(double) ? 4 : 2;
+    static_assert(3 * 2 * E * 64 <= WaveLds<N>::NUMS, "staging must fit the wave's LDS");
+    constexpr int K = E + 2;
+    const BT_GLOBAL int *gF = (const BT_GLOBAL int *)sF;
+    const BT_GLOBAL int *gG = (const BT_GLOBAL int *)sG;
+    const int tm = NLANES * E;
+    const int mF = F.m, mG = G.m, Lt = mF + mG;
+    if (out.cap < 1) return -1;
+    N P0;
+    int iF0, iG0;
+    {
+        const double xa = val(F.X(0)), xb = val(G.X(0));
+        if (xa < xb) { P0 = F.X(0); iF0 = 1; iG0 = 0; }
+        else if (xb < xa) { P0 = G.X(0); iF0 = 0; iG0 = 1; }
+        else { P0 = F.X(0); iF0 = 1; iG0 = 1; }
+    }
+    const N fF0 = eval_at<N>(F, iF0, P0), fG0 = eval_at<N>(G, iG0, P0);
+    const Slot<N> L = slot_left<OP, N>(F, G, P0, fF0, fG0);
+    const int keepL = (L.hc && val(L.rs) != val(L.crs)) ? 1 : 0;
+    double psl = val(L.hc ? L.crs : L.rs);   // slope arriving at the next tile's first union point
+    const int SZ = 2 * E * NLANES;
+    N *stg = lds;
+    int carry = keepL;
+    for (int dt = 0; dt < Lt; dt += tm) {
+        WSYNC();   // the previous tile's reads of the staging are done
+        const int dend = dt + tm < Lt ? dt + tm : Lt;
+        LV<LaneWalk<E>> wk;
+        LANES(l) {
+            LaneWalk<E> &w = wk(l);
+            const int d0 = dt + l * E;
+            const int d1 = d0 + E < dend ? d0 + E : dend;
+            w.d0 = d0;
+            w.d1 = d1;
+            w.pe = d1 + 2 < Lt ? d1 + 2 : Lt;
+            w.aend = 0;
+            int pf = 0, pg = 0;
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                int f = pf, g = pg, sc = 0;
+                if (d0 < d1 && d0 + k < w.pe) {
+                    const int e = gF[d0 + k];
+                    f = e >> 2;
+                    sc = e & 3;
+                    g = gG[d0 + k];
+                }
+                w.iF[k] = f;
+                w.iG[k] = g;
+                w.src[k] = sc;
+                pf = f;
+                pg = g;
+            }
+        }
+        LV<int> c, own;
+        LV<double> pso;
+        LV<LaneFirst<N>> fst;
+        LANES(l) {
+            double po;
+            own(l) = merge_settle<OP, E, false, N>(F, G, wk(l), stg + l, stg + SZ + l, stg + 2 * SZ + l, NLANES,
+                                                   &fst(l), &po, N{});
+            pso(l) = po;
+        }
+        const double pnext = from_lane<double>(NLANES - 1, [&](int l) { return pso(l); });
+        lv_up1(pso, psl);
+        LANES(l) {
+            const LaneFirst<N> &f = fst(l);
+            const int cf = f.have ? (pso(l) != val(f.rs) ? 1 : 0) + ((f.hc && val(f.rs) != val(f.crs)) ? 1 : 0) : 0;
+            c(l) = cf + own(l);
+        }
+        const int tot = lv_exscan(c);
+        if (carry + tot > out.cap) return -1;
+        LANES(l) {
+            const LaneFirst<N> &f = fst(l);
+            int p = carry + c(l);
+            if (f.have) {
+                if (pso(l) != val(f.rs)) { out.X(p) = f.x; out.V(p) = f.v; out.S(p + 1) = f.rs; p++; }
+                if (f.hc && val(f.rs) != val(f.crs)) { out.X(p) = f.cy; out.V(p) = f.cv; out.S(p + 1) = f.crs; p++; }
+            }
+            const int n = own(l);
+#pragma unroll
+            for (int k = 0; k < 2 * E; k++) {
+                if (k < n) {
+                    const int q = k * NLANES + l;
+                    out.X(p + k) = stg[q]; out.V(p + k) = stg[SZ + q]; out.S(p + k + 1) = stg[2 * SZ + q];
+                }
+            }
+        }
+        carry += tot;
+        psl = pnext;
+    }
+    if (carry == 0) {
+        LANE0((out.X(0) = L.hc ? L.cy : P0, out.V(0) = L.hc ? L.cv : pick<OP, N>(fF0, fG0),
+               out.S(0) = L.rs, out.S(1) = L.rs));
+        WSYNC();
+        return 1;
+    }
+    LANE0(out.S(0) = L.rs);
+    if (keepL) LANE0((out.X(0) = L.cy, out.V(0) = L.cv, out.S(1) = L.crs));
+    WSYNC();
+    return carry;
 }
 
 // ENV(F, a, b) into out (buyer).
@@ -1195,16 +1408,34 @@ BTD int wave_env(const Arr<N> &Fa, int m, const N &a, const N &b, const Arr<N> &
     }
     Arr<N> A, RB;
     if (!T.arr<N>(2 * m, &A) || !T.arr<N>(2 * m, &RB)) { T.used = mark; return -1; }
+    int *codes = (int *)T.dbl((int64_t)m + 1);   // 2 m ints
+    if (!codes) { T.used = mark; return -1; }
+    int *codesA = codes, *codesR = codes + m;
     int offA = 0, offR = 0;
-    const int ma = wave_sweep_a<false, N>(F, a, A, &offA);
-    const int mrb = ma < 0 ? -1 : wave_sweep_a<true, N>(F, -b, RB, &offR);
+    bool lineA = false, lineR = false;
+    const int ma = wave_sweep_a<false, N>(F, a, A, &offA, codesA, &lineA);
+    const int mrb = ma < 0 ? -1 : wave_sweep_a<true, N>(F, -b, RB, &offR, codesR, &lineR);
     if (ma < 0 || mrb < 0) { T.used = mark; return -1; }
     const View<N> Av{A.x + offA, A.v + offA, A.s + offA, ma, 1};
     const View<N> Rv{RB.x + offR, RB.v + offR, RB.s + offR, mrb, 1};
     // B = CANON(mirror image of RB) is the mirror image itself: the sweep
     // emits a point only where its slope changes (and a one-point line stays
     // one point), so the merge reads RB through the mirror
-    const int mv = wave_merge<OPMIN, N>(Av, MirSrc<N>{Rv, mrb}, out, lds);
+    const MirSrc<N> Bv{Rv, mrb};
+    int mv = -1;
+    bool done = false;
+    if (!lineA && !lineR) {
+        const int64_t nd = ((int64_t)ma + mrb + 2) / 2;   // ma + mrb ints
+        int *sF = (int *)T.dbl(nd), *sG = (int *)T.dbl(nd);
+        if (sF && sG && env_schedule<N>(Av, Bv, ma, mrb, codesA, codesR, m, sF, sG)) {
+            mv = wave_merge_sched<OPMIN, N>(Av, Bv, sF, sG, out, lds);
+            done = true;
+        }
+    }
+    if (!done) mv = wave_merge<OPMIN, N>(Av, Bv, out, lds);
+#ifdef BT_HOST_DEBUG
+    bt_host_env_sched[done ? 0 : 1]++;
+#endif
     T.used = mark;
     return mv;
 }
