@@ -103,20 +103,23 @@ __device__ __forceinline__ D4 shfl_num(const D4 &x, int src)
 }
 #endif
 
-// Elements per lane in a tile.
+// Elements per lane in a tile of CANON and the sweeps.
 template <typename N>
 struct TileE {
     static constexpr int E = sizeof(N) == sizeof(double) ? 4 : 1;
 };
 
-// Numbers of LDS one wave's MERGE takes: two windows (x and v of W points
-// and s of W + 1 slopes each, W = 64 E + 9) and the staging of the points
+// MERGE: merged positions per lane (E), and the numbers of LDS one wave's
+// MERGE takes: the abscissas of two windows of W = 64 E + 9 points each
+// (binary64, the walk compares nothing else) and the staging of the points
 // the lanes emit (x, v, s of 2 E slots per lane).
 template <typename N>
 struct WaveLds {
-    static constexpr int W = 64 * TileE<N>::E + 9;
-    static constexpr int STAGE = 2 * TileE<N>::E * 64;
-    static constexpr int NUMS = 2 * (3 * W + 1) + 3 * STAGE;
+    static constexpr int E = sizeof(N) == sizeof(double) ? 4 : 2;
+    static constexpr int W = 64 * E + 9;
+    static constexpr int STAGE = 2 * E * 64;
+    static constexpr int WIN = (2 * W * (int)sizeof(double) + (int)sizeof(N) - 1) / (int)sizeof(N);
+    static constexpr int NUMS = WIN + 3 * STAGE;
 };
 
 // Bump allocator over a wave's slice of the pool (doubles).  All lanes make
@@ -406,54 +409,13 @@ BTD int wave_canon(const SRC &src, int m, const Arr<N> &out)
 // MERGE(F, G, op) (same result as merge<OP>).
 // ---------------------------------------------------------------------------
 
-// A window of a function's points [base, base + W) (and slopes up to
-// base + W) staged in LDS; indices are those of the whole function.
-template <typename N>
-struct Win {
-    N *x, *v, *s;
+// The abscissas of a function's points [base, base + W) staged in LDS;
+// indices are those of the whole function.
+struct XWin {
+    double *x;
     int base, m;
-    BTD const N &X(int j) const { return x[j - base]; }
-    BTD const N &V(int j) const { return v[j - base]; }
-    BTD const N &S(int j) const { return s[j - base]; }
+    BTD double X(int j) const { return x[j - base]; }
 };
-
-template <typename N, typename FF>
-BTD Win<N> win_fill(const FF &F, N *buf, int W, int base)
-{
-    Win<N> w{buf, buf + W, buf + 2 * W, base, F.m};
-#ifdef BT_HOST_DEBUG
-    LANES(l) {
-        for (int i = l; i < W; i += NLANES) {
-            const int j = base + i;
-            if (j < F.m) { w.x[i] = F.X(j); w.v[i] = F.V(j); }
-        }
-        for (int i = l; i <= W; i += NLANES) {
-            const int j = base + i;
-            if (j <= F.m) w.s[i] = F.S(j);
-        }
-    }
-#else
-    // W = WaveLds<N>::W here: every load of the window is issued before the
-    // first store to LDS
-    constexpr int K = (WaveLds<N>::W + 1 + 63) / 64;
-    N tx[K], tv[K], ts[K];
-    const int l = WLANE;
-#pragma unroll
-    for (int k = 0; k < K; k++) {
-        const int i = l + 64 * k, j = base + i;
-        if (i < W && j < F.m) { tx[k] = F.X(j); tv[k] = F.V(j); }
-        if (i <= W && j <= F.m) ts[k] = F.S(j);
-    }
-#pragma unroll
-    for (int k = 0; k < K; k++) {
-        const int i = l + 64 * k, j = base + i;
-        if (i < W && j < F.m) { w.x[i] = tx[k]; w.v[i] = tv[k]; }
-        if (i <= W && j <= F.m) w.s[i] = ts[k];
-    }
-#endif
-    WSYNC();
-    return w;
-}
 
 // Number of F elements among the first d of the merged order, searched in
 // [lo, hi] (a bracket known to hold it).
@@ -657,87 +619,44 @@ BTD int merge_settle(const FF &F, const GG &G, const LaneWalk<E> &w, N *sx, N *s
     return cnt;
 }
 
-#ifndef BT_HOST_DEBUG
-// The windows of a tile held in registers (loads issued early, stores to
-// LDS later).
+// The abscissas of both windows of a tile held in registers (loads issued
+// early, e.g. while the tile before settles; stores to LDS later).
 template <typename N>
 struct WinRegs {
-    static constexpr int KW = (WaveLds<N>::W + 1 + 63) / 64;
-    N fx[KW], fv[KW], fs[KW], gx[KW], gv[KW], gs[KW];
+#ifdef BT_HOST_DEBUG
+    static constexpr int KW = WaveLds<N>::W;   // any number of emulated lanes
+#else
+    static constexpr int KW = (WaveLds<N>::W + 63) / 64;
+#endif
+    double fx[KW], gx[KW];
     int fb, gb, fm, gm;
 };
 
 template <typename N, typename FF, typename GG>
-__device__ __forceinline__ void win_load(const FF &F, const GG &G, int W, int fb, int gb, WinRegs<N> &r)
+BTD void win_load(const FF &F, const GG &G, int fb, int gb, WinRegs<N> &r, int l)
 {
+    constexpr int W = WaveLds<N>::W;
     r.fb = fb; r.gb = gb; r.fm = F.m; r.gm = G.m;
-    const int l = WLANE;
 #pragma unroll
     for (int k = 0; k < WinRegs<N>::KW; k++) {
-        const int i = l + 64 * k, jf = fb + i, jg = gb + i;
-        if (i < W && jf < F.m) { r.fx[k] = F.X(jf); r.fv[k] = F.V(jf); }
-        if (i <= W && jf <= F.m) r.fs[k] = F.S(jf);
-        if (i < W && jg < G.m) { r.gx[k] = G.X(jg); r.gv[k] = G.V(jg); }
-        if (i <= W && jg <= G.m) r.gs[k] = G.S(jg);
+        const int i = l + NLANES * k, jf = fb + i, jg = gb + i;
+        if (i < W && jf < F.m) r.fx[k] = val(F.X(jf));
+        if (i < W && jg < G.m) r.gx[k] = val(G.X(jg));
     }
 }
 
 template <typename N>
-__device__ __forceinline__ void win_store(N *buf, int W, const WinRegs<N> &r, Win<N> *wf, Win<N> *wg)
+BTD void win_store(double *buf, const WinRegs<N> &r, XWin *wf, XWin *wg, int l)
 {
-    N *gbuf = buf + 3 * W + 1;
-    *wf = Win<N>{buf, buf + W, buf + 2 * W, r.fb, r.fm};
-    *wg = Win<N>{gbuf, gbuf + W, gbuf + 2 * W, r.gb, r.gm};
-    const int l = WLANE;
+    constexpr int W = WaveLds<N>::W;
+    *wf = XWin{buf, r.fb, r.fm};
+    *wg = XWin{buf + W, r.gb, r.gm};
 #pragma unroll
     for (int k = 0; k < WinRegs<N>::KW; k++) {
-        const int i = l + 64 * k, jf = r.fb + i, jg = r.gb + i;
-        if (i < W && jf < r.fm) { wf->x[i] = r.fx[k]; wf->v[i] = r.fv[k]; }
-        if (i <= W && jf <= r.fm) wf->s[i] = r.fs[k];
-        if (i < W && jg < r.gm) { wg->x[i] = r.gx[k]; wg->v[i] = r.gv[k]; }
-        if (i <= W && jg <= r.gm) wg->s[i] = r.gs[k];
+        const int i = l + NLANES * k, jf = r.fb + i, jg = r.gb + i;
+        if (i < W && jf < r.fm) buf[i] = r.fx[k];
+        if (i < W && jg < r.gm) buf[W + i] = r.gx[k];
     }
-}
-#endif
-
-// Both windows of a tile, every load issued before the first store (double
-// numbers; the dual numbers fill one window after the other).
-template <typename N, typename FF, typename GG>
-BTD void win_fill2(const FF &F, const GG &G, N *buf, int W, int fb, int gb, Win<N> *wf, Win<N> *wg)
-{
-#ifdef BT_HOST_DEBUG
-    *wf = win_fill<N>(F, buf, W, fb);
-    *wg = win_fill<N>(G, buf + 3 * W + 1, W, gb);
-#else
-    if constexpr (sizeof(N) != sizeof(double)) {
-        *wf = win_fill<N>(F, buf, W, fb);
-        *wg = win_fill<N>(G, buf + 3 * W + 1, W, gb);
-    } else {
-        constexpr int KW = (WaveLds<N>::W + 1 + 63) / 64;
-        N *gbuf = buf + 3 * W + 1;
-        *wf = Win<N>{buf, buf + W, buf + 2 * W, fb, F.m};
-        *wg = Win<N>{gbuf, gbuf + W, gbuf + 2 * W, gb, G.m};
-        N fx[KW], fv[KW], fs[KW], gx[KW], gv[KW], gs[KW];
-        const int l = WLANE;
-#pragma unroll
-        for (int k = 0; k < KW; k++) {
-            const int i = l + 64 * k, jf = fb + i, jg = gb + i;
-            if (i < W && jf < F.m) { fx[k] = F.X(jf); fv[k] = F.V(jf); }
-            if (i <= W && jf <= F.m) fs[k] = F.S(jf);
-            if (i < W && jg < G.m) { gx[k] = G.X(jg); gv[k] = G.V(jg); }
-            if (i <= W && jg <= G.m) gs[k] = G.S(jg);
-        }
-#pragma unroll
-        for (int k = 0; k < KW; k++) {
-            const int i = l + 64 * k, jf = fb + i, jg = gb + i;
-            if (i < W && jf < F.m) { wf->x[i] = fx[k]; wf->v[i] = fv[k]; }
-            if (i <= W && jf <= F.m) wf->s[i] = fs[k];
-            if (i < W && jg < G.m) { wg->x[i] = gx[k]; wg->v[i] = gv[k]; }
-            if (i <= W && jg <= G.m) wg->s[i] = gs[k];
-        }
-        WSYNC();
-    }
-#endif
 }
 
 // lds: WaveLds<N>::NUMS numbers of this wave's LDS (in a host build, windows
@@ -752,8 +671,8 @@ BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds, const N 
         if constexpr (SC) return x * rho;
         else return x;
     };
-    constexpr int E = TileE<N>::E;
-    const int tm = NLANES * E, W = tm + 9;
+    constexpr int E = WaveLds<N>::E;
+    const int tm = NLANES * E;
     const int mF = F.m, mG = G.m, Lt = mF + mG;
     if (out.cap < 1) return -1;
     N P0;
@@ -769,26 +688,20 @@ BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds, const N 
     const N Lrs = scl(L.rs), Lcrs = L.hc ? scl(L.crs) : Lrs;
     const int keepL = (L.hc && val(Lrs) != val(Lcrs)) ? 1 : 0;
     double psl = val(L.hc ? Lcrs : Lrs);   // slope arriving at the next tile's first union point
-#ifndef BT_HOST_DEBUG
-    WinRegs<N> pre;      // the next tile's windows (double numbers)
-    bool pre_ok = false;
-#endif
-    // staging in LDS after the windows: slot k of lane l at k * NLANES + l
+    // the windows' abscissas, then the staging (slot k of lane l at
+    // k * NLANES + l); a tile's windows are loaded into registers while the
+    // tile before settles
+    double *xw = (double *)lds;
     const int SZ = 2 * E * NLANES;
-    N *stg = lds + 2 * (3 * W + 1);
+    N *stg = lds + WaveLds<N>::WIN;
+    LV<WinRegs<N>> pre;
+    LANES(l) { win_load<N>(F, G, 0, 0, pre(l), l); }
     int at = 0, carry = keepL;
     for (int dt = 0; dt < Lt; dt += tm) {
-        const int bt = dt - at;
         WSYNC();   // the previous tile's reads of the windows and staging are done
-        Win<N> wf, wg;
-#ifndef BT_HOST_DEBUG
-        if (pre_ok) {
-            win_store<N>(lds, W, pre, &wf, &wg);
-            WSYNC();
-            pre_ok = false;
-        } else
-#endif
-            win_fill2<N>(F, G, lds, W, at >= 3 ? at - 3 : 0, bt >= 3 ? bt - 3 : 0, &wf, &wg);
+        XWin wf, wg;
+        LANES(l) { win_store<N>(xw, pre(l), &wf, &wg, l); }
+        WSYNC();
         const int dend = dt + tm < Lt ? dt + tm : Lt;
         {
             LV<LaneWalk<E>> wk;
@@ -801,22 +714,15 @@ BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds, const N 
             int at_next = at;
             if (dend < Lt) {
                 at_next = from_lane<int>((dend - dt - 1) / E, [&](int l) { return wk(l).aend; });
-#ifndef BT_HOST_DEBUG
-                // the next tile's windows, loaded while this tile settles
-                // (double numbers; dual numbers would take too many registers)
-                if constexpr (sizeof(N) == sizeof(double)) {
-                    win_load<N>(F, G, W, at_next >= 3 ? at_next - 3 : 0, dend - at_next >= 3 ? dend - at_next - 3 : 0,
-                                pre);
-                    pre_ok = true;
-                }
-#endif
+                const int bn = dend - at_next;
+                LANES(l) { win_load<N>(F, G, at_next >= 3 ? at_next - 3 : 0, bn >= 3 ? bn - 3 : 0, pre(l), l); }
             }
             LV<int> c, own;
             LV<double> pso;
             LV<LaneFirst<N>> fst;
             LANES(l) {
                 double po;
-                own(l) = merge_settle<OP, E, SC, N>(wf, wg, wk(l), stg + l, stg + SZ + l, stg + 2 * SZ + l,
+                own(l) = merge_settle<OP, E, SC, N>(F, G, wk(l), stg + l, stg + SZ + l, stg + 2 * SZ + l,
                                                    NLANES, &fst(l), &po, rho);
                 pso(l) = po;
             }
@@ -1279,8 +1185,7 @@ BTD bool env_schedule(const FA &A, const FB &B, int ma, int mb, const int *codes
 template <int OP, typename N, typename FF, typename GG>
 BTD int wave_merge_sched(const FF &F, const GG &G, const int *sF, const int *sG, const Arr<N> &out, N *lds)
 {
-    constexpr int E = sizeof(N) == sizeof(double) ? 4 : 2;
-    static_assert(3 * 2 * E * 64 <= WaveLds<N>::NUMS, "staging must fit the wave's LDS");
+    constexpr int E = WaveLds<N>::E;
     constexpr int K = E + 2;
     const BT_GLOBAL int *gF = (const BT_GLOBAL int *)sF;
     const BT_GLOBAL int *gG = (const BT_GLOBAL int *)sG;
