@@ -201,6 +201,27 @@ def main():
                                            ms=dt * 1e3, kernel_ms=mk, ok=bool(np.all(r["status"] == 0)),
                                            options_needing_larger_levels=n_retry)
         log(f"mixed book: {extra['batched_mixed_4096']}")
+        # the autotuner on a 512-option sample of the same mix, then the whole
+        # book with its choice
+        pick = np.random.default_rng(33).choice(len(mixed), 512, replace=False)
+        t0 = time.perf_counter()
+        best, timed = bt.bt_autotune(mixed[np.sort(pick)], reps=1)
+        tune_s = time.perf_counter() - t0
+        tb = bt.Book(mixed, tune=best)
+        tb.price()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tb.price()
+        torch.cuda.synchronize()
+        dt_t = time.perf_counter() - t0
+        tb.resolve_overflow()
+        tuned_ok = bool(np.all(tb.results()["status"] == 0)) and tb.results().tobytes() == r.tobytes()
+        tb.close()
+        extra["batched_mixed_4096_autotuned"] = dict(
+            options_per_s=len(mixed) / dt_t, ms=dt_t * 1e3, same_results=tuned_ok,
+            tune={k: best[k] for k in ("band_levels", "wgs_per_cu")}, autotune_seconds=tune_s,
+            candidates_ms_on_sample=[[c["band_levels"], c["wgs_per_cu"], m] for c, m in timed])
+        log(f"autotuned mixed book: {extra['batched_mixed_4096_autotuned']}")
         # plain single-option forward: bt_price per option, synchronous
         sub = grid[[0, 5, 11, 18]]  # four N=1500 trees (put and call, several k)
         bt.bt_price(sub[0])

@@ -115,9 +115,16 @@ typedef struct {
  *                the later ones with the same buffers launch the graph on
  *                the caller's stream.  New buffers re-capture.  No HIP
  *                events are recorded in this mode (BT_TUNE_TIMING is
- *                ignored)                                                  */
+ *                ignored)
+ *   band_levels  tree levels per band launch, 2..32 (default 32): a band's
+ *                column blocks are 256 - band_levels columns wide and each
+ *                recomputes a halo of band_levels - 1 columns, so shorter
+ *                bands recompute less and launch more often.  Outside
+ *                2..32 (and not 0) bt_book_create returns BT_EINVAL.
+ * No field changes a result: prices, Greeks and breakpoint counts are the
+ * same bits under every tuning.                                            */
 typedef struct {
-    int32_t wgs_per_cu, level_factor, pool_points, flags;
+    int32_t wgs_per_cu, level_factor, pool_points, flags, band_levels;
 } bt_tune;
 
 enum { BT_TUNE_TIMING = 1, BT_TUNE_GREEKS = 2, BT_TUNE_GRAPH = 4 };
@@ -184,6 +191,28 @@ int bt_book_timings(bt_book *book, double *ms, int32_t *calls);
 
 /* Frees the book's device memory (synchronises the device first). */
 void bt_book_destroy(bt_book *book);
+
+/* Autotuner: picks the tuning of a batch by timing it on the GPU.  For every
+ * candidate tuning it builds a book of the n options in h_params (host
+ * memory), prices it once to warm up and then `reps` times on `stream`,
+ * timed with HIP events around the timed calls, and destroys the book; the
+ * fastest candidate is written to *best and, when ms is not NULL, each
+ * candidate's mean milliseconds per call to ms[i].  Candidates: the n_cand
+ * tunings in cand (host memory), or, when cand is NULL, the library's list
+ * of BT_AUTOTUNE_CANDIDATES tunings: band_levels in {8, 16, 32} x
+ * wgs_per_cu in {1, 2}, every other field taken from *base (NULL: all zero).
+ * A candidate with BT_TUNE_GREEKS is timed with bt_book_price_grad,
+ * otherwise with bt_book_price; BT_TUNE_TIMING and BT_TUNE_GRAPH are cleared
+ * for the timing and kept in *best.  A candidate that bt_book_create rejects
+ * gets ms[i] = -1 and is skipped.  Options that outgrow their level buffers
+ * are timed as they are (re-pricing them is bt_book_resolve_overflow's job,
+ * outside the tuner).  Device memory: one book at a time plus the results.
+ * Returns BT_OK, BT_EINVAL (bad arguments or no candidate could be built),
+ * BT_ENOMEM or BT_EHIP.  A caller tuning a large batch can pass a sample of
+ * it: the choice carries over to batches of the same mix. */
+#define BT_AUTOTUNE_CANDIDATES 6
+int bt_autotune(const bt_params *h_params, int32_t n, const bt_tune *base, const bt_tune *cand, int32_t n_cand,
+                int32_t reps, void *stream, bt_tune *best, double *ms);
 
 /* Plain single-option pricing: host in, host out, synchronous on the null
  * stream.  Uses a cached one-option book per calling thread. */

@@ -22,7 +22,7 @@ PUT, CALL, BULL = 0, 1, 2
 EUROPEAN, COST_AT_T0 = 1, 2
 
 # Function names declared in include/bt.h.
-ABI_FUNCTIONS = ("bt_book_create", "bt_book_info", "bt_book_price", "bt_book_price_grad",
+ABI_FUNCTIONS = ("bt_autotune", "bt_book_create", "bt_book_info", "bt_book_price", "bt_book_price_grad",
                  "bt_book_resolve_overflow", "bt_book_timings", "bt_book_destroy", "bt_price", "bt_model_constants", "bt_strerror",
                  "bt_version", "bt_last_hip_error")
 
@@ -39,9 +39,19 @@ BT_TUNE_GRAPH = 4
 KERNEL_NAMES = ("setup", "bid", "ask", "price0")
 
 
+BT_AUTOTUNE_CANDIDATES = 6   # the library's own candidate list (include/bt.h)
+
+
 class _Tune(ctypes.Structure):
     _fields_ = [("wgs_per_cu", ctypes.c_int32), ("level_factor", ctypes.c_int32),
-                ("pool_points", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("pool_points", ctypes.c_int32), ("flags", ctypes.c_int32), ("band_levels", ctypes.c_int32)]
+
+    @classmethod
+    def of(cls, tune):
+        return cls(*(int(tune.get(f, 0)) for f, _ in cls._fields_))
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 _lib = None
@@ -65,6 +75,7 @@ def lib():
     L.bt_book_timings.argtypes = [vp, dp, ctypes.POINTER(i32)]
     L.bt_book_resolve_overflow.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i32)]
     L.bt_book_destroy.argtypes = [vp]
+    L.bt_autotune.argtypes = [vp, i32, vp, vp, i32, i32, vp, vp, dp]
     L.bt_book_destroy.restype = None
     L.bt_price.argtypes = [vp, vp]
     L.bt_model_constants.argtypes = [vp, dp, dp, dp, dp, dp]
@@ -72,7 +83,7 @@ def lib():
     L.bt_strerror.restype = ctypes.c_char_p
     L.bt_version.argtypes = []
     L.bt_last_hip_error.argtypes = []
-    for f in ("bt_book_create", "bt_book_info", "bt_book_price", "bt_book_price_grad", "bt_book_timings", "bt_book_resolve_overflow",
+    for f in ("bt_autotune", "bt_book_create", "bt_book_info", "bt_book_price", "bt_book_price_grad", "bt_book_timings", "bt_book_resolve_overflow",
               "bt_price", "bt_model_constants", "bt_version", "bt_last_hip_error"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
@@ -110,14 +121,36 @@ def bt_book_create(params, tune=None):
     """Creates a book (opaque handle) from a PARAMS_DTYPE array."""
     p = _params(params)
     h = ctypes.c_void_p()
-    t = None
-    if tune is not None:
-        t = _Tune(int(tune.get("wgs_per_cu", 0)), int(tune.get("level_factor", 0)),
-                  int(tune.get("pool_points", 0)), int(tune.get("flags", 0)))
+    t = _Tune.of(tune) if tune is not None else None
     rc = lib().bt_book_create(p.ctypes.data, len(p), ctypes.byref(t) if t is not None else None,
                               ctypes.byref(h))
     _check(rc, "bt_book_create")
     return h
+
+
+def bt_autotune(params, base=None, candidates=None, reps=1, stream=None):
+    """Times candidate tunings of a book of `params` on the GPU and returns
+    (best tune dict, [(candidate dict, ms per call), ...]); candidates=None
+    takes the library's list (band_levels x wgs_per_cu)."""
+    p = _params(params)
+    b = _Tune.of(base) if base is not None else None
+    cand = None
+    n_cand = BT_AUTOTUNE_CANDIDATES
+    if candidates is not None:
+        cand = (_Tune * len(candidates))(*[_Tune.of(c) for c in candidates])
+        n_cand = len(candidates)
+    ms = (ctypes.c_double * n_cand)()
+    best = _Tune()
+    rc = lib().bt_autotune(p.ctypes.data, len(p), ctypes.byref(b) if b is not None else None,
+                           ctypes.cast(cand, ctypes.c_void_p) if cand is not None else None,
+                           n_cand if cand is not None else 0, int(reps), _stream_ptr(stream), ctypes.byref(best), ms)
+    _check(rc, "bt_autotune")
+    if cand is not None:
+        listed = [c.as_dict() for c in cand]
+    else:
+        b0 = b.as_dict() if b is not None else _Tune().as_dict()
+        listed = [dict(b0, band_levels=band, wgs_per_cu=w) for band in (8, 16, 32) for w in (1, 2)]
+    return best.as_dict(), list(zip(listed, list(ms)))
 
 
 def bt_book_info(book):

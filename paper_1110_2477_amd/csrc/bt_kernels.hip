@@ -2,9 +2,10 @@
 //
 // Seller (ask) and buyer (bid) recursions of Section 3 on the tree of
 // Section 4.1.  Every tree side (option x party) is swept from level N+1 to
-// the root in bands of BAND levels.  A band is cut into column blocks of
-// BLOCK_COLS output columns; the workgroup that owns a block also recomputes
-// the halo of up to BAND-1 columns to its right that its trapezoid needs, so
+// the root in bands of `band` levels (a tuning field, at most BAND).  A band
+// is cut into column blocks of WG - band output columns; the workgroup that
+// owns a block also recomputes the halo of up to band-1 columns to its right
+// that its trapezoid needs, so
 // the blocks of a band are independent (the block/region partition of
 // Section 4.2, with the region that would wait for a neighbour recomputed
 // instead).  Consecutive bands are separated by kernel boundaries.  Band
@@ -38,8 +39,8 @@ using namespace bt;
 
 namespace {
 
-constexpr int BAND = 32;                   // levels per band
-constexpr int BLOCK_COLS = WG - BAND;      // output columns per block (+ halo <= WG)
+constexpr int BAND = 32;                   // default (and largest) levels per band
+constexpr int MIN_BAND = 2;
 constexpr int DEFAULT_LEVEL_FACTOR = 32;   // breakpoints per node the band buffers hold
 constexpr int64_t DEFAULT_POOL_POINTS = (int64_t)1 << 18;   // per-workgroup pool, in breakpoints
 constexpr int64_t MIN_PRIVATE_POINTS = (int64_t)1 << 16;    // floor of a private level, in breakpoints
@@ -67,6 +68,7 @@ struct KArgs {
     unsigned long long *fill;   // band-buffer fill counters
     int *failed;            // per item
     int n_opts, n_items, nbands_max;
+    int band;               // levels per band (a block has WG - band output columns)
     bt_result *out;
     double *lvl;            // tree-side band buffers
     int *lvli;
@@ -201,10 +203,11 @@ __device__ __forceinline__ void band_task(const KArgs &A, int r, int item, int b
     const Model md = A.models[I.opt];
     const Inputs<T> in = inputs_of(md, T{});
     const int N = I.N;
-    const int t_top = N - r * BAND;
-    const int t_bot = t_top - BAND + 1 > 0 ? t_top - BAND + 1 : 0;
-    const int c0 = blk * BLOCK_COLS;
-    const int c1 = min(c0 + BLOCK_COLS, t_bot + 1);
+    const int band = A.band, block_cols = WG - band;
+    const int t_top = N - r * band;
+    const int t_bot = t_top - band + 1 > 0 ? t_top - band + 1 : 0;
+    const int c0 = blk * block_cols;
+    const int c1 = min(c0 + block_cols, t_bot + 1);
     const bool last = c1 == t_bot + 1;
 
     // the two parties run concurrently, each on a workspace of its own
@@ -693,6 +696,9 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
     const bool greeks = tune && (tune->flags & BT_TUNE_GREEKS);
     const int64_t nt = greeks ? (int64_t)(sizeof(D4) / sizeof(double)) : 1;  // doubles per number
     const int wpc = (tune && tune->wgs_per_cu > 0) ? tune->wgs_per_cu : 2;
+    if (tune && tune->band_levels != 0 && (tune->band_levels < MIN_BAND || tune->band_levels > BAND)) return BT_EINVAL;
+    const int band = (tune && tune->band_levels > 0) ? tune->band_levels : BAND;
+    const int block_cols = WG - band;
     const int64_t pool_pts = (tune && tune->pool_points > 0) ? (int64_t)tune->pool_points
                                                              : (greeks ? DEFAULT_POOL_POINTS / 4 : DEFAULT_POOL_POINTS);
     const int64_t pool = pool_pts * 4 * nt;
@@ -710,7 +716,7 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
         for (int i : order) {
             Item it;
             it.opt = i; it.side = side; it.N = models[i].N;
-            it.nbands = (it.N + 1 + BAND - 1) / BAND;
+            it.nbands = (it.N + 1 + band - 1) / band;
             it.lcap = round_up(((int64_t)lf * (it.N + 2) * 3 + (it.N + 2)) * nt, 32);
             it.lbuf = lbuf; lbuf += 2 * it.lcap;
             it.ibuf = ibuf; ibuf += round_up(4 * (int64_t)(it.N + 2), 32);
@@ -729,9 +735,9 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
             for (int q = 0; q < (int)items.size(); q++) {
                 const Item &it = items[q];
                 if (it.side != side || r >= it.nbands) continue;
-                const int t_top = it.N - r * BAND;
-                const int t_bot = std::max(t_top - BAND + 1, 0);
-                const int nb = (t_bot + 1 + BLOCK_COLS - 1) / BLOCK_COLS;
+                const int t_top = it.N - r * band;
+                const int t_bot = std::max(t_top - band + 1, 0);
+                const int nb = (t_bot + 1 + block_cols - 1) / block_cols;
                 for (int bk = 0; bk < nb; bk++) tasks.push_back(Task{q, bk});
             }
             ntasks[2 * r + side] = (int)tasks.size() - task_off[2 * r + side];
@@ -774,6 +780,7 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
     a.n_opts = n;
     a.n_items = (int)items.size();
     a.nbands_max = nbands_max;
+    a.band = band;
     a.n_p0 = (int)p0.size();
 
     b->use_graph = tune && (tune->flags & BT_TUNE_GRAPH);
@@ -1086,6 +1093,74 @@ void bt_book_destroy(bt_book *book)
     (void)hipDeviceSynchronize();
     book_free(book);
     delete book;
+}
+
+int bt_autotune(const bt_params *h_params, int32_t n, const bt_tune *base, const bt_tune *cand, int32_t n_cand,
+                int32_t reps, void *stream, bt_tune *best, double *ms)
+{
+    if (!h_params || n < 1 || !best || reps < 1 || (cand && n_cand < 1)) return BT_EINVAL;
+    std::vector<bt_tune> list;
+    const bt_tune b0 = base ? *base : bt_tune{};
+    if (cand) {
+        list.assign(cand, cand + n_cand);
+    } else {
+        for (int band : {8, 16, 32})
+            for (int w : {1, 2}) {
+                bt_tune t = b0;
+                t.band_levels = band;
+                t.wgs_per_cu = w;
+                list.push_back(t);
+            }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    bt_result *d_out = nullptr;
+    bt_grad *d_grad = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = BT_OK, best_i = -1;
+    double best_ms = 0.0;
+    auto hip_ok = [&](hipError_t e) {
+        if (e == hipSuccess) return true;
+        g_last_hip = (int)e;
+        rc = BT_EHIP;
+        return false;
+    };
+    if (hip_ok(hipMalloc(&d_out, (size_t)n * sizeof(bt_result))) &&
+        hip_ok(hipMalloc(&d_grad, (size_t)n * sizeof(bt_grad))) && hip_ok(hipEventCreate(&e0)) &&
+        hip_ok(hipEventCreate(&e1))) {
+        for (size_t i = 0; i < list.size() && rc == BT_OK; i++) {
+            bt_tune t = list[i];
+            t.flags &= ~(BT_TUNE_TIMING | BT_TUNE_GRAPH);
+            const bool grad = (t.flags & BT_TUNE_GREEKS) != 0;
+            if (ms) ms[i] = -1.0;
+            bt_book *bk = nullptr;
+            const int crc = bt_book_create(h_params, n, &t, &bk);
+            if (crc == BT_EINVAL) continue;   // a candidate the library rejects
+            if (crc != BT_OK) { rc = crc; break; }
+            auto call = [&]() { return grad ? bt_book_price_grad(bk, d_out, d_grad, s) : bt_book_price(bk, d_out, s); };
+            int prc = call();
+            if (prc == BT_OK && hip_ok(hipEventRecord(e0, s))) {
+                for (int r = 0; r < reps && prc == BT_OK; r++) prc = call();
+                if (prc == BT_OK && hip_ok(hipEventRecord(e1, s)) && hip_ok(hipEventSynchronize(e1))) {
+                    float el = 0.0f;
+                    if (hip_ok(hipEventElapsedTime(&el, e0, e1))) {
+                        const double m = el / reps;
+                        if (ms) ms[i] = m;
+                        if (best_i < 0 || m < best_ms) { best_ms = m; best_i = (int)i; }
+                    }
+                }
+            }
+            if (prc != BT_OK && rc == BT_OK) rc = prc;
+            bt_book_destroy(bk);
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (d_out) (void)hipFree(d_out);
+    if (d_grad) (void)hipFree(d_grad);
+    if (rc != BT_OK) return rc;
+    if (best_i < 0) return BT_EINVAL;
+    *best = list[best_i];
+    return BT_OK;
 }
 
 int bt_price(const bt_params *p, bt_result *out)
