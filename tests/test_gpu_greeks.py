@@ -166,3 +166,32 @@ def test_autograd_function_backward():
         want = 2.0 * o["grad_ask"] - 3.0 * o["grad_bid"]
         got = np.array([S0.grad[i].item(), sig.grad[i].item(), R.grad[i].item(), k.grad[i].item()])
         assert np.allclose(got, want, rtol=1e-9, atol=1e-9), (i, got, want)
+
+
+def test_stress_book_sample_graph_greeks_vs_oracle():
+    """The stress mix (N log-uniform in [64, 8192], k up to 2 %, puts, calls
+    and bull spreads): a seeded sample of its options small enough for the
+    oracle, priced with Greeks through a captured HIP graph with 16-level
+    bands, against the oracle's values and tangents."""
+    s = W.stress_book(16384, seed=5)
+    small = np.flatnonzero(s["N"] <= 160)
+    pick = np.sort(np.random.Generator(np.random.PCG64(55)).choice(small, 48, replace=False))
+    b = s[pick]
+    say(f"case: stress-book sample, {len(b)} options with N <= 160, graph + Greeks, band 16")
+    bk = bt.Book(b, tune=dict(band_levels=16), greeks=True, graph=True)
+    bk.price_grad()
+    assert bk.resolve_overflow(grad=True) == 0
+    res, g = bk.results(), bk.grads()
+    bk.price_grad()   # a replay gives the same bytes
+    assert bk.results().tobytes() == res.tobytes() and bk.grads().tobytes() == g.tobytes()
+    bk.close()
+    for i in range(len(b)):
+        o = oracle.price_params(b[i], grad=True)
+        assert res[i]["status"] == 0
+        assert res[i]["ask"] == o["ask"] and res[i]["bid"] == o["bid"] and res[i]["price0"] == o["price0"], i
+        assert res[i]["bp_total_ask"] == o["bp_total_ask"] and res[i]["bp_total_bid"] == o["bp_total_bid"], i
+        for side in ("ask", "bid"):
+            ad = grads_of(g[i], side)
+            ref = o["grad_" + side]
+            err = np.max(np.abs(ad - ref) / np.maximum(1.0, np.abs(ref)))
+            assert err <= 1e-9, (i, side, ad, ref)
