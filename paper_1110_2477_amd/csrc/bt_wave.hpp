@@ -878,7 +878,7 @@ BTD int wave_clip(const Arr<N> &A, int m, const N &a, const N &b, const Arr<N> &
 template <typename N>
 struct SweepElem {
     N rs, y, yv;
-    bool sp;
+    bool sp, fw;   // split; rs is s_{j+1} (FOLLOW or SPLIT) rather than a
 };
 
 // Piece j from x_j, v_j, s_{j+1}, x_{j+1} and (SMn, Qn) = (SM_{j+1}, Q_{j+1}).
@@ -888,6 +888,7 @@ BTD SweepElem<N> sweep_elem(const Src<MIR, N> &f, const N &a, int j, int m, cons
 {
     SweepElem<N> e;
     e.sp = false;
+    e.fw = true;
     e.y = mk<N>(0.0);
     e.yv = mk<N>(0.0);
     if (j == m - 1) {
@@ -911,6 +912,7 @@ BTD SweepElem<N> sweep_elem(const Src<MIR, N> &f, const N &a, int j, int m, cons
         }
     }
     e.rs = kind != 0 ? spj : a;
+    e.fw = kind != 0;
     e.sp = kind == 2;
     return e;
 }
@@ -919,18 +921,25 @@ BTD SweepElem<N> sweep_elem(const Src<MIR, N> &f, const N &a, int j, int m, cons
 // of the buffer: the result is at offset *off (points [*off, *off + count),
 // slopes [*off, *off + count]).  Returns the count or -1 on overflow.
 // codes (m ints, global memory): for every piece j, bit 0 = the point x_j is
-// emitted, bit 1 = the split point y_j is emitted.  *line: the result is the
-// one-point line that no piece emits.
-template <bool MIR, typename N>
-BTD int wave_sweep_a(const View<N> &F, const N &a, const Arr<N> &out, int *off, int *codes, bool *line)
+// emitted, bit 1 = the split point y_j is emitted, bit 2 = the slope leaving
+// x_j is s_{j+1} (else a).  *line: the result is the one-point line that no
+// piece emits.  With VO (decisions only) nothing is written to out (only its
+// capacity counts) and qarr[j] receives, for every emitted split point, the
+// index of the minimiser it was computed from: wave_sweep_fill then writes
+// the points (dual numbers take their decisions on the values this way).
+template <bool MIR, typename N, bool VO = false>
+BTD int wave_sweep_a(const View<N> &F, const N &a, const Arr<N> &out, int *off, int *codes, bool *line,
+                     int *qarr = nullptr)
 {
     BT_GLOBAL int *const gcodes = (BT_GLOBAL int *)codes;
+    BT_GLOBAL int *const gq = (BT_GLOBAL int *)qarr;
     *line = false;
     constexpr int E = TileE<N>::E;
     struct St {
         N x[E], v[E], s1[E], x1[E], rs[E], y[E], yv[E];
         double h[E];
-        bool sp[E];
+        int qq[E];
+        bool sp[E], fw[E];
     };
     const Src<MIR, N> f{F, F.m};
     const int m = F.m, tm = NLANES * E, cap = out.cap;
@@ -940,7 +949,8 @@ BTD int wave_sweep_a(const View<N> &F, const N &a, const Arr<N> &out, int *off, 
     double SMc = __builtin_huge_val();
     int Qc = 0x7fffffff;
     // the first piece of the tile on the right, settled by the next tile
-    bool havep = false, p_sp = false;
+    bool havep = false, p_sp = false, p_fw = false;
+    int p_q = 0;
     N p_x = mk<N>(0.0), p_v = mk<N>(0.0), p_rs = mk<N>(0.0), p_y = mk<N>(0.0), p_yv = mk<N>(0.0);
     int rc = 0;   // points written so far, from the right end
     for (int t1 = m; t1 > 0; t1 -= tm) {
@@ -988,7 +998,7 @@ BTD int wave_sweep_a(const View<N> &F, const N &a, const Arr<N> &out, int *off, 
                 const int j = j0 + u;
                 if (j < t1) {
                     const SweepElem<N> e = sweep_elem<MIR, N>(f, a, j, m, q.x[u], q.v[u], q.s1[u], q.x1[u], SM, Q);
-                    q.rs[u] = e.rs; q.y[u] = e.y; q.yv[u] = e.yv; q.sp[u] = e.sp;
+                    q.rs[u] = e.rs; q.y[u] = e.y; q.yv[u] = e.yv; q.sp[u] = e.sp; q.fw[u] = e.fw; q.qq[u] = Q;
                     if (q.h[u] <= SM) { SM = q.h[u]; Q = j; }
                 }
             }
@@ -1031,10 +1041,14 @@ BTD int wave_sweep_a(const View<N> &F, const N &a, const Arr<N> &out, int *off, 
         if (rc + pc1 + pc2 + tot > cap) return -1;
         if (havep) {
             LANE0({
-                int s = cap - (rc + pc1 + pc2);
-                if (pc1) { out.X(s) = p_x; out.V(s) = p_v; out.S(s + 1) = p_rs; s++; }
-                if (pc2) { out.X(s) = p_y; out.V(s) = p_yv; out.S(s + 1) = a; }
-                gcodes[t1] = pc1 | (pc2 << 1);
+                if constexpr (!VO) {
+                    int s = cap - (rc + pc1 + pc2);
+                    if (pc1) { out.X(s) = p_x; out.V(s) = p_v; out.S(s + 1) = p_rs; s++; }
+                    if (pc2) { out.X(s) = p_y; out.V(s) = p_yv; out.S(s + 1) = a; }
+                } else {
+                    if (pc2) gq[t1] = p_q;
+                }
+                gcodes[t1] = pc1 | (pc2 << 1) | (p_fw ? 4 : 0);
             });
         }
         LANES(l) {
@@ -1049,10 +1063,14 @@ BTD int wave_sweep_a(const View<N> &F, const N &a, const Arr<N> &out, int *off, 
                     const int c1 = sl != val(q.rs[u]) ? 1 : 0;
                     const int c2 = (q.sp[u] && val(q.rs[u]) != av) ? 1 : 0;
                     r += c1 + c2;
-                    int s = cap - r;
-                    if (c1) { out.X(s) = q.x[u]; out.V(s) = q.v[u]; out.S(s + 1) = q.rs[u]; s++; }
-                    if (c2) { out.X(s) = q.y[u]; out.V(s) = q.yv[u]; out.S(s + 1) = a; }
-                    gcodes[j] = c1 | (c2 << 1);
+                    if constexpr (!VO) {
+                        int s = cap - r;
+                        if (c1) { out.X(s) = q.x[u]; out.V(s) = q.v[u]; out.S(s + 1) = q.rs[u]; s++; }
+                        if (c2) { out.X(s) = q.y[u]; out.V(s) = q.yv[u]; out.S(s + 1) = a; }
+                    } else {
+                        if (c2) gq[j] = q.qq[u];
+                    }
+                    gcodes[j] = c1 | (c2 << 1) | (q.fw[u] ? 4 : 0);
                 }
             }
         }
@@ -1067,19 +1085,92 @@ BTD int wave_sweep_a(const View<N> &F, const N &a, const Arr<N> &out, int *off, 
             p_y = from_lane<N>(0, [&](int l) { return st(l).y[0]; });
             p_yv = from_lane<N>(0, [&](int l) { return st(l).yv[0]; });
             p_sp = from_lane<int>(0, [&](int l) { return st(l).sp[0] ? 1 : 0; }) != 0;
+            p_fw = from_lane<int>(0, [&](int l) { return st(l).fw[0] ? 1 : 0; }) != 0;
+            p_q = from_lane<int>(0, [&](int l) { return st(l).qq[0]; });
         }
     }
     if (rc == 0) {
-        LANE0((out.X(cap - 1) = f.X(0), out.V(cap - 1) = f.V(0), out.S(cap - 1) = a, out.S(cap) = a));
+        if constexpr (!VO) LANE0((out.X(cap - 1) = f.X(0), out.V(cap - 1) = f.V(0), out.S(cap - 1) = a, out.S(cap) = a));
         *off = cap - 1;
         *line = true;
         WSYNC();
         return 1;
     }
-    LANE0(out.S(cap - rc) = a);
+    if constexpr (!VO) LANE0(out.S(cap - rc) = a);
     *off = cap - rc;
     WSYNC();
     return rc;
+}
+
+// Writes the points of a sweep whose decisions a VO pass took (codes, qarr;
+// rc points, or the one-point line when line): piece j's points go to the
+// slots right after those of the pieces before it, packed against the right
+// end of out as the sweep itself would have written them, with the same
+// arithmetic (x_j, v_j and the slope are copies; a split point is computed
+// from x_j, v_j, s_{j+1} and the minimiser's x and v as in sweep_elem).
+template <bool MIR, typename N>
+BTD void wave_sweep_fill(const View<N> &F, const N &a, const int *codes, const int *qarr, int rc, bool line,
+                         const Arr<N> &out)
+{
+    constexpr int E = 2;
+    const BT_GLOBAL int *gcodes = (const BT_GLOBAL int *)codes;
+    const BT_GLOBAL int *gq = (const BT_GLOBAL int *)qarr;
+    const Src<MIR, N> f{F, F.m};
+    const int m = F.m, tm = NLANES * E, cap = out.cap;
+    if (line) {
+        LANE0((out.X(cap - 1) = f.X(0), out.V(cap - 1) = f.V(0), out.S(cap - 1) = a, out.S(cap) = a));
+        WSYNC();
+        return;
+    }
+    int carry = 0;   // points of the pieces already done, on the right
+    for (int t1 = m; t1 > 0; t1 -= tm) {
+        const int t0 = t1 - tm > 0 ? t1 - tm : 0;
+        LV<int> cnt;
+        LV<int> cd[E];
+        LANES(l) {
+            int n = 0;
+#pragma unroll
+            for (int u = 0; u < E; u++) {
+                const int j = t0 + l * E + u;
+                const int c = j < t1 ? gcodes[j] : 0;
+                cd[u](l) = c;
+                n += (c & 1) + ((c >> 1) & 1);
+            }
+            cnt(l) = n;
+        }
+        const int tot = lv_rexscan(cnt);
+        LANES(l) {
+            // slot of the first point of the lane's first piece
+            int s = cap - (carry + cnt(l));
+#pragma unroll
+            for (int u = 0; u < E; u++) s -= (cd[u](l) & 1) + ((cd[u](l) >> 1) & 1);
+#pragma unroll
+            for (int u = 0; u < E; u++) {
+                const int j = t0 + l * E + u;
+                const int c = cd[u](l);
+                if (c & 3) {
+                    const N xj = f.X(j), vj = f.V(j);
+                    const N spj = f.S(j + 1);
+                    if (c & 1) {
+                        out.X(s) = xj; out.V(s) = vj; out.S(s + 1) = (c & 4) ? spj : a;
+                        s++;
+                    }
+                    if (c & 2) {
+                        const int Q = gq[j];
+                        const N xq = f.X(Q), vq = f.V(Q);
+                        const N hj = vj - a * xj;
+                        const N hq = vq - a * xq;
+                        const N yy = xj + (hq - hj) / (spj - a);
+                        out.X(s) = yy; out.V(s) = vq + a * (yy - xq); out.S(s + 1) = a;
+                        s++;
+                    }
+                }
+            }
+        }
+        carry += tot;
+    }
+    LANE0(out.S(cap - rc) = a);
+    WSYNC();
 }
 
 // ---------------------------------------------------------------------------
@@ -1316,10 +1407,27 @@ BTD int wave_env(const Arr<N> &Fa, int m, const N &a, const N &b, const Arr<N> &
     int *codes = (int *)T.dbl((int64_t)m + 1);   // 2 m ints
     if (!codes) { T.used = mark; return -1; }
     int *codesA = codes, *codesR = codes + m;
-    int offA = 0, offR = 0;
+    int offA = 0, offR = 0, ma = -1, mrb = -1;
     bool lineA = false, lineR = false;
-    const int ma = wave_sweep_a<false, N>(F, a, A, &offA, codesA, &lineA);
-    const int mrb = ma < 0 ? -1 : wave_sweep_a<true, N>(F, -b, RB, &offR, codesR, &lineR);
+    if constexpr (sizeof(N) == sizeof(double)) {
+        ma = wave_sweep_a<false, N>(F, a, A, &offA, codesA, &lineA);
+        mrb = ma < 0 ? -1 : wave_sweep_a<true, N>(F, -b, RB, &offR, codesR, &lineR);
+    } else {
+        // dual numbers: the decisions on the values (a binary64 sweep over
+        // the value parts, several pieces per lane), then the points with
+        // their tangents
+        int *qs = (int *)T.dbl((int64_t)m + 1);   // 2 m ints
+        if (!qs) { T.used = mark; return -1; }
+        constexpr int NT = (int)(sizeof(N) / sizeof(double));
+        const View<double> Fv{(const double *)F.x, (const double *)F.v, (const double *)F.s, m, NT * F.st};
+        const Arr<double> capA{nullptr, nullptr, nullptr, 1, A.cap}, capR{nullptr, nullptr, nullptr, 1, RB.cap};
+        ma = wave_sweep_a<false, double, true>(Fv, val(a), capA, &offA, codesA, &lineA, qs);
+        mrb = ma < 0 ? -1 : wave_sweep_a<true, double, true>(Fv, -val(b), capR, &offR, codesR, &lineR, qs + m);
+        if (ma >= 0 && mrb >= 0) {
+            wave_sweep_fill<false, N>(F, a, codesA, qs, ma, lineA, A);
+            wave_sweep_fill<true, N>(F, -b, codesR, qs + m, mrb, lineR, RB);
+        }
+    }
     if (ma < 0 || mrb < 0) { T.used = mark; return -1; }
     const View<N> Av{A.x + offA, A.v + offA, A.s + offA, ma, 1};
     const View<N> Rv{RB.x + offR, RB.v + offR, RB.s + offR, mrb, 1};
