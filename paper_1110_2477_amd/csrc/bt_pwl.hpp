@@ -171,6 +171,12 @@ template <int OP> BTD int better(double d)
     return d < 0.0 ? PF : (d > 0.0 ? PG : PNONE);
 }
 
+// Whether pick<OP>(a, b) takes a.
+template <int OP, typename T> BTD bool pick_first(const T &a, const T &b)
+{
+    return OP == OPMAX ? val(a) >= val(b) : val(a) <= val(b);
+}
+
 template <int OP, typename T> BTD T pick(const T &a, const T &b)
 {
     if (OP == OPMAX) return val(a) >= val(b) ? a : b;
@@ -238,11 +244,15 @@ BTD int canon(const Arr<T> &f, int m)
 // What MERGE emits for one union point P_k: the slope leaving P_k to the
 // right (rs) and, when the interval after P_k holds a crossing, that point
 // (cy, cv) and the slope leaving it (crs).
+// rsF, cvF, crsF: rs, cv and crs are F's (else G's), so that the same point
+// can be rebuilt from the pieces (dual numbers take their decisions on the
+// values first).
 template <typename T>
 struct Slot {
     T rs;
     bool hc;
     T cy, cv, crs;
+    bool rsF, cvF, crsF;
 };
 
 // Interval (P, P1) with F, G values fF, fG at P and d1 = F - G at P1;
@@ -256,18 +266,22 @@ BTD Slot<T> slot_interval_seg(const Seg<T> &gF, const Seg<T> &gG, const T &P, co
     o.hc = false;
     const T sF = gF.s, sG = gG.s;
     const int b0 = better<OP>(val(fF) - val(fG)), b1 = better<OP>(d1);
+    o.cvF = o.crsF = false;
     if (val(sF) != val(sG) && b0 != PNONE && b1 != PNONE && b0 != b1) {
         const T y = P + (fF - fG) / (sG - sF);
         if (val(y) <= val(P)) {
-            o.rs = b1 == PF ? sF : sG;
+            o.rsF = b1 == PF;
         } else if (val(y) >= val(P1)) {
-            o.rs = b0 == PF ? sF : sG;
+            o.rsF = b0 == PF;
         } else {
-            o.rs = b0 == PF ? sF : sG;
+            o.rsF = b0 == PF;
             o.hc = true;
             o.cy = y;
-            o.cv = pick<OP, T>(seg_eval<T>(gF, y), seg_eval<T>(gG, y));
-            o.crs = b1 == PF ? sF : sG;
+            const T eF = seg_eval<T>(gF, y), eG = seg_eval<T>(gG, y);
+            o.cvF = pick_first<OP, T>(eF, eG);
+            o.cv = o.cvF ? eF : eG;
+            o.crsF = b1 == PF;
+            o.crs = o.crsF ? sF : sG;
         }
     } else {
         int act = b0 != PNONE ? b0 : b1;
@@ -275,8 +289,9 @@ BTD Slot<T> slot_interval_seg(const Seg<T> &gF, const Seg<T> &gG, const T &P, co
             if (OP == OPMAX) act = (val(sG) > val(sF)) ? PG : PF;
             else act = (val(sG) < val(sF)) ? PG : PF;
         }
-        o.rs = act == PF ? sF : sG;
+        o.rsF = act == PF;
     }
+    o.rs = o.rsF ? sF : sG;
     return o;
 }
 
@@ -299,20 +314,25 @@ BTD Slot<T> slot_right(const FF &F, const GG &G, const T &P, const T &fF, const 
     int far;
     if (val(sF) != val(sG)) far = (OP == OPMAX) ? (val(sF) > val(sG) ? PF : PG) : (val(sF) < val(sG) ? PF : PG);
     else far = (bl != PNONE) ? bl : PF;
+    o.cvF = o.crsF = false;
     if (val(sF) != val(sG) && bl != PNONE && bl != far) {
         const T y = P + (fF - fG) / (sG - sF);
         if (val(y) > val(P)) {
-            o.rs = bl == PF ? sF : sG;
+            o.rsF = bl == PF;
             o.hc = true;
             o.cy = y;
-            o.cv = pick<OP, T>(eval_at<T>(F, F.m, y), eval_at<T>(G, G.m, y));
-            o.crs = far == PF ? sF : sG;
+            const T eF = eval_at<T>(F, F.m, y), eG = eval_at<T>(G, G.m, y);
+            o.cvF = pick_first<OP, T>(eF, eG);
+            o.cv = o.cvF ? eF : eG;
+            o.crsF = far == PF;
+            o.crs = o.crsF ? sF : sG;
         } else {
-            o.rs = far == PF ? sF : sG;
+            o.rsF = far == PF;
         }
     } else {
-        o.rs = far == PF ? sF : sG;
+        o.rsF = far == PF;
     }
+    o.rs = o.rsF ? sF : sG;
     return o;
 }
 

@@ -466,6 +466,7 @@ template <typename N>
 struct LaneFirst {
     N x, v, rs, cy, cv, crs;
     bool hc, have;
+    double rf, rg, fl, cfl;   // records of the point and of the crossing (VO)
 };
 
 // The decisions of a lane's walk over its K = E + 2 merged positions
@@ -540,7 +541,13 @@ BTD void merge_walk(const FF &F, const GG &G, int d0, int d1, int dt, int at, La
 // With SC the emitted values and slopes are multiplied by rho and the CANON
 // decisions compare the products (MERGE followed by SCALE: a point whose
 // scaled slopes are equal is the one SCALE's CANON would drop).
-template <int OP, int E, bool SC, typename N, typename FF, typename GG>
+//
+// With VO (decisions only) the staged slots and the records of *first hold,
+// instead of a point, how to rebuild it from the pieces: the point counts of
+// F and G at its union point P (the pieces it evaluates) and flags: 1 = the
+// crossing after P (else P itself), 2 = P is F's point (else G's), 4 = the
+// value is F's (else G's), 8 = the slope leaving is F's (else G's).
+template <int OP, int E, bool SC, typename N, typename FF, typename GG, bool VO = false>
 BTD int merge_settle(const FF &F, const GG &G, const LaneWalk<E> &w, N *sx, N *sv, N *ss, int stride,
                      LaneFirst<N> *first, double *psl_out, const N &rho)
 {
@@ -563,10 +570,36 @@ BTD int merge_settle(const FF &F, const GG &G, const LaneWalk<E> &w, N *sx, N *s
     }
     N cP = mk<N>(0.0), cfF = mk<N>(0.0), cfG = mk<N>(0.0);
     Seg<N> cgF{}, cgG{};
-    int cpos = -1;
-    bool have = false;
+    int cpos = -1, ciF = 0, ciG = 0;
+    bool have = false, cpF = false;
     double psl = 0.0;
     int cnt = 0;
+    // emits the union point cP (with slot o) and its crossing, or their records
+    const auto emit = [&](const Slot<N> &o) {
+        const N rs = scl(o.rs), crs = o.hc ? scl(o.crs) : rs, cv = o.hc ? scl(o.cv) : rs;
+        const bool vF = pick_first<OP, N>(cfF, cfG);
+        double pfl = 0.0, cfl = 0.0;
+        if constexpr (VO) {
+            pfl = (cpF ? 2 : 0) + (vF ? 4 : 0) + (o.rsF ? 8 : 0);
+            cfl = 1 + (cpF ? 2 : 0) + (o.cvF ? 4 : 0) + (o.crsF ? 8 : 0);
+        }
+        if (!first->have) {
+            *first = LaneFirst<N>{cP, scl(vF ? cfF : cfG), rs, o.cy, cv, crs, o.hc, true,
+                                  VO ? (double)ciF : 0.0, VO ? (double)ciG : 0.0, pfl, cfl};
+        } else {
+            if (psl != val(rs)) {
+                if constexpr (VO) { sx[cnt * stride] = ciF; sv[cnt * stride] = ciG; ss[cnt * stride] = pfl; }
+                else { sx[cnt * stride] = cP; sv[cnt * stride] = scl(vF ? cfF : cfG); ss[cnt * stride] = rs; }
+                cnt++;
+            }
+            if (o.hc && val(rs) != val(crs)) {
+                if constexpr (VO) { sx[cnt * stride] = ciF; sv[cnt * stride] = ciG; ss[cnt * stride] = cfl; }
+                else { sx[cnt * stride] = o.cy; sv[cnt * stride] = cv; ss[cnt * stride] = crs; }
+                cnt++;
+            }
+        }
+        psl = val(o.hc ? crs : rs);
+    };
 #pragma unroll
     for (int k = 0; k < K; k++) {
         if (k + PD < K) {
@@ -576,45 +609,14 @@ BTD int merge_settle(const FF &F, const GG &G, const LaneWalk<E> &w, N *sx, N *s
         if (w.src[k] != 0) {
             const N x = w.src[k] == 1 ? gFk[k].x : gGk[k].x;
             const N fF = seg_eval<N>(gFk[k], x), fG = seg_eval<N>(gGk[k], x);
-            if (have && cpos < d1) {
-                const Slot<N> o = slot_interval_seg<OP, N>(cgF, cgG, cP, cfF, cfG, x, val(fF) - val(fG));
-                const N rs = scl(o.rs), crs = o.hc ? scl(o.crs) : rs, cv = o.hc ? scl(o.cv) : rs;
-                if (!first->have) {
-                    *first = LaneFirst<N>{cP, scl(pick<OP, N>(cfF, cfG)), rs, o.cy, cv, crs, o.hc, true};
-                } else {
-                    if (psl != val(rs)) {
-                        sx[cnt * stride] = cP; sv[cnt * stride] = scl(pick<OP, N>(cfF, cfG)); ss[cnt * stride] = rs;
-                        cnt++;
-                    }
-                    if (o.hc && val(rs) != val(crs)) {
-                        sx[cnt * stride] = o.cy; sv[cnt * stride] = cv; ss[cnt * stride] = crs;
-                        cnt++;
-                    }
-                }
-                psl = val(o.hc ? crs : rs);
-            }
+            if (have && cpos < d1) emit(slot_interval_seg<OP, N>(cgF, cgG, cP, cfF, cfG, x, val(fF) - val(fG)));
             cP = x; cfF = fF; cfG = fG; cgF = gFk[k]; cgG = gGk[k]; cpos = d0 + k;
+            ciF = w.iF[k]; ciG = w.iG[k]; cpF = w.src[k] == 1;
             have = true;
         }
     }
     // the last union point of the whole merge has the right tail after it
-    if (have && pe == Lt && cpos < d1) {
-        const Slot<N> o = slot_right<OP, N>(F, G, cP, cfF, cfG);
-        const N rs = scl(o.rs), crs = o.hc ? scl(o.crs) : rs, cv = o.hc ? scl(o.cv) : rs;
-        if (!first->have) {
-            *first = LaneFirst<N>{cP, scl(pick<OP, N>(cfF, cfG)), rs, o.cy, cv, crs, o.hc, true};
-        } else {
-            if (psl != val(rs)) {
-                sx[cnt * stride] = cP; sv[cnt * stride] = scl(pick<OP, N>(cfF, cfG)); ss[cnt * stride] = rs;
-                cnt++;
-            }
-            if (o.hc && val(rs) != val(crs)) {
-                sx[cnt * stride] = o.cy; sv[cnt * stride] = cv; ss[cnt * stride] = crs;
-                cnt++;
-            }
-        }
-        psl = val(o.hc ? crs : rs);
-    }
+    if (have && pe == Lt && cpos < d1) emit(slot_right<OP, N>(F, G, cP, cfF, cfG));
     *psl_out = psl;
     return cnt;
 }
@@ -664,7 +666,11 @@ BTD void win_store(double *buf, const WinRegs<N> &r, XWin *wf, XWin *wg, int l)
 // With SC (rho given) the result is SCALE(MERGE(F, G), rho) in one pass; a
 // scaled result that collapses to a line returns 0 (the caller then merges
 // and scales in two passes).
-template <int OP, typename N, bool SC = false, typename FF, typename GG>
+// With VO the merge only decides: out receives, per emitted point p >=
+// keepL, the record merge_settle describes (F count at X(p), G count at V(p),
+// flags at S(p + 1)); S(0) and a kept left crossing are not written, and a
+// result without points returns 0.
+template <int OP, typename N, bool SC = false, bool VO = false, typename FF, typename GG>
 BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds, const N &rho = N{})
 {
     const auto scl = [&](const N &x) -> N {
@@ -722,8 +728,8 @@ BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds, const N 
             LV<LaneFirst<N>> fst;
             LANES(l) {
                 double po;
-                own(l) = merge_settle<OP, E, SC, N>(F, G, wk(l), stg + l, stg + SZ + l, stg + 2 * SZ + l,
-                                                   NLANES, &fst(l), &po, rho);
+                own(l) = merge_settle<OP, E, SC, N, FF, GG, VO>(F, G, wk(l), stg + l, stg + SZ + l,
+                                                               stg + 2 * SZ + l, NLANES, &fst(l), &po, rho);
                 pso(l) = po;
             }
             // the slope arriving at each lane's first union point comes from
@@ -752,8 +758,13 @@ BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds, const N 
                 const LaneFirst<N> &f = fst(l);
                 int p = carry + c(l);
                 if (f.have) {
-                    if (pso(l) != val(f.rs)) { out.X(p) = f.x; out.V(p) = f.v; out.S(p + 1) = f.rs; p++; }
-                    if (f.hc && val(f.rs) != val(f.crs)) { out.X(p) = f.cy; out.V(p) = f.cv; out.S(p + 1) = f.crs; p++; }
+                    if constexpr (VO) {
+                        if (pso(l) != val(f.rs)) { out.X(p) = f.rf; out.V(p) = f.rg; out.S(p + 1) = f.fl; p++; }
+                        if (f.hc && val(f.rs) != val(f.crs)) { out.X(p) = f.rf; out.V(p) = f.rg; out.S(p + 1) = f.cfl; p++; }
+                    } else {
+                        if (pso(l) != val(f.rs)) { out.X(p) = f.x; out.V(p) = f.v; out.S(p + 1) = f.rs; p++; }
+                        if (f.hc && val(f.rs) != val(f.crs)) { out.X(p) = f.cy; out.V(p) = f.cv; out.S(p + 1) = f.crs; p++; }
+                    }
                 }
                 const int n = own(l);
 #pragma unroll
@@ -770,11 +781,15 @@ BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds, const N 
         }
     }
     if (carry == 0) {
-        if constexpr (SC) return 0;
+        if constexpr (SC || VO) return 0;
         LANE0((out.X(0) = L.hc ? L.cy : P0, out.V(0) = L.hc ? L.cv : pick<OP, N>(fF0, fG0),
                out.S(0) = L.rs, out.S(1) = L.rs));
         WSYNC();
         return 1;
+    }
+    if constexpr (VO) {
+        WSYNC();
+        return carry;
     }
     LANE0(out.S(0) = Lrs);
     if (keepL) LANE0((out.X(0) = L.cy, out.V(0) = scl(L.cv), out.S(1) = Lcrs));
@@ -1376,6 +1391,117 @@ BTD int wave_merge_sched(const FF &F, const GG &G, const int *sF, const int *sG,
     return carry;
 }
 
+// ---------------------------------------------------------------------------
+// Dual numbers: the first MERGE of a node update takes its decisions on the
+// values (a binary64 merge over value views, in decisions-only mode) and then
+// rebuilds every emitted point with its tangents from the recorded pieces,
+// with the settle step's own arithmetic; the records are independent, so the
+// rebuild runs several points per lane at once.  (For the envelope's
+// MERGE_MIN the rebuild measured slower than the dual-number merge itself.)
+// ---------------------------------------------------------------------------
+
+// The value parts of a function of dual numbers, as a binary64 function.
+BTD View<double> vview(const View<D4> &f)
+{
+    constexpr int NT = (int)(sizeof(D4) / sizeof(double));
+    return View<double>{(const double *)f.x, (const double *)f.v, (const double *)f.s, f.m, NT * f.st};
+}
+
+// Points [p0, n) of out from their records (merge_settle, VO).
+template <int OP, bool SC, typename N, typename FF, typename GG>
+BTD void merge_fill(const FF &F, const GG &G, const Arr<double> &rec, int p0, int n, const Arr<N> &out,
+                    const N &rho)
+{
+    constexpr int U = 4;   // records per lane per step, their loads issued together
+    LANES(l) {
+        for (int p1 = p0 + l; p1 < n; p1 += U * NLANES) {
+            int iF[U], iG[U], fl[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int p = p1 + u * NLANES;
+                const int q = p < n ? p : p1;
+                iF[u] = (int)rec.X(q); iG[u] = (int)rec.V(q); fl[u] = (int)rec.S(q + 1);
+            }
+            Seg<N> gF[U], gG[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                gF[u] = seg_at<N>(F, iF[u]);
+                gG[u] = seg_at<N>(G, iG[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int p = p1 + u * NLANES;
+                if (p < n) {
+                    const N P = (fl[u] & 2) ? gF[u].x : gG[u].x;
+                    const N fF = seg_eval<N>(gF[u], P), fG = seg_eval<N>(gG[u], P);
+                    N x, v;
+                    if (fl[u] & 1) {
+                        x = P + (fF - fG) / (gG[u].s - gF[u].s);
+                        v = (fl[u] & 4) ? seg_eval<N>(gF[u], x) : seg_eval<N>(gG[u], x);
+                    } else {
+                        x = P;
+                        v = (fl[u] & 4) ? fF : fG;
+                    }
+                    N sl = (fl[u] & 8) ? gF[u].s : gG[u].s;
+                    if constexpr (SC) {
+                        v = v * rho;
+                        sl = sl * rho;
+                    }
+                    out.X(p) = x; out.V(p) = v; out.S(p + 1) = sl;
+                }
+            }
+        }
+    }
+    WSYNC();
+}
+
+// The left tail of MERGE(F, G): S(0) and a kept crossing before the first
+// union point, written as wave_merge writes them; returns keepL.
+template <int OP, bool SC, typename N, typename FF, typename GG>
+BTD int merge_left_write(const FF &F, const GG &G, const Arr<N> &out, const N &rho)
+{
+    const auto scl = [&](const N &x) -> N {
+        if constexpr (SC) return x * rho;
+        else return x;
+    };
+    N P0;
+    int iF0, iG0;
+    {
+        const double xa = val(F.X(0)), xb = val(G.X(0));
+        if (xa < xb) { P0 = F.X(0); iF0 = 1; iG0 = 0; }
+        else if (xb < xa) { P0 = G.X(0); iF0 = 0; iG0 = 1; }
+        else { P0 = F.X(0); iF0 = 1; iG0 = 1; }
+    }
+    const N fF0 = eval_at<N>(F, iF0, P0), fG0 = eval_at<N>(G, iG0, P0);
+    const Slot<N> L = slot_left<OP, N>(F, G, P0, fF0, fG0);
+    const N Lrs = scl(L.rs), Lcrs = L.hc ? scl(L.crs) : Lrs;
+    const int keepL = (L.hc && val(Lrs) != val(Lcrs)) ? 1 : 0;
+    LANE0(out.S(0) = Lrs);
+    if (keepL) LANE0((out.X(0) = L.cy, out.V(0) = scl(L.cv), out.S(1) = Lcrs));
+    return keepL;
+}
+
+// wave_merge for dual numbers (same result): decisions on the values, then
+// the points.  Falls back to the dual-number merge itself when the records
+// find no room or the result has no points.
+template <int OP, bool SC, typename FF, typename GG>
+BTD int wave_merge_d4(const FF &F, const GG &G, const Arr<D4> &out, D4 *lds, const D4 &rho, WaveTmp &T)
+{
+    const int64_t mark = T.used;
+    Arr<double> rec;
+    int n = 0;
+    if (T.arr<double>(out.cap, &rec)) n = wave_merge<OP, double, SC, true>(vview(F), vview(G), rec, (double *)lds, val(rho));
+    if (n <= 0) {
+        T.used = mark;
+        if (n < 0) return -1;
+        return wave_merge<OP, D4, SC>(F, G, out, lds, rho);
+    }
+    const int keepL = merge_left_write<OP, SC, D4>(F, G, out, rho);
+    merge_fill<OP, SC, D4>(F, G, rec, keepL, n, out, rho);
+    T.used = mark;
+    return n;
+}
+
 // ENV(F, a, b) into out (buyer).
 template <typename N>
 BTD int wave_env(const Arr<N> &Fa, int m, const N &a, const N &b, const Arr<N> &out, WaveTmp &T, N *lds)
@@ -1467,7 +1593,9 @@ BTD int wave_node_update(const View<N> &Zu, const View<N> &Zd, const N &S, const
     Arr<N> W, W2, V;
     if (!T.arr<N>(2 * M + 1, &W)) return -1;
     // f = SCALE(MERGE(Zu, Zd), rho), in one pass unless the result is a line
-    int mw = wave_merge<OPMAX, N, true>(Zu, Zd, W, lds, rho);
+    int mw;
+    if constexpr (sizeof(N) == sizeof(double)) mw = wave_merge<OPMAX, N, true>(Zu, Zd, W, lds, rho);
+    else mw = wave_merge_d4<OPMAX, true>(Zu, Zd, W, lds, rho, T);
     if (mw == 0) {
         mw = wave_merge<OPMAX, N>(Zu, Zd, W, lds);
         if (mw < 0 || !T.arr<N>(mw, &W2)) return -1;
