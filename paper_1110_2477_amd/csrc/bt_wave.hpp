@@ -115,7 +115,7 @@ struct TileE {
 // the lanes emit (x, v, s of 2 E slots per lane).
 template <typename N>
 struct WaveLds {
-    static constexpr int E = sizeof(N) == sizeof(double) ? 4 : 2;
+    static constexpr int E = sizeof(N) == sizeof(double) ? 8 : 2;
     static constexpr int W = 64 * E + 9;
     static constexpr int STAGE = 2 * E * 64;
     static constexpr int WIN = (2 * W * (int)sizeof(double) + (int)sizeof(N) - 1) / (int)sizeof(N);
@@ -1487,6 +1487,8 @@ BTD int merge_left_write(const FF &F, const GG &G, const Arr<N> &out, const N &r
 template <int OP, bool SC, typename FF, typename GG>
 BTD int wave_merge_d4(const FF &F, const GG &G, const Arr<D4> &out, D4 *lds, const D4 &rho, WaveTmp &T)
 {
+    static_assert(WaveLds<double>::NUMS * sizeof(double) <= WaveLds<D4>::NUMS * sizeof(D4),
+                  "the binary64 merge must fit the dual-number wave's LDS");
     const int64_t mark = T.used;
     Arr<double> rec;
     int n = 0;
