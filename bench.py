@@ -89,6 +89,55 @@ def measured_traffic(kernel):
     return float(kv["hbm_bytes_per_launch"])
 
 
+def stress_leg(bt, W, np, torch):
+    """One batch of 2048 options of the stress generator, and the long put."""
+    res = {}
+    batch = W.stress_book(16384, seed=5)[:2048]
+    pick = np.random.default_rng(66).choice(len(batch), 256, replace=False)
+    best, _ = bt.bt_autotune(batch[np.sort(pick)], reps=1)
+    tune = {k: best[k] for k in ("band_levels", "wgs_per_cu")}
+    for greeks in (False, True):
+        # Greeks on the first 512 options of the batch (four times the work per option)
+        b = batch[:512] if greeks else batch
+        name = "batch_512_greeks" if greeks else "batch_2048_prices"
+        bk = bt.Book(b, tune=tune, greeks=greeks, graph=True)
+        call = bk.price_grad if greeks else bk.price
+        log(f"{name}: capture and first call")
+        call()
+        torch.cuda.synchronize()
+        log(f"{name}: timed call")
+        t0 = time.perf_counter()
+        call()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        n_over = int(np.sum(bk.results()["status"] == bt.BT_EOVERFLOW))
+        log(f"{name}: {dt:.1f} s; re-pricing {n_over} options with larger levels")
+        bk.resolve_overflow(grad=greeks)
+        ok = bool(np.all(bk.results()["status"] == 0))
+        bk.close()
+        res[name] = dict(options_per_s=len(b) / dt, ms=dt * 1e3, tree_nodes_per_s=W.nodes(b) / dt, ok=ok,
+                         options_needing_larger_levels=n_over)
+        log(f"stress {name}: {res[name]}")
+    res["batch_tune"] = tune
+    lp = W.long_put()
+    for greeks in (False, True):
+        log(f"put N=20000, greeks={greeks}")
+        bk = bt.Book(lp, greeks=greeks)
+        call = bk.price_grad if greeks else bk.price
+        call()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        call()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        bk.resolve_overflow(grad=greeks)
+        res["put_N20000_" + ("greeks" if greeks else "prices")] = dict(ms=dt * 1e3, tree_nodes_per_s=W.nodes(lp) / dt,
+                                                                    ok=bool(np.all(bk.results()["status"] == 0)))
+        bk.close()
+    log(f"stress: {res}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +145,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-extra", action="store_true", help="skip the mixed-book and plain legs")
+    ap.add_argument("--stress", action="store_true",
+                    help="also time the stress mix: one batch of 2048 options of the 16384-option "
+                         "generator (N log-uniform in [64, 8192]) through a captured graph with the "
+                         "autotuner's choice (prices; Greeks on its first 512), and the N=20000 put")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB from one device buffer to another (the known-size "
                          "reference for the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -276,6 +329,9 @@ def main():
                        "flops_per_step": flops, "launches_per_step": n_launch,
                        "flops_per_launch": flops / n_launch,
                        "ms_per_launch": kernel_ms[dom] / n_launch}
+
+    if args.stress:
+        out["stress"] = stress_leg(bt, W, np, torch)
 
     cores = cpu_cores()
     if not args.no_cpu:

@@ -30,6 +30,7 @@
 #include <cstring>
 #include <new>
 #include <vector>
+#include <functional>
 
 #include "../../include/bt.h"
 #include "bt_device.hpp"
@@ -1009,9 +1010,14 @@ int bt_book_resolve_overflow(bt_book *book, bt_result *d_out, bt_grad *d_grad, v
     const int64_t base_pool = book->tune.pool_points > 0 ? book->tune.pool_points
                                                          : (book->greeks ? DEFAULT_POOL_POINTS / 4 : DEFAULT_POOL_POINTS);
     const bool had = !idx.empty();
-    for (int mult = 4; !idx.empty() && mult <= 1024; mult *= 4) {
+    // prices the options ids with level buffers `mult` times the book's;
+    // a set whose book does not fit in device memory is halved (a single
+    // option that does not fit stays overflowed)
+    std::vector<int> still;
+    const std::function<int(const std::vector<int> &, int)> price_set = [&](const std::vector<int> &ids,
+                                                                            int mult) -> int {
         std::vector<bt_params> sub;
-        for (int i : idx) sub.push_back(book->params[i]);
+        for (int i : ids) sub.push_back(book->params[i]);
         bt_tune t = book->tune;
         t.flags = d_grad ? BT_TUNE_GREEKS : 0;
         t.level_factor = base_lf * mult;
@@ -1019,15 +1025,27 @@ int bt_book_resolve_overflow(bt_book *book, bt_result *d_out, bt_grad *d_grad, v
         t.wgs_per_cu = 1;
         bt_book *sb = nullptr;
         int rc = bt_book_create(sub.data(), (int32_t)sub.size(), &t, &sb);
-        if (rc != BT_OK) return rc;
         bt_result *d_sub = nullptr;
         bt_grad *d_subg = nullptr;
-        if (hipMalloc(&d_sub, sizeof(bt_result) * sub.size()) != hipSuccess ||
-            (d_grad && hipMalloc(&d_subg, sizeof(bt_grad) * sub.size()) != hipSuccess)) {
+        if (rc == BT_OK && (hipMalloc(&d_sub, sizeof(bt_result) * sub.size()) != hipSuccess ||
+                            (d_grad && hipMalloc(&d_subg, sizeof(bt_grad) * sub.size()) != hipSuccess))) {
             (void)hipGetLastError();
+            rc = BT_ENOMEM;
+        }
+        const bool no_room = rc == BT_ENOMEM || (rc == BT_EHIP && g_last_hip == (int)hipErrorOutOfMemory);
+        if (rc != BT_OK) {
             if (d_sub) (void)hipFree(d_sub);
-            bt_book_destroy(sb);
-            return BT_ENOMEM;
+            if (sb) bt_book_destroy(sb);
+            if (!no_room) return rc;
+            (void)hipGetLastError();
+            if (ids.size() == 1) {
+                still.push_back(ids[0]);
+                return BT_OK;
+            }
+            const size_t h = ids.size() / 2;
+            const int r1 = price_set(std::vector<int>(ids.begin(), ids.begin() + h), mult);
+            if (r1 != BT_OK) return r1;
+            return price_set(std::vector<int>(ids.begin() + h, ids.end()), mult);
         }
         rc = d_grad ? bt_book_price_grad(sb, d_sub, d_subg, stream) : bt_book_price(sb, d_sub, stream);
         std::vector<bt_result> sres(sub.size());
@@ -1043,12 +1061,18 @@ int bt_book_resolve_overflow(bt_book *book, bt_result *d_out, bt_grad *d_grad, v
         if (d_subg) (void)hipFree(d_subg);
         bt_book_destroy(sb);
         if (rc != BT_OK) return rc;
-        std::vector<int> still;
-        for (size_t j = 0; j < idx.size(); j++) {
-            res[idx[j]] = sres[j];
-            if (d_grad) grd[idx[j]] = sgrd[j];
-            if (sres[j].status == BT_EOVERFLOW) still.push_back(idx[j]);
+        for (size_t j = 0; j < ids.size(); j++) {
+            res[ids[j]] = sres[j];
+            if (d_grad) grd[ids[j]] = sgrd[j];
+            if (sres[j].status == BT_EOVERFLOW) still.push_back(ids[j]);
         }
+        return BT_OK;
+    };
+    for (int mult = 4; !idx.empty() && mult <= 1024; mult *= 4) {
+        still.clear();
+        const int rc = price_set(idx, mult);
+        if (rc != BT_OK) return rc;
+        std::sort(still.begin(), still.end());
         idx.swap(still);
     }
     if (had) {
