@@ -176,7 +176,10 @@ int bt_book_price_grad(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *s
  * after bt_book_price_grad it is that call's Greeks buffer, and the
  * re-pricing then also writes the Greeks of those options.  *remaining (may
  * be NULL) receives the number of options still overflowing.  Synchronous;
- * allocates temporary device memory only when some option overflowed. */
+ * allocates temporary device memory only when some option overflowed, one
+ * re-pricing book at a time: a set of options whose book does not fit in
+ * device memory is re-priced in halves, and a single option that does not
+ * fit even alone stays BT_EOVERFLOW (counted in *remaining). */
 int bt_book_resolve_overflow(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream,
                              int32_t *remaining);
 
