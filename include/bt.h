@@ -97,12 +97,21 @@ typedef struct {
  * "library's choice".
  *   wgs_per_cu   persistent workgroups per compute unit (default 2)
  *   level_factor capacity of one tree level, in points per node (default
- *                32; a workgroup's private level holds at least 65536)
+ *                32); a workgroup's private level holds at least
+ *                65536 * max(1, level_factor / 32) points, and 16N for a
+ *                book with the buyer of a call or a bull spread with costs
+ *                at N steps
  *   pool_points  per-workgroup temporaries of the nodes with many
  *                breakpoints, in points (default 262144; 65536 for a
  *                BT_TUNE_GREEKS book); a node too big for its wave's share
- *                takes its temporaries from a book-wide arena of at least
- *                2^28 doubles (5x that for Greeks) instead
+ *                takes its temporaries from its party's arena instead.
+ *                bt_book_create sizes each party's arena from the book's
+ *                options (the buyer sides of calls and bull spreads with
+ *                costs, which grow the largest nodes): at least 2^28
+ *                doubles (5x that for Greeks, and at least 64 pools), at
+ *                most 2^31 doubles or an eighth of the free device memory.
+ *                Options whose nodes outgrow it end BT_EOVERFLOW, for
+ *                bt_book_resolve_overflow
  *   flags        BT_TUNE_TIMING: record HIP events around every kernel of
  *                every pricing call (read with bt_book_timings; not for use
  *                under graph capture);

@@ -45,7 +45,8 @@ constexpr int MIN_BAND = 2;
 constexpr int DEFAULT_LEVEL_FACTOR = 32;   // breakpoints per node the band buffers hold
 constexpr int64_t DEFAULT_POOL_POINTS = (int64_t)1 << 18;   // per-workgroup pool, in breakpoints
 constexpr int64_t MIN_PRIVATE_POINTS = (int64_t)1 << 16;    // floor of a private level, in breakpoints
-constexpr int64_t DEFAULT_ARENA_DOUBLES = (int64_t)1 << 28;  // shared by one launch's big nodes
+constexpr int64_t DEFAULT_ARENA_DOUBLES = (int64_t)1 << 28;  // floor of one party's big-node arena
+constexpr int64_t MAX_ARENA_DOUBLES = (int64_t)1 << 31;      // ceiling of the arena estimate (16 GiB)
 
 // One tree side: option `opt`, party `side` (0 seller, 1 buyer); offsets of
 // its two band-boundary level buffers (doubles) and index arrays (ints).
@@ -88,7 +89,8 @@ struct KArgs {
     int n_p0;
     bt_grad *grad;          // Greeks output (dual-number launches only)
     double *arena;          // temporaries of big nodes that outgrow a wave's pool slice
-    int64_t arena_cap;      // doubles per party (the buyer's half follows the seller's)
+    int64_t arena_cap[2];   // doubles of the seller's (0) and the buyer's (1) arena
+    int64_t arena_base[2];  // their offsets in `arena` (the buyer's follows the seller's)
     unsigned long long *arena_ctr;  // bump counters, one per (band, party) launch
 };
 
@@ -107,8 +109,8 @@ __device__ __forceinline__ double *arena_take(const KArgs &A, int ctr, int64_t n
     unsigned long long pos = 0;
     if ((threadIdx.x & 63) == 0) pos = atomicAdd(A.arena_ctr + ctr, (unsigned long long)n);
     pos = __shfl(pos, 0, 64);
-    if ((int64_t)pos + n > A.arena_cap) return nullptr;
-    return A.arena + (int64_t)(ctr & 1) * A.arena_cap + pos;
+    if ((int64_t)pos + n > A.arena_cap[ctr & 1]) return nullptr;
+    return A.arena + A.arena_base[ctr & 1] + pos;
 }
 
 // Exclusive prefix sum over the workgroup; *total gets the sum.
@@ -682,6 +684,34 @@ int dalloc(T **p, size_t count)
     return BT_OK;
 }
 
+// Doubles of arena that one party of a book may need: the temporaries of
+// the nodes too big for a wave's pool slice (`slice` doubles).  The buyer of
+// a call or a bull spread with costs grows nodes of up to about 3N
+// breakpoints (2.7N on the N = 5000 call at k = 1 %), so a node's two
+// children hold up to about 6N; a bull spread's seller stays near N; puts
+// stay at a few points.  Each such tree side counts three big nodes per
+// level, each taking up to twice its need (a wave keeps its chunk for the
+// whole launch and grows it by doubling), and every tree side of the book
+// runs in the same launch.  The estimate only sizes the allocation: an
+// option whose nodes outgrow it is reported BT_EOVERFLOW, and
+// bt_book_resolve_overflow re-prices it.
+int64_t arena_estimate(const std::vector<Model> &models, const std::vector<Item> &items, int side,
+                       int64_t slice, int64_t nt)
+{
+    int64_t est = 0;
+    for (const Item &it : items) {
+        const Model &m = models[it.opt];
+        if (it.side != side || !(m.k > 0)) continue;
+        int64_t M = 0;
+        if (side == 1 && m.payoff != BT_PUT) M = 6 * (int64_t)it.N;
+        if (side == 0 && m.payoff == BT_BULL) M = it.N;
+        const int64_t need = (64 * M + 4096) * nt;   // as big_need on the device
+        if (need > slice) est += 3 * 2 * need;
+        if (est >= MAX_ARENA_DOUBLES) return MAX_ARENA_DOUBLES;
+    }
+    return est;
+}
+
 int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
 {
     std::vector<Model> models(n);
@@ -703,7 +733,7 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
     const int64_t pool_pts = (tune && tune->pool_points > 0) ? (int64_t)tune->pool_points
                                                              : (greeks ? DEFAULT_POOL_POINTS / 4 : DEFAULT_POOL_POINTS);
     const int64_t pool = pool_pts * 4 * nt;
-    const int64_t arena = std::max<int64_t>(DEFAULT_ARENA_DOUBLES * nt, 64 * pool);
+    const int64_t arena_floor = std::max<int64_t>(DEFAULT_ARENA_DOUBLES * nt, 64 * pool);
 
     // tree sides (buyer first: the longer recursion), longest tree first
     std::vector<int> order;
@@ -757,12 +787,32 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
     const int grid = std::max(1, std::min(max_tasks, resident));
     const int grid_p0 = std::max(1, std::min((int)p0.size(), resident));
     const int ws_wgs = grid;
+    // each party's arena: its estimate, at least the floor, and beyond the
+    // floor at most an eighth of the device's free memory
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        (void)hipGetLastError();
+        free_b = 0;
+    }
+    int64_t arena[2];
+    for (int side = 0; side < 2; side++) {
+        const int64_t e = std::min<int64_t>(arena_estimate(models, items, side, pool / NWAVE, nt),
+                                            (int64_t)(free_b / 8 / sizeof(double)));
+        arena[side] = round_up(std::max(arena_floor, e), 32);
+    }
 
     KArgs a{};
     // a private level holds the records of WG + 1 columns: lf breakpoints per
-    // node on average, and never fewer than MIN_PRIVATE_POINTS in all (a few
-    // nodes of a level can hold most of its breakpoints)
-    const int64_t pcap = round_up(std::max((int64_t)lf * (WG + 1), MIN_PRIVATE_POINTS) * 3 * nt + (WG + 1) * nt, 32);
+    // node on average, and never fewer than MIN_PRIVATE_POINTS (scaled up
+    // with lf) in all, since a few nodes of a level can hold most of its
+    // breakpoints.  The buyer of a call or a bull spread with costs reaches
+    // about 2N breakpoints per node (16175 at N = 8129) with several such
+    // nodes in a block, so such a book's levels get 16N points.
+    int64_t ppts = std::max((int64_t)lf * (WG + 1), MIN_PRIVATE_POINTS * std::max(1, lf / DEFAULT_LEVEL_FACTOR));
+    for (const Item &it : items)
+        if (it.side == 1 && models[it.opt].k > 0 && models[it.opt].payoff != BT_PUT)
+            ppts = std::max(ppts, 16 * (int64_t)it.N);
+    const int64_t pcap = round_up(ppts * 3 * nt + (WG + 1) * nt, 32);
     const Caps sc = small_caps();
     a.oStab = 0;
     const int64_t stab_n = std::max<int64_t>((2 * (int64_t)WG + BAND + 8) * nt, 2 * (int64_t)n_max + 3);
@@ -804,7 +854,7 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
         (rc = dalloc(&b->d_lvl, lbuf)) || (rc = dalloc(&b->d_lvli, ibuf)) ||
         (rc = dalloc(&b->d_ws, 2 * a.ws_side)) || (rc = dalloc(&b->d_wsi, 2 * a.wsi_side)) ||
         (rc = dalloc(&b->d_wsp, a.p0_doubles * grid_p0)) ||
-        (rc = dalloc(&b->d_arena, 2 * arena)) || (rc = dalloc(&b->d_arena_ctr, 2 * (size_t)nbands_max))) {
+        (rc = dalloc(&b->d_arena, arena[0] + arena[1])) || (rc = dalloc(&b->d_arena_ctr, 2 * (size_t)nbands_max))) {
         book_free(b);
         return rc;
     }
@@ -832,7 +882,10 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
     a.p0_queue = p0q;
     a.p0_sched = p0s;
     a.arena = b->d_arena;
-    a.arena_cap = arena;
+    a.arena_cap[0] = arena[0];
+    a.arena_cap[1] = arena[1];
+    a.arena_base[0] = 0;
+    a.arena_base[1] = arena[0];
     a.arena_ctr = b->d_arena_ctr;
     b->args = a;
     HIPCHK(hipStreamCreateWithFlags(&b->s_ask, hipStreamNonBlocking));

@@ -101,3 +101,26 @@ def test_autotuner_returns_its_fastest_candidate():
     assert a.results().tobytes() == t.results().tobytes()
     a.close()
     t.close()
+
+
+def test_arena_sized_from_the_book_prices_high_cost_calls_in_one_pass():
+    # a quarter of the mixed book: its high-cost call buyers grow nodes of
+    # thousands of breakpoints, and all of them share one launch per band;
+    # the book's arena is sized for them, so nothing overflows, and the
+    # results are those of a book whose larger pools keep the big nodes out
+    # of the arena
+    b = W.mixed_book(4096, seed=3)[:1024]
+    say(f"case: arena sizing, {len(b)} options of the mixed book")
+    bk = bt.Book(b)
+    bk.price()
+    got = bk.results()
+    bk.close()
+    assert int(np.sum(got["status"] == bt.BT_EOVERFLOW)) == 0
+    assert np.all(got["status"] == 0)
+    say("case: arena sizing, reference with 4x pools")
+    ref = bt.Book(b, tune=dict(pool_points=1 << 20))
+    ref.price()
+    assert ref.resolve_overflow() == 0
+    want = ref.results()
+    ref.close()
+    assert got.tobytes() == want.tobytes()
