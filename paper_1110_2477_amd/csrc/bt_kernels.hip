@@ -10,7 +10,11 @@
 // Section 4.2, with the region that would wait for a neighbour recomputed
 // instead).  Consecutive bands are separated by kernel boundaries.  Band
 // tasks of all tree sides of a book are handed to persistent workgroups from
-// one counter per (band, party).
+// one counter per (launch, party).  The tree sides are aligned at the root:
+// a tree side of nb bands runs its band r in launch r + nbands_max - nb, so
+// every tree side ends in the last launch.  Nodes grow toward the root, so
+// the expensive bands of trees of different N run side by side instead of
+// one after another.
 //
 // Inside a block one lane owns one column; a level's records are packed
 // variable-length PWL functions in per-workgroup buffers, the band's input
@@ -65,7 +69,7 @@ struct KArgs {
     const Model *models;
     const Item *items;
     const Task *tasks;
-    const int *task_off;    // [2 * nbands_max + 1]: tasks of (band r, side s) at r*2+s
+    const int *task_off;    // [2 * nbands_max + 1]: tasks of (launch L, side s) at L*2+s
     int *band_ctr;          // persistent-workgroup counters, [2 * nbands_max]
     unsigned long long *fill;   // band-buffer fill counters
     int *failed;            // per item
@@ -190,11 +194,12 @@ __global__ void bt_init_kernel(KArgs A)
     }
 }
 
-// One band task: block `blk` of band `r` of tree side `item`.
+// One band task of launch `launch`: block `blk` of tree side `item`, whose
+// band that launch runs.
 // s_chunk / s_chunk_cap: each wave's arena chunk (kept for the whole launch
 // and reused by the wave's later big nodes; grown when a node needs more).
 template <int SIDE, typename T>
-__device__ __forceinline__ void band_task(const KArgs &A, int r, int item, int blk, int64_t *sh, int *sflag,
+__device__ __forceinline__ void band_task(const KArgs &A, int launch, int item, int blk, int64_t *sh, int *sflag,
                           double **s_chunk, int64_t *s_chunk_cap, T *s_win)
 {
     constexpr int NT = sizeof(T) / sizeof(double);
@@ -206,6 +211,7 @@ __device__ __forceinline__ void band_task(const KArgs &A, int r, int item, int b
     const Model md = A.models[I.opt];
     const Inputs<T> in = inputs_of(md, T{});
     const int N = I.N;
+    const int r = launch - (A.nbands_max - I.nbands);   // the tree side's band
     const int band = A.band, block_cols = WG - band;
     const int t_top = N - r * band;
     const int t_bot = t_top - band + 1 > 0 ? t_top - band + 1 : 0;
@@ -326,7 +332,7 @@ __device__ __forceinline__ void band_task(const KArgs &A, int r, int item, int b
                     if (attempt == 1) {
                         if (chunk_cap < 2 * need) {
                             const int64_t take = 2 * need > 2 * chunk_cap ? 2 * need : 2 * chunk_cap;
-                            double *p = arena_take(A, 2 * r + SIDE, take);
+                            double *p = arena_take(A, 2 * launch + SIDE, take);
                             if (!p) break;
                             chunk = p;
                             chunk_cap = take;
@@ -438,7 +444,8 @@ __device__ __forceinline__ void band_task(const KArgs &A, int r, int item, int b
     __syncthreads();
 }
 
-// Band r of every tree side of one party, on persistent workgroups.
+// Launch r of one party: the bands of its tree sides that this launch runs
+// (see the file header), on persistent workgroups.
 template <int SIDE, typename T>
 __global__ __launch_bounds__(WG) void bt_band_kernel(KArgs A, int r)
 {
@@ -756,22 +763,24 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
             items.push_back(it);
         }
     }
-    // band tasks, grouped by (band, side)
+    // band tasks, grouped by (launch, side); launch L runs band
+    // L - (nbands_max - nbands) of each tree side, so that all end together
     std::vector<Task> tasks;
     std::vector<int> task_off(2 * (size_t)nbands_max + 1, 0);
     std::vector<int> ntasks(2 * (size_t)nbands_max, 0);
-    for (int r = 0; r < nbands_max; r++) {
+    for (int L = 0; L < nbands_max; L++) {
         for (int side = 0; side < 2; side++) {
-            task_off[2 * r + side] = (int)tasks.size();
+            task_off[2 * L + side] = (int)tasks.size();
             for (int q = 0; q < (int)items.size(); q++) {
                 const Item &it = items[q];
-                if (it.side != side || r >= it.nbands) continue;
+                const int r = L - (nbands_max - it.nbands);
+                if (it.side != side || r < 0) continue;
                 const int t_top = it.N - r * band;
                 const int t_bot = std::max(t_top - band + 1, 0);
                 const int nb = (t_bot + 1 + block_cols - 1) / block_cols;
                 for (int bk = 0; bk < nb; bk++) tasks.push_back(Task{q, bk});
             }
-            ntasks[2 * r + side] = (int)tasks.size() - task_off[2 * r + side];
+            ntasks[2 * L + side] = (int)tasks.size() - task_off[2 * L + side];
         }
     }
     task_off[2 * (size_t)nbands_max] = (int)tasks.size();
