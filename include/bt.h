@@ -109,7 +109,7 @@ typedef struct {
  *                options (the buyer sides of calls and bull spreads with
  *                costs, which grow the largest nodes): at least 2^28
  *                doubles (5x that for Greeks, and at least 64 pools), at
- *                most 2^31 doubles or an eighth of the free device memory.
+ *                most 2^32 doubles or an eighth of the free device memory.
  *                Options whose nodes outgrow it end BT_EOVERFLOW, for
  *                bt_book_resolve_overflow
  *   flags        BT_TUNE_TIMING: record HIP events around every kernel of

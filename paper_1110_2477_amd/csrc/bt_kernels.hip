@@ -50,7 +50,7 @@ constexpr int DEFAULT_LEVEL_FACTOR = 32;   // breakpoints per node the band buff
 constexpr int64_t DEFAULT_POOL_POINTS = (int64_t)1 << 18;   // per-workgroup pool, in breakpoints
 constexpr int64_t MIN_PRIVATE_POINTS = (int64_t)1 << 16;    // floor of a private level, in breakpoints
 constexpr int64_t DEFAULT_ARENA_DOUBLES = (int64_t)1 << 28;  // floor of one party's big-node arena
-constexpr int64_t MAX_ARENA_DOUBLES = (int64_t)1 << 31;      // ceiling of the arena estimate (16 GiB)
+constexpr int64_t MAX_ARENA_DOUBLES = (int64_t)1 << 32;      // ceiling of the arena estimate (32 GiB)
 
 // One tree side: option `opt`, party `side` (0 seller, 1 buyer); offsets of
 // its two band-boundary level buffers (doubles) and index arrays (ints).
@@ -693,27 +693,34 @@ int dalloc(T **p, size_t count)
 
 // Doubles of arena that one party of a book may need: the temporaries of
 // the nodes too big for a wave's pool slice (`slice` doubles).  The buyer of
-// a call or a bull spread with costs grows nodes of up to about 3N
-// breakpoints (2.7N on the N = 5000 call at k = 1 %), so a node's two
-// children hold up to about 6N; a bull spread's seller stays near N; puts
-// stay at a few points.  Each such tree side counts three big nodes per
-// level, each taking up to twice its need (a wave keeps its chunk for the
-// whole launch and grows it by doubling), and every tree side of the book
-// runs in the same launch.  The estimate only sizes the allocation: an
-// option whose nodes outgrow it is reported BT_EOVERFLOW, and
+// a call or a bull spread with costs grows nodes of up to about 2N to 2.7N
+// breakpoints (13512 at N = 5000, 16175 at N = 8129), so a node's two
+// children hold up to about 5N; a bull spread's seller stays near N; puts
+// stay at a few points.  Tree sides are aligned at the root, so their
+// largest nodes meet in the same launches; near the root a tree side is one
+// task, so at most `conc` of them (the resident workgroups) hold big nodes
+// at once: the largest `conc` count three big nodes per level, each taking
+// up to twice its need (a wave keeps its chunk for the whole launch and
+// grows it by doubling).  The estimate only sizes the allocation: an option
+// whose nodes outgrow it is reported BT_EOVERFLOW, and
 // bt_book_resolve_overflow re-prices it.
 int64_t arena_estimate(const std::vector<Model> &models, const std::vector<Item> &items, int side,
-                       int64_t slice, int64_t nt)
+                       int64_t slice, int64_t nt, int conc)
 {
-    int64_t est = 0;
+    std::vector<int64_t> needs;
     for (const Item &it : items) {
         const Model &m = models[it.opt];
         if (it.side != side || !(m.k > 0)) continue;
         int64_t M = 0;
-        if (side == 1 && m.payoff != BT_PUT) M = 6 * (int64_t)it.N;
+        if (side == 1 && m.payoff != BT_PUT) M = 5 * (int64_t)it.N;
         if (side == 0 && m.payoff == BT_BULL) M = it.N;
         const int64_t need = (64 * M + 4096) * nt;   // as big_need on the device
-        if (need > slice) est += 3 * 2 * need;
+        if (need > slice) needs.push_back(need);
+    }
+    std::sort(needs.begin(), needs.end(), std::greater<int64_t>());
+    int64_t est = 0;
+    for (size_t i = 0; i < needs.size() && i < (size_t)conc; i++) {
+        est += 3 * 2 * needs[i];
         if (est >= MAX_ARENA_DOUBLES) return MAX_ARENA_DOUBLES;
     }
     return est;
@@ -805,7 +812,7 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
     }
     int64_t arena[2];
     for (int side = 0; side < 2; side++) {
-        const int64_t e = std::min<int64_t>(arena_estimate(models, items, side, pool / NWAVE, nt),
+        const int64_t e = std::min<int64_t>(arena_estimate(models, items, side, pool / NWAVE, nt, grid),
                                             (int64_t)(free_b / 8 / sizeof(double)));
         arena[side] = round_up(std::max(arena_floor, e), 32);
     }
