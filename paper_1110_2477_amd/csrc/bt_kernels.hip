@@ -330,8 +330,12 @@ __device__ __forceinline__ void band_task(const KArgs &A, int launch, int item, 
                     double *tb = pool + w * slice;
                     int64_t tcap = slice;
                     if (attempt == 1) {
-                        if (chunk_cap < 2 * need) {
-                            const int64_t take = 2 * need > 2 * chunk_cap ? 2 * need : 2 * chunk_cap;
+                        if (chunk_cap < need) {
+                            // a quarter of headroom for the slow growth of a
+                            // tree side's nodes over the band; doubling when
+                            // a later node outgrows the chunk
+                            const int64_t grow = ((need + need / 4) + 31) & ~(int64_t)31;
+                            const int64_t take = grow > 2 * chunk_cap ? grow : 2 * chunk_cap;
                             double *p = arena_take(A, 2 * launch + SIDE, take);
                             if (!p) break;
                             chunk = p;
@@ -700,8 +704,8 @@ int dalloc(T **p, size_t count)
 // largest nodes meet in the same launches; near the root a tree side is one
 // task, so at most `conc` of them (the resident workgroups) hold big nodes
 // at once: the largest `conc` count three big nodes per level, each taking
-// up to twice its need (a wave keeps its chunk for the whole launch and
-// grows it by doubling).  The estimate only sizes the allocation: an option
+// up to twice its need (a wave takes 1.25 times its first need and keeps the
+// chunk for the whole launch, doubling it when a later node outgrows it).  The estimate only sizes the allocation: an option
 // whose nodes outgrow it is reported BT_EOVERFLOW, and
 // bt_book_resolve_overflow re-prices it.
 int64_t arena_estimate(const std::vector<Model> &models, const std::vector<Item> &items, int side,
@@ -749,16 +753,29 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
     const int64_t pool = pool_pts * 4 * nt;
     const int64_t arena_floor = std::max<int64_t>(DEFAULT_ARENA_DOUBLES * nt, 64 * pool);
 
-    // tree sides (buyer first: the longer recursion), longest tree first
+    // tree sides, buyer first (the longer recursion).  Within a party the
+    // sides whose nodes grow large (costly call and bull-spread buyers,
+    // costly bull-spread sellers) come first, then the longest trees: a
+    // launch's task list follows this order, so its slowest tasks start
+    // first
     std::vector<int> order;
     for (int i = 0; i < n; i++)
         if (models[i].valid) order.push_back(i);
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return models[x].N > models[y].N; });
+    const auto grows = [&](int i, int side) {
+        const Model &m = models[i];
+        return m.k > 0 && (side == 1 ? m.payoff != BT_PUT : m.payoff == BT_BULL);
+    };
     std::vector<Item> items;
     int64_t lbuf = 0, ibuf = 0, ctr = 0;
     int nbands_max = 0;
     for (int side = 1; side >= 0; side--) {
-        for (int i : order) {
+        std::vector<int> so(order);
+        std::stable_sort(so.begin(), so.end(), [&](int x, int y) {
+            const bool gx = grows(x, side), gy = grows(y, side);
+            return gx != gy ? gx : models[x].N > models[y].N;
+        });
+        for (int i : so) {
             Item it;
             it.opt = i; it.side = side; it.N = models[i].N;
             it.nbands = (it.N + 1 + band - 1) / band;
