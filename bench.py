@@ -172,8 +172,8 @@ def main():
         log(f"copied {n} bytes")
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build prices on a single MI355X "
-              "(options are independent; see DESIGN.md for how a book would shard). "
+        print("bench.py measures one GPU only: the library prices a book on a single MI355X "
+              "(options are independent, so a book would shard by option over several GPUs). "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
