@@ -177,10 +177,11 @@ int bt_book_price(bt_book *book, bt_result *d_out, void *stream);
  * BT_TUNE_GREEKS (else BT_ENOSUPP). */
 int bt_book_price_grad(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream);
 
-/* Completes a pricing call whose options overflowed the book's level
- * buffers (status BT_EOVERFLOW; a tree whose levels hold more breakpoints
- * than level_factor per node): waits for `stream`, then re-prices those
- * options on `stream` with buffers 4x larger each attempt (up to 1024x),
+/* Completes a pricing call whose options overflowed the book's buffers
+ * (status BT_EOVERFLOW: a tree whose band levels, private levels or
+ * big-node temporaries outgrew what the book sized for them): waits for
+ * `stream`, then re-prices those options on `stream` with level_factor and
+ * pool_points 4x larger each attempt (up to 1024x),
  * writing their results into d_out.  d_grad is NULL after bt_book_price;
  * after bt_book_price_grad it is that call's Greeks buffer, and the
  * re-pricing then also writes the Greeks of those options.  *remaining (may
