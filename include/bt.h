@@ -228,8 +228,15 @@ int bt_autotune(const bt_params *h_params, int32_t n, const bt_tune *base, const
                 int32_t reps, void *stream, bt_tune *best, double *ms);
 
 /* Plain single-option pricing: host in, host out, synchronous on the null
- * stream.  Uses a cached one-option book per calling thread. */
+ * stream.  Uses a cached one-option book per calling thread, kept until
+ * bt_shutdown on that thread. */
 int bt_price(const bt_params *p, bt_result *out);
+
+/* Frees what bt_price keeps between calls on the calling thread (its cached
+ * one-option book and result buffer; synchronises the device first).  Books
+ * from bt_book_create are not affected, and a later bt_price builds a new
+ * cache.  Safe to call at any time, also repeatedly.  Returns BT_OK. */
+int bt_shutdown(void);
 
 /* Tree constants the library derives for one option on the host (u, d, r,
  * rho = 1/r, p = (r-d)/(u-d)); BT_EINVAL if the option is invalid. */

@@ -23,7 +23,8 @@ EUROPEAN, COST_AT_T0 = 1, 2
 
 # Function names declared in include/bt.h.
 ABI_FUNCTIONS = ("bt_autotune", "bt_book_create", "bt_book_info", "bt_book_price", "bt_book_price_grad",
-                 "bt_book_resolve_overflow", "bt_book_timings", "bt_book_destroy", "bt_price", "bt_model_constants", "bt_strerror",
+                 "bt_book_resolve_overflow", "bt_book_timings", "bt_book_destroy", "bt_price", "bt_shutdown",
+                 "bt_model_constants", "bt_strerror",
                  "bt_version", "bt_last_hip_error")
 
 
@@ -78,13 +79,14 @@ def lib():
     L.bt_autotune.argtypes = [vp, i32, vp, vp, i32, i32, vp, vp, dp]
     L.bt_book_destroy.restype = None
     L.bt_price.argtypes = [vp, vp]
+    L.bt_shutdown.argtypes = []
     L.bt_model_constants.argtypes = [vp, dp, dp, dp, dp, dp]
     L.bt_strerror.argtypes = [ctypes.c_int]
     L.bt_strerror.restype = ctypes.c_char_p
     L.bt_version.argtypes = []
     L.bt_last_hip_error.argtypes = []
     for f in ("bt_autotune", "bt_book_create", "bt_book_info", "bt_book_price", "bt_book_price_grad", "bt_book_timings", "bt_book_resolve_overflow",
-              "bt_price", "bt_model_constants", "bt_version", "bt_last_hip_error"):
+              "bt_price", "bt_shutdown", "bt_model_constants", "bt_version", "bt_last_hip_error"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -205,6 +207,11 @@ def bt_price(params):
     out = np.zeros(1, dtype=RESULT_DTYPE)
     _check(lib().bt_price(p.ctypes.data, out.ctypes.data), "bt_price")
     return out[0]
+
+
+def bt_shutdown():
+    """Frees bt_price's cached book of the calling thread."""
+    _check(lib().bt_shutdown(), "bt_shutdown")
 
 
 def bt_model_constants(params):

@@ -573,6 +573,10 @@ __global__ void bt_reset_kernel(KArgs A, int64_t n_fill)
 // Host side.
 // ---------------------------------------------------------------------------
 thread_local int g_last_hip = 0;
+// What bt_price keeps between calls on a thread (freed by bt_shutdown).
+thread_local bt_result *t_price_res = nullptr;
+thread_local bt_book *t_price_book = nullptr;
+thread_local int t_price_N = -1;
 
 #define HIPCHK(call)                                   \
     do {                                               \
@@ -1278,9 +1282,9 @@ int bt_price(const bt_params *p, bt_result *out)
     if (!p || !out) return BT_EINVAL;
     // one cached book per thread, rebuilt when N changes (the band tasks
     // depend on N only); otherwise only the option's constants are replaced
-    thread_local bt_result *d_res = nullptr;
-    thread_local bt_book *cache = nullptr;
-    thread_local int cache_N = -1;
+    bt_result *&d_res = t_price_res;
+    bt_book *&cache = t_price_book;
+    int &cache_N = t_price_N;
     if (!d_res) HIPCHK(hipMalloc(&d_res, sizeof(bt_result)));
     Model m;
     const bool ok = derive(*p, m);
@@ -1298,6 +1302,20 @@ int bt_price(const bt_params *p, bt_result *out)
     if (rc == BT_OK) rc = bt_book_resolve_overflow(cache, d_res, nullptr, nullptr, nullptr);
     if (rc != BT_OK) return rc;
     HIPCHK(hipMemcpy(out, d_res, sizeof(bt_result), hipMemcpyDeviceToHost));
+    return BT_OK;
+}
+
+int bt_shutdown(void)
+{
+    if (t_price_book) {
+        bt_book_destroy(t_price_book);
+        t_price_book = nullptr;
+    }
+    t_price_N = -1;
+    if (t_price_res) {
+        (void)hipFree(t_price_res);
+        t_price_res = nullptr;
+    }
     return BT_OK;
 }
 

@@ -77,6 +77,22 @@ def test_single_put_n100_book_and_plain():
     assert r["ask"] == res[0]["ask"] and r["bid"] == res[0]["bid"] and r["price0"] == res[0]["price0"]
 
 
+def test_shutdown_releases_the_bt_price_cache():
+    # bt_shutdown frees the calling thread's cached book; later calls build a
+    # new one and give the same bytes, also for an option of another N
+    b = W.book([dict(S0=100.0, K=100.0, R=0.05, sigma=0.2, T=1.0, k=0.005, N=100, payoff=W.PUT),
+                dict(S0=100.0, K=95.0, K2=110.0, R=0.03, sigma=0.25, T=0.5, k=0.01, N=257, payoff=W.BULL)])
+    say("case: bt_price around bt_shutdown")
+    first = [bt.bt_price(p).tobytes() for p in b]
+    bt.bt_shutdown()
+    bt.bt_shutdown()
+    again = [bt.bt_price(p).tobytes() for p in b[::-1]][::-1]
+    assert first == again
+    bt.bt_shutdown()
+    check(b, bt.price_book(b))
+    assert first == [bt.price_book(b[i:i + 1])[0].tobytes() for i in range(len(b))]
+
+
 def test_random_small_book():
     b = W.random_small(240, seed=7, n_max=300)
     say("case: random small book, 240 options, N <= 300, all payoffs and flags")
