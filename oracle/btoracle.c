@@ -18,6 +18,29 @@
  * -ffp-contract=off).  Every piecewise-linear (PWL) operation follows the
  * canonical definitions written out next to it; readings of the paper where
  * it is silent are listed in the design notes of the repository.
+ *
+ * What pins each function (a plausible mistake in it fails these tests):
+ *   pwl_canon, pwl_eval      tests/test_oracle_pwl.py (points, tails, lines)
+ *                            and every price test below
+ *   pwl_merge                test_oracle_pwl.py (pointwise max/min on a
+ *                            grid, crossings, ties); the worked example of
+ *                            Section 3; the superhedging LP (N <= 8)
+ *   pwl_scale                the worked example (110.1695 = 130 / 1.18)
+ *   pwl_clip                 brute-force inf-convolution (test_oracle_pwl);
+ *                            the LP for the ask; exact-rational recursion
+ *   env_scan_a, pwl_env      brute-force inf-convolution on random
+ *                            non-convex functions; stopping-time
+ *                            enumeration for the bid (N <= 4); exact-rational
+ *                            recursion (tests/test_oracle_exact.py, equal
+ *                            breakpoint counts for puts and calls)
+ *   model_init, upow         13.906 (Appendix); Black-Scholes convergence
+ *                            and put-call parity (European, k = 0)
+ *   crr_price                k = 0 ask = bid = CRR; 13.906
+ *   side_price               every test above; cost at t = 0 and the
+ *                            European variant against their LPs and
+ *                            enumerations; level N+1 against the one-step
+ *                            LP; spread monotone in k; trivial hedges
+ *   tangents (NT = 4 build)  tests/test_oracle_grad.py (central differences)
  */
 #include <math.h>
 #include <stdint.h>

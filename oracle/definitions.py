@@ -26,6 +26,19 @@ import scipy.sparse as sp
 from scipy.optimize import linprog
 
 PUT, CALL, BULL = 0, 1, 2
+EUROPEAN, COST_AT_T0 = 1, 2
+
+
+def _kt(k, t, flags):
+    """Cost rate at time t: none at t = 0 (Section 4.1) unless the variant
+    charges it there too."""
+    return k if (t >= 1 or (flags & COST_AT_T0)) else 0.0
+
+
+def _exercisable(t, N, flags):
+    """Times at which the holder may exercise: 0..N for the American option,
+    N only for the European variant; never at the extra time N+1."""
+    return t == N if (flags & EUROPEAN) else t <= N
 
 
 def _payoff(pay, S, K, K2):
@@ -56,8 +69,12 @@ def _nodes(N):
     return out[: 2 ** (N + 2) - 1]
 
 
-def ask_lp(S0, K, R, sigma, T, k, N, payoff=PUT, K2=0.0):
-    """Seller's superhedging price by linear programming on the path tree."""
+def ask_lp(S0, K, R, sigma, T, k, N, payoff=PUT, K2=0.0, flags=0):
+    """Seller's superhedging price by linear programming on the path tree.
+
+    The portfolio that arrives at a node must cover delivery there when the
+    holder may exercise at that time (every time 0..N, or N alone for the
+    European variant) and must be solvent at the extra time N+1."""
     u, r = _tree(S0, sigma, R, T, N)
     nodes = _nodes(N)
     n = len(nodes)
@@ -79,7 +96,7 @@ def ask_lp(S0, K, R, sigma, T, k, N, payoff=PUT, K2=0.0):
     for i in trade:
         t, j = nodes[i]
         S = S0 * u ** (2 * j - t)
-        kt = k if t >= 1 else 0.0
+        kt = _kt(k, t, flags)
         Sa, Sb = (1 + kt) * S, (1 - kt) * S
         for c in (2 * i + 1, 2 * i + 2):
             # X_c = r (X_i - Sa b_i + Sb s_i)
@@ -92,8 +109,10 @@ def ask_lp(S0, K, R, sigma, T, k, N, payoff=PUT, K2=0.0):
     ub_r, ub_c, ub_v, bub = [], [], [], []
     row = 0
     for i, (t, j) in enumerate(nodes):
+        if not (_exercisable(t, N, flags) or t == N + 1):
+            continue
         S = S0 * u ** (2 * j - t)
-        kt = k if t >= 1 else 0.0
+        kt = _kt(k, t, flags)
         Sa, Sb = (1 + kt) * S, (1 - kt) * S
         xi, ze = _payoff(payoff, S, K, K2) if t <= N else (0.0, 0.0)
         for Sx in (Sa, Sb):
@@ -109,13 +128,15 @@ def ask_lp(S0, K, R, sigma, T, k, N, payoff=PUT, K2=0.0):
     return res.fun
 
 
-def _stopping_times(N):
+def _stopping_times(N, flags=0):
     """All stopping times of the path tree with values in 0..N+1, each as the
-    set of path-tree node indices at which the buyer exercises."""
+    set of path-tree node indices at which the buyer exercises (N+1 means the
+    option is left unexercised, payoff (0, 0)).  For the European variant
+    the buyer can stop only at N or N+1."""
     def rec(i, t):
         if t == N + 1:
             return [(i,)]
-        out = [(i,)]
+        out = [(i,)] if _exercisable(t, N, flags) else []
         for a in rec(2 * i + 1, t + 1):
             for b in rec(2 * i + 2, t + 1):
                 out.append(a + b)
@@ -123,7 +144,12 @@ def _stopping_times(N):
     return rec(0, 0)
 
 
-def _bid_for(stop, nodes, S0, u, r, K, K2, k, N, payoff):
+def _bid_for(stop, nodes, S0, u, r, K, K2, k, N, payoff, flags=0):
+    """The most the buyer can borrow at t = 0 against exercising at the
+    stopping time `stop`: start from (-x, 0), trade at (1 + k_t) S and
+    (1 - k_t) S at every node strictly before the stopping time, and arrive
+    at each stopping node in the epigraph of the buyer's expense function
+    (payoff (0, 0) at N+1)."""
     stop = set(stop)
     # nodes strictly before tau: those with a stopping node strictly below them
     live = set()
@@ -147,7 +173,7 @@ def _bid_for(stop, nodes, S0, u, r, K, K2, k, N, payoff):
     for i in tr:
         t, j = nodes[i]
         S = S0 * u ** (2 * j - t)
-        kt = k if t >= 1 else 0.0
+        kt = _kt(k, t, flags)
         Sa, Sb = (1 + kt) * S, (1 - kt) * S
         for c in (2 * i + 1, 2 * i + 2):
             er += [row] * 4; ec += [X(c), X(i), B(i), Sv(i)]; ev += [1.0, -r, r * Sa, -r * Sb]
@@ -160,7 +186,7 @@ def _bid_for(stop, nodes, S0, u, r, K, K2, k, N, payoff):
     for i in sorted(stop):
         t, j = nodes[i]
         S = S0 * u ** (2 * j - t)
-        kt = k if t >= 1 else 0.0
+        kt = _kt(k, t, flags)
         Sa, Sb = (1 + kt) * S, (1 - kt) * S
         xi, ze = _payoff(payoff, S, K, K2) if t <= N else (0.0, 0.0)
         for Sx in (Sa, Sb):
@@ -177,15 +203,26 @@ def _bid_for(stop, nodes, S0, u, r, K, K2, k, N, payoff):
     return -res.fun
 
 
-def bid_enum(S0, K, R, sigma, T, k, N, payoff=PUT, K2=0.0):
-    """Buyer's price: the best over all stopping times of the path tree of the
-    amount that can be borrowed against exercising at that stopping time."""
+def _bid_chunk(args):
+    stops, S0, K, R, sigma, T, k, N, payoff, K2, flags = args
     u, r = _tree(S0, sigma, R, T, N)
     nodes = _nodes(N)
-    best = -math.inf
-    for stop in _stopping_times(N):
-        best = max(best, _bid_for(stop, nodes, S0, u, r, K, K2, k, N, payoff))
-    return best
+    return max(_bid_for(s, nodes, S0, u, r, K, K2, k, N, payoff, flags) for s in stops)
+
+
+def bid_enum(S0, K, R, sigma, T, k, N, payoff=PUT, K2=0.0, flags=0, workers=1):
+    """Buyer's price: the best over all stopping times of the path tree of the
+    amount that can be borrowed against exercising at that stopping time.
+    ``workers`` > 1 spreads the linear programs over processes (the value is
+    the same: a maximum)."""
+    stops = _stopping_times(N, flags)
+    if workers <= 1:
+        return _bid_chunk((stops, S0, K, R, sigma, T, k, N, payoff, K2, flags))
+    import multiprocessing as mp
+    step = max(1, len(stops) // (8 * workers))
+    jobs = [(stops[i:i + step], S0, K, R, sigma, T, k, N, payoff, K2, flags) for i in range(0, len(stops), step)]
+    with mp.get_context("fork").Pool(workers) as pool:
+        return max(pool.map(_bid_chunk, jobs))
 
 
 def count_stopping_times(N):

@@ -83,7 +83,7 @@ LP_CASES = [
 
 
 @pytest.mark.parametrize("case", LP_CASES)
-@pytest.mark.parametrize("N", [1, 2, 4, 7])
+@pytest.mark.parametrize("N", [1, 2, 4, 7, 8])
 def test_ask_equals_superhedging_lp(case, N):
     pay, K, K2, k, sig, R, T = case
     o = oracle.price(100.0, K, R, sig, T, k, N, payoff=pay, K2=K2, sides=1)
@@ -108,10 +108,79 @@ def test_bid_equals_stopping_time_enumeration_n3(case):
     assert o["bid"] == pytest.approx(b, rel=1e-10, abs=1e-10)
 
 
+# The two variants of the model: costs charged at t = 0 as well (the paper
+# charges none there, Section 4.1), and exercise at N only (European).  The
+# linear programs change only where the definition does: the cost rate of
+# the trades at t = 0, and the times at which delivery must be covered (the
+# seller) or the buyer may stop.
+VARIANT_CASES = [LP_CASES[0], LP_CASES[2], LP_CASES[4], LP_CASES[5]]
+
+
+@pytest.mark.parametrize("case", VARIANT_CASES)
+@pytest.mark.parametrize("flags", [oracle.COST_AT_T0, oracle.EUROPEAN, oracle.EUROPEAN | oracle.COST_AT_T0])
+@pytest.mark.parametrize("N", [2, 5])
+def test_variant_ask_equals_superhedging_lp(case, flags, N):
+    pay, K, K2, k, sig, R, T = case
+    o = oracle.price(100.0, K, R, sig, T, k, N, payoff=pay, K2=K2, flags=flags, sides=1)
+    lp = D.ask_lp(100.0, K, R, sig, T, k, N, payoff=pay, K2=K2, flags=flags)
+    assert o["ask"] == pytest.approx(lp, rel=1e-10, abs=1e-10)
+
+
+@pytest.mark.parametrize("case", VARIANT_CASES)
+@pytest.mark.parametrize("flags", [oracle.COST_AT_T0, oracle.EUROPEAN, oracle.EUROPEAN | oracle.COST_AT_T0])
+@pytest.mark.parametrize("N", [2, 3])
+def test_variant_bid_equals_stopping_time_enumeration(case, flags, N):
+    pay, K, K2, k, sig, R, T = case
+    o = oracle.price(100.0, K, R, sig, T, k, N, payoff=pay, K2=K2, flags=flags, sides=2)
+    b = D.bid_enum(100.0, K, R, sig, T, k, N, payoff=pay, K2=K2, flags=flags)
+    assert o["bid"] == pytest.approx(b, rel=1e-10, abs=1e-10)
+
+
+def test_variants_change_the_prices():
+    # the variant pins above would pass for an oracle that ignored the flags
+    # only if the flags did not matter: check that they do
+    # (the European variant of a call on a stock without dividends is worth
+    # the American call, so the put shows that flag)
+    for case, fl in ((LP_CASES[2], oracle.COST_AT_T0), (LP_CASES[0], oracle.EUROPEAN),
+                     (LP_CASES[4], oracle.COST_AT_T0), (LP_CASES[4], oracle.EUROPEAN)):
+        pay, K, K2, k, sig, R, T = case
+        base = oracle.price(100.0, K, R, sig, T, k, 5, payoff=pay, K2=K2)
+        v = oracle.price(100.0, K, R, sig, T, k, 5, payoff=pay, K2=K2, flags=fl)
+        assert abs(v["ask"] - base["ask"]) > 1e-3 and abs(v["bid"] - base["bid"]) > 1e-3
+
+
+def _enum_golden():
+    with open(os.path.join(GOLDEN, "bid_enumeration_n4.json")) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("i", [0, 1])
+def test_bid_equals_stopping_time_enumeration_n4(i):
+    # all 458,330 stopping times of the N = 4 path tree, each priced by an LP
+    # (tests/golden/make_bid_enumeration_n4.py, oracle.definitions only)
+    c = _enum_golden()[i]
+    assert c["stopping_times"] == D.count_stopping_times(4)
+    o = oracle.price(c["S0"], c["K"], c["R"], c["sigma"], c["T"], c["k"], c["N"], payoff=c["payoff"],
+                     K2=c["K2"], sides=2)
+    assert o["bid"] == pytest.approx(c["bid_enumeration"], rel=1e-10, abs=1e-10)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("i", [0, 1])
+def test_bid_enumeration_n4_recomputed(i):
+    # recomputes the stored enumeration (minutes on 8 cores)
+    c = _enum_golden()[i]
+    b = D.bid_enum(c["S0"], c["K"], c["R"], c["sigma"], c["T"], c["k"], c["N"], payoff=c["payoff"], K2=c["K2"],
+                   workers=os.cpu_count() or 1)
+    assert b == pytest.approx(c["bid_enumeration"], rel=1e-12, abs=1e-12)
+
+
 def test_stopping_time_counts():
     # one stopping time per choice "exercise here or continue on both branches"
     assert [D.count_stopping_times(n) for n in (2, 3, 4)] == [26, 677, 458330]
     assert len(D._stopping_times(2)) == 26
+    # European: stop at N or leave unexercised, per path: 2^(2^N)
+    assert [len(D._stopping_times(n, oracle.EUROPEAN)) for n in (1, 2, 3)] == [4, 16, 256]
 
 
 # ---------------------------------------------------------------------------
