@@ -33,6 +33,8 @@
  *                            enumeration for the bid (N <= 4); exact-rational
  *                            recursion (tests/test_oracle_exact.py, equal
  *                            breakpoint counts for puts and calls)
+ *   exp_nearest              decimal arithmetic at 60 digits
+ *                            (test_oracle_pins.py, model constants)
  *   model_init, upow         13.906 (Appendix); Black-Scholes convergence
  *                            and put-call parity (European, k = 0)
  *   crr_price                k = 0 ask = bid = CRR; 13.906
@@ -457,6 +459,24 @@ static void pwl_env(const pwl *F, num a, num b, pwl *V)
 /* S at node (t, c) = S0 u^(2c - t) by binary powering, costs k at t >= 1    */
 /* and none at t = 0.                                                        */
 /* ------------------------------------------------------------------------ */
+
+/* e^x as the binary64 number nearest to the real number e^x: the model's u
+ * and r are exponentials, and as binary64 numbers they are taken to be their
+ * correctly rounded values.  Summed in binary128 (113-bit significand): the
+ * argument is halved until |t| <= 1/16, the Taylor series of e^t is added
+ * term by term up to t^30/30!, and the sum is squared back as often; the
+ * binary128 result is within about 2^-100 (relative) of e^x for |x| <= 700,
+ * and it is rounded once to binary64.  Pinned against decimal arithmetic at
+ * 60 digits (tests/test_oracle_pins.py). */
+static double exp_nearest(double x)
+{
+    __float128 t = x, term = 1, sum = 1;
+    int s = 0;
+    while (t > (__float128)0.0625 || t < -(__float128)0.0625) { t = t / 2; s++; }
+    for (int n = 1; n <= 30; n++) { term = term * t / n; sum = sum + term; }
+    while (s-- > 0) sum = sum * sum;
+    return (double)sum;
+}
 enum { PAY_PUT = 0, PAY_CALL = 1, PAY_BULL = 2 };
 enum { FL_EUROPEAN = 1u, FL_COST_AT_T0 = 2u };
 
@@ -506,8 +526,9 @@ static int model_init(model *md, double S0, double K, double K2, double R, doubl
     double dt = T / (double)N;
     double sq = sqrt(dt);
     double lam = sigma * sq;
-    md->u = nc(exp(lam));
-    md->r = nc(exp(R * dt));
+    if (!(lam <= 700.0) || !(R * dt <= 700.0 && R * dt >= -700.0)) return -1;
+    md->u = nc(exp_nearest(lam));
+    md->r = nc(exp_nearest(R * dt));
     /* tangents: 0 = S0, 1 = sigma, 2 = R, 3 = k */
     if (NT >= 4) {
         md->S0.d[0] = 1.0;

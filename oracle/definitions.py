@@ -20,6 +20,7 @@ oracle's backward induction is an independent check.  ``infconv_brute`` is the
 rebalancing restriction of Section 3 evaluated by brute force.
 """
 import math
+from decimal import Context, Decimal
 
 import numpy as np
 import scipy.sparse as sp
@@ -50,10 +51,18 @@ def _payoff(pay, S, K, K2):
     return max(S - K, 0.0) - max(S - K2, 0.0), 0.0
 
 
+def exp_nearest(x):
+    """e^x as the binary64 number nearest to it (Section 4.1's u and r are
+    exponentials; their binary64 values are taken correctly rounded): the
+    exponential in 60-digit decimal arithmetic, then Python's correctly
+    rounded conversion to binary64."""
+    return float(Decimal(x).exp(Context(prec=60)))
+
+
 def _tree(S0, sigma, R, T, N):
     dt = T / N
-    u = math.exp(sigma * math.sqrt(dt))
-    r = math.exp(R * dt)
+    u = exp_nearest(sigma * math.sqrt(dt))
+    r = exp_nearest(R * dt)
     return u, r
 
 

@@ -6,9 +6,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "bt_pwl.hpp"
-
 #define BTHD __host__ __device__ inline
+
+#include "bt_model.hpp"
+#include "bt_pwl.hpp"
 
 namespace bt {
 
@@ -18,16 +19,6 @@ constexpr int SMALL_CAP = 12;    // points per stage on the interleaved fast pat
 
 enum { PAY_PUT = 0, PAY_CALL = 1, PAY_BULL = 2 };
 enum { F_EUROPEAN = 1u, F_COST_AT_T0 = 2u };
-
-// Tree constants of one option, derived on the host (Section 4.1):
-// u = exp(sigma sqrt(T/N)), d = 1/u, r = exp(R T/N), rho = 1/r,
-// p = (r - d)/(u - d).  sq = sqrt(T/N) and dt = T/N seed the Greeks.
-struct Model {
-    double S0, u, d, r, rho, p, K, K2, k, sq, dt;
-    int32_t N, payoff;
-    uint32_t flags;
-    int32_t valid;
-};
 
 // The model's inputs as numbers of type T: plain values, or for D4 the
 // values with their tangents seeded for (S0, sigma, R, k):

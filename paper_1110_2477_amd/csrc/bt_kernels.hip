@@ -589,32 +589,7 @@ thread_local int t_price_N = -1;
 
 // Derives the tree constants of Section 4.1 for one option; false if the
 // option is invalid (see bt_params in bt.h).
-bool derive(const bt_params &p, Model &m)
-{
-    std::memset(&m, 0, sizeof(m));
-    m.valid = 0;
-    if (!(p.N >= 1 && p.N <= BT_MAX_N)) return false;
-    if (!(std::isfinite(p.S0) && std::isfinite(p.K) && std::isfinite(p.R) && std::isfinite(p.sigma) &&
-          std::isfinite(p.T) && std::isfinite(p.k)))
-        return false;
-    if (!(p.S0 > 0.0 && p.K > 0.0 && p.sigma > 0.0 && p.T > 0.0 && p.k >= 0.0 && p.k < 1.0)) return false;
-    if (p.payoff < 0 || p.payoff > 2) return false;
-    if (p.payoff == BT_BULL && !(std::isfinite(p.K2) && p.K2 > p.K)) return false;
-    if (p.flags & ~(uint32_t)(BT_F_EUROPEAN | BT_F_COST_AT_T0)) return false;
-    const double dt = p.T / (double)p.N;
-    const double sq = std::sqrt(dt);
-    const double u = std::exp(p.sigma * sq);
-    const double r = std::exp(p.R * dt);
-    const double d = 1.0 / u;
-    const double rho = 1.0 / r;
-    if (!(d < r && r < u)) return false;
-    m.S0 = p.S0; m.u = u; m.d = d; m.r = r; m.rho = rho;
-    m.p = (r - d) / (u - d);
-    m.K = p.K; m.K2 = p.K2; m.k = p.k; m.sq = sq; m.dt = dt;
-    m.N = p.N; m.payoff = p.payoff; m.flags = p.flags;
-    m.valid = 1;
-    return true;
-}
+bool derive(const bt_params &p, Model &m) { return derive_model(p, BT_MAX_N, m); }
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 

@@ -74,8 +74,9 @@ int main(int argc, char** argv) {
   int grad = argc > 2 ? atoi(argv[2]) : 0;
   if (argc > 3) bt_host_lanes = atoi(argv[3]);
   while (scanf("%lf %lf %lf %lf %lf %lf %lf %d %d %u", &S0,&K,&K2,&R,&sig,&T,&k,&N,&pay,&fl) == 10) {
-    Model m{}; double dt = T/(double)N, sq = std::sqrt(dt); double u = std::exp(sig*sq), r = std::exp(R*dt);
-    m.S0=S0; m.u=u; m.d=1.0/u; m.r=r; m.rho=1.0/r; m.p=(r-m.d)/(u-m.d); m.K=K; m.K2=K2; m.k=k; m.sq=sq; m.dt=dt; m.N=N; m.payoff=pay; m.flags=fl; m.valid=1;
+    bt_params p{S0, K, K2, R, sig, T, k, N, pay, fl, 0u};
+    Model m{};
+    if (!derive_model(p, BT_MAX_N, m)) { printf("-1\n"); fflush(stdout); continue; }
     long long ta, tb; int ma, mb;
     if (!grad) {
       double ra, rb;

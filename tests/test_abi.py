@@ -55,7 +55,14 @@ def test_model_constants_match_oracle_bitwise(lib):
     # The tree constants (Section 4.1) are derived on the host by the
     # library and, independently, by the oracle; both use the same formulas,
     # so they agree to the bit.
-    for b in (W.single_put_n100(), W.paper_grid(1500)[:3], W.mixed_book(16, seed=9)):
+    hard = W.single_put_n100().repeat(4)
+    # sigma = exponent with T = N = 1: arguments whose libm exp is not the
+    # nearest binary64 number
+    for i, h in enumerate(["0x1.a056d88f0ced3p-8", "0x1.88ab8b85f2710p-9", "0x1.983139ccee7acp-7",
+                           "0x1.6c15d3740474dp-9"]):
+        hard[i]["sigma"], hard[i]["T"], hard[i]["N"], hard[i]["R"] = float.fromhex(h), 1.0, 1, 0.0
+    for b in (W.single_put_n100(), W.paper_grid(1500)[:3], W.mixed_book(16, seed=9), hard,
+              W.stress_book(2000, seed=12), W.mixed_book(2000, seed=13)):
         for p in b:
             c = bt.bt_model_constants(p)
             _, o = oracle.model_table(p["S0"], p["sigma"], p["R"], p["T"], int(p["N"]))

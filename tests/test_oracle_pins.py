@@ -313,3 +313,32 @@ def test_invalid_parameters_rejected():
         oracle.price(100, 100, 0.05, 0.3, 1.0, 0.0, 0)           # N < 1
     with pytest.raises(oracle.OracleError):
         oracle.price(100, 100, 0.05, 0.3, 1.0, 0.0, 10, payoff=oracle.BULL, K2=90)
+
+
+# glibc's exp rounds these arguments to the other neighbour of e^x; the model
+# takes u and r correctly rounded (Section 4.1 defines them as exponentials)
+_HARD_EXP_ARGS = ["0x1.a056d88f0ced3p-8", "0x1.88ab8b85f2710p-9", "0x1.983139ccee7acp-7",
+                  "0x1.6c15d3740474dp-9"]
+
+
+def test_model_exponentials_are_correctly_rounded():
+    # u = e^(sigma sqrt(T/N)) and r = e^(R T/N) against 60-digit decimal
+    # arithmetic: with T = N = 1 the exponents are sigma and R themselves
+    from decimal import Context, Decimal
+    rng = np.random.default_rng(61)
+    xs = [float.fromhex(h) for h in _HARD_EXP_ARGS] + list(rng.uniform(1e-4, 0.6, 400))
+    for x in xs:
+        ref = float(Decimal(x).exp(Context(prec=60)))
+        _, c = oracle.model_table(100.0, x, 0.0, 1.0, 1)
+        assert c["u"] == ref, x.hex()
+        _, c = oracle.model_table(100.0, 1.0, x, 1.0, 1)
+        assert c["r"] == ref, x.hex()
+    # the general case: sqrt(T/N) too
+    for _ in range(200):
+        N = int(rng.integers(1, 20000))
+        T, sig, R = rng.uniform(0.05, 3), rng.uniform(0.05, 0.8), rng.uniform(0.0, 0.1)
+        dt = T / N
+        _, c = oracle.model_table(100.0, sig, R, T, N)
+        assert c["u"] == float(Decimal(sig * math.sqrt(dt)).exp(Context(prec=60)))
+        assert c["r"] == float(Decimal(R * dt).exp(Context(prec=60)))
+        assert c["d"] == 1.0 / c["u"] and c["rho"] == 1.0 / c["r"]
