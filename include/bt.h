@@ -27,7 +27,9 @@
  *     the current HIP device and are accessed asynchronously on `stream`
  *     (a hipStream_t passed as void*, NULL = the null stream).
  *   - All memory passed in is owned by the caller.  The library owns only
- *     what a book (bt_book) allocates, freed by bt_book_destroy().
+ *     what a book (bt_book) allocates, freed by bt_book_destroy(), and the
+ *     workspaces of bt_price, bt_price_batch and bt_price_grad_batch, freed
+ *     by bt_shutdown().
  *   - All arithmetic is IEEE binary64 with no contraction.
  */
 #ifndef BT_H
@@ -153,7 +155,9 @@ typedef struct bt_book bt_book;
 
 /* h_params: host pointer to n options (n >= 1).  tune: host pointer or
  * NULL.  *out receives the book.  Returns BT_OK even when some options are
- * invalid (see the per-option status); BT_EINVAL only for bad arguments. */
+ * invalid (see the per-option status); BT_EINVAL only for bad arguments,
+ * including a tuning whose level buffers would need offsets beyond int
+ * (level_factor x 3 (N_max+2) above 2^31 - 1). */
 int bt_book_create(const bt_params *h_params, int32_t n, const bt_tune *tune, bt_book **out);
 
 /* Number of options, largest N, and the number of tree nodes
@@ -165,7 +169,15 @@ int bt_book_info(const bt_book *book, int32_t *n, int32_t *n_max, int64_t *nodes
  * book order.  Asynchronous on `stream` (the three recursions run on two
  * streams of the book's own as well, forked from `stream` and joined back
  * to it before the call's work ends there); the book's buffers are shared
- * by all calls on it, so calls on one book must not overlap. */
+ * by all calls on it, so calls on one book must not overlap.
+ * An option whose tree outgrows the book's buffers on either side gets
+ * status BT_EOVERFLOW, NaN prices and zero counts (no partial result).
+ * Whether an option outgrows the big-node arena can depend on the order in
+ * which the GPU schedules the workgroups of a launch (the arena is shared by
+ * all tree sides of a party), so two calls may differ in which options end
+ * BT_EOVERFLOW; every option that ends BT_OK has the same bits in every
+ * call, and bt_book_resolve_overflow completes the others with those same
+ * bits. */
 int bt_book_price(bt_book *book, bt_result *d_out, void *stream);
 
 /* As bt_book_price, and also the Greeks of ask and bid: d_grad is a device
@@ -176,6 +188,52 @@ int bt_book_price(bt_book *book, bt_result *d_out, void *stream);
  * piecewise-smooth price.  The book must have been created with
  * BT_TUNE_GREEKS (else BT_ENOSUPP). */
 int bt_book_price_grad(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream);
+
+/* Batch pricing of options held in device memory (for example a caller's
+ * tensors): ask, bid and price0 of d_params[0..n-1] into d_out[0..n-1],
+ * asynchronous on `stream`, with the same results as a book of the same
+ * options and tuning (Section 3 recursions, Section 4.1 tree).
+ *   d_params  device pointer to n bt_params (read on the stream);
+ *   n         number of options (0: nothing is done);
+ *   max_N     the largest N the call may meet, 1..BT_MAX_N; an option with
+ *             N > max_N gets status BT_EINVAL.  It sizes the workspace and
+ *             fixes the launch sequence (ceil((max_N+1)/band_levels) band
+ *             launches per party), so a tight bound is faster;
+ *   d_out     device pointer to n bt_result;
+ *   tune      host pointer or NULL; wgs_per_cu defaults to 1 here, and
+ *             BT_TUNE_TIMING and BT_TUNE_GRAPH are ignored (capture the
+ *             caller's stream instead).
+ * Everything runs on the GPU: the tree constants (bt_model.hpp's correctly
+ * rounded exp, bit-equal to bt_model_constants), the order of the tree
+ * sides and the band task lists are built by kernels, then the book's
+ * kernels price them.  Nothing of the options is read by the host.
+ * Workspace: the library keeps one per (device, stream, with or without
+ * Greeks), sized for n options of up to max_N steps each (as if every option
+ * were the costly buyer of a call: about 2 x 2 x (3 level_factor + 1)(max_N+2)
+ * numbers of band buffers per option, plus per-workgroup levels, pools and
+ * each party's arena of at most 2^31 doubles).  A call that fits the
+ * existing workspace allocates nothing, waits for nothing on the host and
+ * can be captured in a HIP graph; a call that needs a larger one (more
+ * options, a larger max_N, another tuning) frees the old one after waiting
+ * for the device and allocates, which is refused with BT_ENOSUPP while the
+ * stream is capturing.  bt_shutdown frees every workspace.  Calls on one
+ * stream share its workspace in stream order; calls from several host
+ * threads are serialised by the library.
+ * Errors: BT_EINVAL (bad arguments), BT_ENOMEM, BT_EHIP, BT_ENOSUPP; per
+ * option, status BT_EINVAL (invalid option) or BT_EOVERFLOW (its tree
+ * outgrew the workspace: price it again with a larger level_factor or
+ * pool_points, or through a book and bt_book_resolve_overflow).  An option
+ * whose status is not BT_OK has NaN prices and zero counts (no partial
+ * results). */
+int bt_price_batch(const bt_params *d_params, int32_t n, int32_t max_N, bt_result *d_out, void *stream,
+                   const bt_tune *tune);
+
+/* As bt_price_batch, and the Greeks of ask and bid into d_grad[0..n-1]
+ * (device pointer; NaN where status is not BT_OK), carried forward through
+ * the recursion as in bt_book_price_grad.  Its workspace is separate from
+ * the price-only one and holds five numbers per number. */
+int bt_price_grad_batch(const bt_params *d_params, int32_t n, int32_t max_N, bt_result *d_out, bt_grad *d_grad,
+                        void *stream, const bt_tune *tune);
 
 /* Completes a pricing call whose options overflowed the book's buffers
  * (status BT_EOVERFLOW: a tree whose band levels, private levels or
@@ -189,7 +247,9 @@ int bt_book_price_grad(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *s
  * allocates temporary device memory only when some option overflowed, one
  * re-pricing book at a time: a set of options whose book does not fit in
  * device memory is re-priced in halves, and a single option that does not
- * fit even alone stays BT_EOVERFLOW (counted in *remaining). */
+ * fit even alone stays BT_EOVERFLOW (counted in *remaining), as does an
+ * option whose level buffers would need more than 2^31 - 1 numbers (offsets
+ * are int: level_factor x 3 (N+2) must stay below that). */
 int bt_book_resolve_overflow(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream,
                              int32_t *remaining);
 
@@ -233,9 +293,10 @@ int bt_autotune(const bt_params *h_params, int32_t n, const bt_tune *base, const
 int bt_price(const bt_params *p, bt_result *out);
 
 /* Frees what bt_price keeps between calls on the calling thread (its cached
- * one-option book and result buffer; synchronises the device first).  Books
- * from bt_book_create are not affected, and a later bt_price builds a new
- * cache.  Safe to call at any time, also repeatedly.  Returns BT_OK. */
+ * one-option book and result buffer) and every workspace of bt_price_batch
+ * and bt_price_grad_batch (of all threads; waits for each device first).
+ * Books from bt_book_create are not affected, and later calls build new
+ * caches.  Safe to call at any time, also repeatedly.  Returns BT_OK. */
 int bt_shutdown(void);
 
 /* Tree constants the library derives for one option on the host (u, d, r,

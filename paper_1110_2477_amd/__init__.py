@@ -24,7 +24,7 @@ EUROPEAN, COST_AT_T0 = 1, 2
 # Function names declared in include/bt.h.
 ABI_FUNCTIONS = ("bt_autotune", "bt_book_create", "bt_book_info", "bt_book_price", "bt_book_price_grad",
                  "bt_book_resolve_overflow", "bt_book_timings", "bt_book_destroy", "bt_price", "bt_shutdown",
-                 "bt_model_constants", "bt_strerror",
+                 "bt_price_batch", "bt_price_grad_batch", "bt_model_constants", "bt_strerror",
                  "bt_version", "bt_last_hip_error")
 
 
@@ -79,6 +79,8 @@ def lib():
     L.bt_autotune.argtypes = [vp, i32, vp, vp, i32, i32, vp, vp, dp]
     L.bt_book_destroy.restype = None
     L.bt_price.argtypes = [vp, vp]
+    L.bt_price_batch.argtypes = [vp, i32, i32, vp, vp, vp]
+    L.bt_price_grad_batch.argtypes = [vp, i32, i32, vp, vp, vp, vp]
     L.bt_shutdown.argtypes = []
     L.bt_model_constants.argtypes = [vp, dp, dp, dp, dp, dp]
     L.bt_strerror.argtypes = [ctypes.c_int]
@@ -86,7 +88,8 @@ def lib():
     L.bt_version.argtypes = []
     L.bt_last_hip_error.argtypes = []
     for f in ("bt_autotune", "bt_book_create", "bt_book_info", "bt_book_price", "bt_book_price_grad", "bt_book_timings", "bt_book_resolve_overflow",
-              "bt_price", "bt_shutdown", "bt_model_constants", "bt_version", "bt_last_hip_error"):
+              "bt_price", "bt_shutdown", "bt_model_constants", "bt_version", "bt_last_hip_error",
+              "bt_price_batch", "bt_price_grad_batch"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -209,8 +212,65 @@ def bt_price(params):
     return out[0]
 
 
+def bt_price_batch(d_params_ptr, n, max_N, d_out_ptr, stream=None, tune=None):
+    """Batch pricing of n bt_params records at device address d_params_ptr
+    into n bt_result records at d_out_ptr, on ``stream`` (torch's current
+    stream when None); every option's N must be at most max_N."""
+    t = _Tune.of(tune) if tune is not None else None
+    _check(lib().bt_price_batch(ctypes.c_void_p(d_params_ptr), int(n), int(max_N), ctypes.c_void_p(d_out_ptr),
+                                ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(t) if t is not None else None),
+           "bt_price_batch")
+
+
+def bt_price_grad_batch(d_params_ptr, n, max_N, d_out_ptr, d_grad_ptr, stream=None, tune=None):
+    """As bt_price_batch, plus n bt_grad records at d_grad_ptr."""
+    t = _Tune.of(tune) if tune is not None else None
+    _check(lib().bt_price_grad_batch(ctypes.c_void_p(d_params_ptr), int(n), int(max_N),
+                                     ctypes.c_void_p(d_out_ptr), ctypes.c_void_p(d_grad_ptr),
+                                     ctypes.c_void_p(_stream_ptr(stream)),
+                                     ctypes.byref(t) if t is not None else None), "bt_price_grad_batch")
+
+
+def params_tensor(params, device="cuda"):
+    """A uint8 device tensor holding PARAMS_DTYPE records (the layout of
+    bt_params)."""
+    import torch
+    p = _params(params)
+    return torch.from_numpy(p.view(np.uint8).copy()).to(device)
+
+
+def price_batch(d_params, max_N, grad=False, stream=None, tune=None):
+    """Prices the bt_params records of the uint8 device tensor ``d_params``
+    (see params_tensor) on the GPU; returns uint8 device tensors of bt_result
+    records (and of bt_grad records with grad=True).  Asynchronous on
+    ``stream``; nothing is copied to the host."""
+    import torch
+    n = d_params.numel() // PARAMS_DTYPE.itemsize
+    if d_params.dtype != torch.uint8 or not d_params.is_cuda or not d_params.is_contiguous() \
+            or d_params.numel() != n * PARAMS_DTYPE.itemsize:
+        raise ValueError("d_params must be a contiguous uint8 CUDA tensor of bt_params records")
+    out = torch.empty(n * RESULT_DTYPE.itemsize, dtype=torch.uint8, device=d_params.device)
+    if not grad:
+        bt_price_batch(d_params.data_ptr(), n, max_N, out.data_ptr(), stream, tune)
+        return out
+    g = torch.empty(n * GRAD_DTYPE.itemsize, dtype=torch.uint8, device=d_params.device)
+    bt_price_grad_batch(d_params.data_ptr(), n, max_N, out.data_ptr(), g.data_ptr(), stream, tune)
+    return out, g
+
+
+def as_results(t):
+    """RESULT_DTYPE array of a uint8 tensor of bt_result records (copies to the host)."""
+    return np.frombuffer(t.cpu().numpy().tobytes(), dtype=RESULT_DTYPE).copy()
+
+
+def as_grads(t):
+    """GRAD_DTYPE array of a uint8 tensor of bt_grad records (copies to the host)."""
+    return np.frombuffer(t.cpu().numpy().tobytes(), dtype=GRAD_DTYPE).copy()
+
+
 def bt_shutdown():
-    """Frees bt_price's cached book of the calling thread."""
+    """Frees bt_price's cached book of the calling thread and every batch
+    workspace."""
     _check(lib().bt_shutdown(), "bt_shutdown")
 
 

@@ -35,6 +35,7 @@
 #include <new>
 #include <vector>
 #include <functional>
+#include <mutex>
 
 #include "../../include/bt.h"
 #include "bt_device.hpp"
@@ -69,7 +70,8 @@ struct KArgs {
     const Model *models;
     const Item *items;
     const Task *tasks;
-    const int *task_off;    // [2 * nbands_max + 1]: tasks of (launch L, side s) at L*2+s
+    const int *task_lo;     // tasks of (launch L, side s): [task_lo, task_hi) at index 2L+s
+    const int *task_hi;
     int *band_ctr;          // persistent-workgroup counters, [2 * nbands_max]
     unsigned long long *fill;   // band-buffer fill counters
     int *failed;            // per item
@@ -90,7 +92,7 @@ struct KArgs {
     int64_t oStab, oP0, oP1, oSmall, oPool;
     int *p0_queue;
     const int *p0_sched;
-    int n_p0;
+    const int *p0_count;    // number of options in p0_sched (device memory)
     bt_grad *grad;          // Greeks output (dual-number launches only)
     double *arena;          // temporaries of big nodes that outgrow a wave's pool slice
     int64_t arena_cap[2];   // doubles of the seller's (0) and the buyer's (1) arena
@@ -175,9 +177,9 @@ __device__ void stock_table(const Model &md, double *Stab)
 template <typename T>
 __global__ void bt_init_kernel(KArgs A)
 {
-    const int it = blockIdx.y;
-    if (it >= A.n_items) return;
+  for (int it = blockIdx.y; it < A.n_items; it += gridDim.y) {
     const Item I = A.items[it];
+    if (I.opt < 0) continue;   // unused slot of a batch planned on the device
     const Model md = A.models[I.opt];
     const Inputs<T> in = inputs_of(md, T{});
     const int N = I.N;
@@ -192,6 +194,7 @@ __global__ void bt_init_kernel(KArgs A)
         off[c] = 4 * c;
         cnt[c] = 1;
     }
+  }
 }
 
 // One band task of launch `launch`: block `blk` of tree side `item`, whose
@@ -459,7 +462,7 @@ __global__ __launch_bounds__(WG) void bt_band_kernel(KArgs A, int r)
     __shared__ double *s_chunk[NWAVE];
     __shared__ int64_t s_chunk_cap[NWAVE];
     __shared__ T s_win[NWAVE * WaveLds<T>::NUMS];   // MERGE windows of the cooperative path
-    const int lo = A.task_off[2 * r + SIDE], hi = A.task_off[2 * r + SIDE + 1];
+    const int lo = A.task_lo[2 * r + SIDE], hi = A.task_hi[2 * r + SIDE];
     if (threadIdx.x < NWAVE) {
         s_chunk[threadIdx.x] = nullptr;
         s_chunk_cap[threadIdx.x] = 0;
@@ -530,7 +533,7 @@ __global__ __launch_bounds__(WG) void bt_price0_kernel(KArgs A)
         __syncthreads();
         const int q = s_item;
         __syncthreads();
-        if (q >= A.n_p0) break;
+        if (q >= *A.p0_count) break;
         const int opt = A.p0_sched[q];
         const Model md = A.models[opt];
         price0_item(A, md, opt, ws);
@@ -567,6 +570,172 @@ __global__ void bt_reset_kernel(KArgs A, int64_t n_fill)
     for (int64_t k = i; k < n_fill; k += stride) A.fill[k] = 0;
     for (int64_t k = i; k < A.n_items; k += stride) A.failed[k] = 0;
     if (i == 0) *A.p0_queue = 0;
+}
+
+// Options whose pricing failed (status other than BT_OK: invalid, or a
+// tree that outgrew its buffers on either side) get no partial result: NaN
+// prices and Greeks, zero breakpoint counts.
+__global__ void bt_finalize_kernel(KArgs A)
+{
+    const double nan = __builtin_nan("");
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < A.n_opts; k += (int64_t)gridDim.x * blockDim.x) {
+        bt_result &o = A.out[k];
+        if (o.status == BT_OK) continue;
+        o.ask = nan; o.bid = nan; o.price0 = nan;
+        o.bp_total_ask = 0; o.bp_total_bid = 0;
+        o.bp_max_ask = 0; o.bp_max_bid = 0;
+        if (A.grad) {
+            bt_grad g;
+            g.ask.dS0 = g.ask.dsigma = g.ask.dR = g.ask.dk = nan;
+            g.bid = g.ask;
+            A.grad[k] = g;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Device planner of a batch whose options are in device memory
+// (bt_price_batch): tree constants, the order of the tree sides and the band
+// task lists, built on the GPU in the same order a book builds them on the
+// host.  Every buffer is laid out for the batch's largest N, so nothing here
+// depends on the host seeing the options.
+// ---------------------------------------------------------------------------
+struct PlanArgs {
+    const bt_params *params;
+    int n, max_N;
+    Model *models;
+    int2 *keys;          // per option: (N, or -1 when invalid; growth bits)
+    int *order;          // [3][n]: buyer, seller and zero-cost orders (position -> option)
+    int *count;          // valid options
+    Item *items;         // [2n]: buyer tree sides at [0, n), seller tree sides at [n, 2n)
+    Task *tasks;
+    int *task_lo, *task_hi;
+    int nbands_max, band, block_cols, lf, nt;
+    int64_t lstride;     // doubles of band buffers per tree side
+    int64_t istride;     // ints of offsets and counts per tree side
+};
+
+// Bits of the tree sides whose nodes grow large: 1 = the buyer of a call or
+// a bull spread with costs, 2 = the seller of a bull spread with costs (the
+// order a book uses puts them first in each party's task list).
+BTHD int growth_bits(const Model &m)
+{
+    if (!m.valid || !(m.k > 0.0)) return 0;
+    return (m.payoff != PAY_PUT ? 1 : 0) | (m.payoff == PAY_BULL ? 2 : 0);
+}
+
+// Upper bound on the column blocks of one tree side in launch L: every tree
+// side ends in the last launch, so its band in launch L starts at most
+// (nbands - L) * band - 1 levels above the root.
+BTHD int launch_blocks(int L, int nbands_max, int band, int block_cols)
+{
+    return ((nbands_max - L - 1) * band + 1 + block_cols - 1) / block_cols;
+}
+
+__global__ void bt_derive_kernel(PlanArgs P)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *P.count = 0;
+    if (i >= P.n) return;
+    Model m;
+    const bool ok = derive_model(P.params[i], P.max_N, m);
+    P.models[i] = m;
+    P.keys[i] = make_int2(ok ? m.N : -1, growth_bits(m));
+}
+
+// Position of every valid option in the three orders, by counting the
+// options that precede it: longer trees first, ties by index (zero-cost
+// order); within a party the growing tree sides first, then the same.
+__global__ __launch_bounds__(WG) void bt_rank_kernel(PlanArgs P)
+{
+    __shared__ int2 sk[WG];
+    const int i = blockIdx.x * WG + threadIdx.x;
+    const int2 ki = i < P.n ? P.keys[i] : make_int2(-1, 0);
+    int pb = 0, ps = 0, pz = 0;
+    for (int j0 = 0; j0 < P.n; j0 += WG) {
+        __syncthreads();
+        sk[threadIdx.x] = j0 + (int)threadIdx.x < P.n ? P.keys[j0 + threadIdx.x] : make_int2(-1, 0);
+        __syncthreads();
+        if (ki.x < 0) continue;
+        const int jn = min(WG, P.n - j0);
+        for (int jj = 0; jj < jn; jj++) {
+            const int2 kj = sk[jj];
+            if (kj.x < 0) continue;
+            const bool first = kj.x > ki.x || (kj.x == ki.x && j0 + jj < i);
+            const int gbj = kj.y & 1, gbi = ki.y & 1, gsj = (kj.y >> 1) & 1, gsi = (ki.y >> 1) & 1;
+            pz += first;
+            pb += gbj > gbi || (gbj == gbi && first);
+            ps += gsj > gsi || (gsj == gsi && first);
+        }
+    }
+    if (ki.x >= 0) {
+        P.order[pb] = i;
+        P.order[P.n + ps] = i;
+        P.order[2 * P.n + pz] = i;
+        atomicAdd(P.count, 1);
+    }
+}
+
+// Tree side q: party slot q / n (0 buyer, 1 seller), position q % n.
+__global__ void bt_items_kernel(PlanArgs P)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= 2 * P.n) return;
+    const int slot = q / P.n, pos = q - slot * P.n;
+    Item it;
+    it.side = slot == 0 ? 1 : 0;
+    it.lbuf = (int64_t)q * P.lstride;
+    it.ibuf = (int64_t)q * P.istride;
+    it.ctr = (int64_t)q * (P.nbands_max + 1);
+    if (pos < *P.count) {
+        it.opt = P.order[slot * P.n + pos];
+        it.N = P.models[it.opt].N;
+        it.nbands = (it.N + P.band) / P.band;
+        it.lcap = (((int64_t)P.lf * (it.N + 2) * 3 + (it.N + 2)) * P.nt + 31) & ~(int64_t)31;
+    } else {
+        it.opt = -1;
+        it.N = 0;
+        it.nbands = 0;
+        it.lcap = 0;
+    }
+    P.items[q] = it;
+}
+
+// Task list of launch L (blockIdx.x), party blockIdx.y (0 seller, 1 buyer):
+// the column blocks of every tree side of that party that launch L runs, in
+// the party's order, in a region sized by launch_blocks.
+__global__ __launch_bounds__(WG) void bt_tasks_kernel(PlanArgs P)
+{
+    __shared__ int64_t sh[NWAVE];
+    const int L = blockIdx.x, side = blockIdx.y, slot = side == 1 ? 0 : 1;
+    int64_t base = 0;
+    for (int l = 0; l < L; l++) base += 2 * (int64_t)launch_blocks(l, P.nbands_max, P.band, P.block_cols);
+    base += side * (int64_t)launch_blocks(L, P.nbands_max, P.band, P.block_cols);
+    base *= P.n;
+    const int cnt = *P.count;
+    int64_t run = 0;
+    for (int p0 = 0; p0 < cnt; p0 += WG) {
+        const int pos = p0 + threadIdx.x;
+        const int q = slot * P.n + pos;
+        int nb = 0;
+        if (pos < cnt) {
+            const Item I = P.items[q];
+            const int r = L - (P.nbands_max - I.nbands);
+            if (r >= 0) {
+                const int t_top = I.N - r * P.band;
+                const int t_bot = t_top - P.band + 1 > 0 ? t_top - P.band + 1 : 0;
+                nb = (t_bot + 1 + P.block_cols - 1) / P.block_cols;
+            }
+        }
+        int64_t tot;
+        const int64_t ex = block_scan(nb, &tot, sh);
+        for (int b = 0; b < nb; b++) P.tasks[base + run + ex + b] = Task{q, b};
+        run += tot;
+    }
+    if (threadIdx.x == 0) {
+        P.task_lo[2 * L + side] = (int)base;
+        P.task_hi[2 * L + side] = (int)(base + run);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -633,6 +802,15 @@ struct bt_book {
     int g_nt = 0;
     std::vector<bt_params> params;   // host copy, for re-pricing on overflow
     bt_tune tune{};
+    // a batch workspace (bt_price_batch): planned on the device for up to
+    // cap_n options of up to cap_N steps each
+    bool device_plan = false;
+    bool carved = false;              // buffers carved from a caller's region: not freed here
+    int cap_n = 0, cap_N = 0;
+    int2 *d_keys = nullptr;
+    int *d_order = nullptr;
+    int *d_plan_ints = nullptr;       // valid count, task bounds
+    PlanArgs plan{};
 };
 
 namespace {
@@ -656,9 +834,11 @@ void book_free(bt_book *b)
     for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
     b->events.clear();
     void *ptrs[] = {b->d_models, b->d_items, b->d_tasks, b->d_task_off, b->d_ints,
-                    b->d_fill, b->d_lvl, b->d_lvli, b->d_ws, b->d_wsi, b->d_arena, b->d_arena_ctr, b->d_wsp};
+                    b->d_fill, b->d_lvl, b->d_lvli, b->d_ws, b->d_wsi, b->d_arena, b->d_arena_ctr, b->d_wsp,
+                    b->d_keys, b->d_order, b->d_plan_ints};
     for (void *p : ptrs)
-        if (p) (void)hipFree(p);
+        if (p && !b->carved) (void)hipFree(p);
+    b->d_keys = nullptr; b->d_order = nullptr; b->d_plan_ints = nullptr;
     b->d_models = nullptr; b->d_items = nullptr; b->d_tasks = nullptr; b->d_task_off = nullptr;
     b->d_ints = nullptr; b->d_fill = nullptr; b->d_lvl = nullptr; b->d_lvli = nullptr;
     b->d_ws = nullptr; b->d_wsi = nullptr; b->d_arena = nullptr; b->d_arena_ctr = nullptr; b->d_wsp = nullptr;
@@ -825,6 +1005,8 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
         if (it.side == 1 && models[it.opt].k > 0 && models[it.opt].payoff != BT_PUT)
             ppts = std::max(ppts, 16 * (int64_t)it.N);
     const int64_t pcap = round_up(ppts * 3 * nt + (WG + 1) * nt, 32);
+    // offsets into a band buffer or a private level are int
+    if ((int64_t)lf * (n_max + 2) * 3 + (n_max + 2) > INT32_MAX || ppts * 3 + (WG + 1) > INT32_MAX) return BT_EINVAL;
     const Caps sc = small_caps();
     a.oStab = 0;
     const int64_t stab_n = std::max<int64_t>((2 * (int64_t)WG + BAND + 8) * nt, 2 * (int64_t)n_max + 3);
@@ -844,7 +1026,6 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
     a.n_items = (int)items.size();
     a.nbands_max = nbands_max;
     a.band = band;
-    a.n_p0 = (int)p0.size();
 
     b->use_graph = tune && (tune->flags & BT_TUNE_GRAPH);
     b->timing = tune && (tune->flags & BT_TUNE_TIMING) && !b->use_graph;
@@ -858,7 +1039,7 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
     b->grid = grid; b->grid_p0 = grid_p0;
     b->ntasks = ntasks;
 
-    const int64_t nints = 2 * (int64_t)nbands_max + (int64_t)items.size() + 64 + (int64_t)p0.size();
+    const int64_t nints = 2 * (int64_t)nbands_max + (int64_t)items.size() + 64 + (int64_t)p0.size() + 1;
     int rc = BT_OK;
     if ((rc = dalloc(&b->d_models, n)) || (rc = dalloc(&b->d_items, items.size())) ||
         (rc = dalloc(&b->d_tasks, tasks.size())) || (rc = dalloc(&b->d_task_off, task_off.size())) ||
@@ -878,11 +1059,15 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
     int *failed = band_ctr + 2 * (int64_t)nbands_max;
     int *p0q = failed + items.size();
     int *p0s = p0q + 64;
+    int *p0n = p0s + p0.size();
     if (!p0.empty()) HIPCHK(hipMemcpy(p0s, p0.data(), sizeof(int) * p0.size(), hipMemcpyHostToDevice));
+    const int n_p0 = (int)p0.size();
+    HIPCHK(hipMemcpy(p0n, &n_p0, sizeof(int), hipMemcpyHostToDevice));
     a.models = b->d_models;
     a.items = b->d_items;
     a.tasks = b->d_tasks;
-    a.task_off = b->d_task_off;
+    a.task_lo = b->d_task_off;
+    a.task_hi = b->d_task_off + 1;
     a.band_ctr = band_ctr;
     a.fill = b->d_fill;
     a.failed = failed;
@@ -893,6 +1078,7 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
     a.wsp = b->d_wsp;
     a.p0_queue = p0q;
     a.p0_sched = p0s;
+    a.p0_count = p0n;
     a.arena = b->d_arena;
     a.arena_cap[0] = arena[0];
     a.arena_cap[1] = arena[1];
@@ -900,6 +1086,180 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
     a.arena_base[1] = arena[0];
     a.arena_ctr = b->d_arena_ctr;
     b->args = a;
+    HIPCHK(hipStreamCreateWithFlags(&b->s_ask, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&b->s_p0, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&b->ev_ask, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&b->ev_p0, hipEventDisableTiming));
+    return BT_OK;
+}
+
+// Carves device buffers out of one region (a caller-provided scratch area)
+// or allocates each with hipMalloc.
+struct Carver {
+    char *base = nullptr;     // nullptr: hipMalloc each buffer
+    size_t cap = 0, used = 0;
+    template <typename T>
+    int take(T **p, size_t count)
+    {
+        const size_t bytes = (sizeof(T) * std::max<size_t>(count, 1) + 255) & ~(size_t)255;
+        if (!base) return dalloc(p, count);
+        if (used + bytes > cap) return BT_ENOMEM;
+        *p = (T *)(base + used);
+        used += bytes;
+        return BT_OK;
+    }
+};
+
+// Tuning of a batch workspace with the library's defaults filled in.
+bt_tune batch_tune(const bt_tune *tune, bool greeks)
+{
+    bt_tune t{};
+    if (tune) t = *tune;
+    t.flags = greeks ? BT_TUNE_GREEKS : 0;
+    if (t.wgs_per_cu <= 0) t.wgs_per_cu = 1;   // the LDS of one band workgroup fills a CU
+    if (t.level_factor <= 0) t.level_factor = DEFAULT_LEVEL_FACTOR;
+    if (t.pool_points <= 0) t.pool_points = (int32_t)(greeks ? DEFAULT_POOL_POINTS / 4 : DEFAULT_POOL_POINTS);
+    if (t.band_levels == 0) t.band_levels = BAND;
+    return t;
+}
+
+// Workspace of a batch planned on the device: every buffer sized for cap_n
+// options of up to cap_N steps each, as if every option were the buyer of a
+// costly call (the largest nodes): two band buffers per tree side, private
+// levels of 16 cap_N points, and each party's arena estimated like a book's
+// for min(cap_n, resident workgroups) such tree sides, between the book's
+// floor and arena_cap doubles.  The buffers come from `carve` (hipMalloc, or a
+// caller's region).  `grid_cap` (0: none) bounds the persistent workgroups.
+int batch_build(bt_book *b, int cap_n, int cap_N, const bt_tune &t, int grid_cap, int64_t arena_cap, Carver &cv)
+{
+    const bool greeks = (t.flags & BT_TUNE_GREEKS) != 0;
+    const int64_t nt = greeks ? (int64_t)(sizeof(D4) / sizeof(double)) : 1;
+    if (t.band_levels < MIN_BAND || t.band_levels > BAND || cap_n < 1 || cap_N < 1 || cap_N > BT_MAX_N) return BT_EINVAL;
+    const int band = t.band_levels, block_cols = WG - band, lf = t.level_factor;
+    const int nbands_max = (cap_N + band) / band;
+    const int64_t pool = (int64_t)t.pool_points * 4 * nt;
+    const int64_t arena_floor = std::min(std::max<int64_t>(DEFAULT_ARENA_DOUBLES * nt, 64 * pool), arena_cap);
+    int64_t ppts = std::max({(int64_t)lf * (WG + 1), MIN_PRIVATE_POINTS * std::max(1, lf / DEFAULT_LEVEL_FACTOR),
+                             16 * (int64_t)cap_N});
+    if ((int64_t)lf * (cap_N + 2) * 3 + (cap_N + 2) > INT32_MAX || ppts * 3 + (WG + 1) > INT32_MAX) return BT_EINVAL;
+    // task capacity: cap_n tree sides per party, launch_blocks each
+    int64_t task_cap = 0;
+    for (int L = 0; L < nbands_max; L++) task_cap += 2 * (int64_t)launch_blocks(L, nbands_max, band, block_cols);
+    task_cap *= cap_n;
+    if (task_cap > INT32_MAX) return BT_EINVAL;
+
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    int grid = prop.multiProcessorCount * t.wgs_per_cu;
+    if (grid_cap > 0) grid = std::min(grid, grid_cap);
+    const int grid_p0 = std::max(1, std::min(cap_n, grid));
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        (void)hipGetLastError();
+        free_b = 0;
+    }
+    int64_t arena[2];
+    for (int side = 0; side < 2; side++) {
+        const int64_t M = side == 1 ? 5 * (int64_t)cap_N : cap_N;
+        const int64_t need = (64 * M + 4096) * nt;
+        const int64_t est = need > pool / NWAVE ? 3 * 2 * need * std::min(cap_n, grid) : 0;
+        int64_t e = std::min({est, arena_cap, (int64_t)(free_b / 8 / sizeof(double))});
+        arena[side] = round_up(std::max(arena_floor, e), 32);
+    }
+
+    KArgs a{};
+    const int64_t lstride = 2 * round_up(((int64_t)lf * (cap_N + 2) * 3 + (cap_N + 2)) * nt, 32);
+    const int64_t istride = round_up(4 * (int64_t)(cap_N + 2), 32);
+    const int64_t pcap = round_up(ppts * 3 * nt + (WG + 1) * nt, 32);
+    const Caps sc = small_caps();
+    a.oStab = 0;
+    const int64_t stab_n = std::max<int64_t>((2 * (int64_t)WG + BAND + 8) * nt, 2 * (int64_t)cap_N + 3);
+    a.oP0 = round_up(stab_n, 32);
+    a.oP1 = a.oP0 + pcap;
+    a.oSmall = a.oP1 + pcap;
+    a.oPool = a.oSmall + round_up(sc.total * WG * nt, 32);
+    a.ws_doubles = a.oPool + round_up(std::max<int64_t>(pool, 2 * (int64_t)cap_N + 4), 32);
+    a.wsi_ints = round_up(4 * (int64_t)(WG + 1), 64);
+    a.ws_side = a.ws_doubles * grid;
+    a.wsi_side = a.wsi_ints * grid;
+    a.p0_stab = round_up(2 * (int64_t)cap_N + 3, 32);
+    a.p0_doubles = a.p0_stab + round_up(2 * (int64_t)cap_N + 2, 32);
+    a.pcap = pcap;
+    a.pool = pool;
+    a.nbands_max = nbands_max;
+    a.band = band;
+
+    const int64_t n_items = 2 * (int64_t)cap_n;
+    const int64_t n_fill = n_items * (nbands_max + 1);
+    const int64_t nints = 2 * (int64_t)nbands_max + n_items + 64;
+    int rc = BT_OK;
+    if ((rc = cv.take(&b->d_models, cap_n)) || (rc = cv.take(&b->d_keys, cap_n)) ||
+        (rc = cv.take(&b->d_order, 3 * (size_t)cap_n)) || (rc = cv.take(&b->d_plan_ints, 1 + 4 * (size_t)nbands_max)) ||
+        (rc = cv.take(&b->d_items, n_items)) || (rc = cv.take(&b->d_tasks, task_cap)) ||
+        (rc = cv.take(&b->d_ints, nints)) || (rc = cv.take(&b->d_fill, n_fill)) ||
+        (rc = cv.take(&b->d_lvl, n_items * lstride)) || (rc = cv.take(&b->d_lvli, n_items * istride)) ||
+        (rc = cv.take(&b->d_ws, 2 * a.ws_side)) || (rc = cv.take(&b->d_wsi, 2 * a.wsi_side)) ||
+        (rc = cv.take(&b->d_wsp, a.p0_doubles * grid_p0)) ||
+        (rc = cv.take(&b->d_arena, arena[0] + arena[1])) || (rc = cv.take(&b->d_arena_ctr, 2 * (size_t)nbands_max)))
+        return rc;
+    int *band_ctr = b->d_ints;
+    int *failed = band_ctr + 2 * (int64_t)nbands_max;
+    int *p0q = failed + n_items;
+    int *count = b->d_plan_ints;
+    int *task_lo = count + 1, *task_hi = task_lo + 2 * nbands_max;
+    a.models = b->d_models;
+    a.items = b->d_items;
+    a.tasks = b->d_tasks;
+    a.task_lo = task_lo;
+    a.task_hi = task_hi;
+    a.band_ctr = band_ctr;
+    a.fill = b->d_fill;
+    a.failed = failed;
+    a.lvl = b->d_lvl;
+    a.lvli = b->d_lvli;
+    a.ws = b->d_ws;
+    a.wsi = b->d_wsi;
+    a.wsp = b->d_wsp;
+    a.p0_queue = p0q;
+    a.p0_count = count;
+    a.arena = b->d_arena;
+    a.arena_cap[0] = arena[0];
+    a.arena_cap[1] = arena[1];
+    a.arena_base[0] = 0;
+    a.arena_base[1] = arena[0];
+    a.arena_ctr = b->d_arena_ctr;
+    b->args = a;
+
+    PlanArgs &P = b->plan;
+    P.models = b->d_models;
+    P.keys = b->d_keys;
+    P.order = b->d_order;
+    P.count = count;
+    P.items = b->d_items;
+    P.tasks = b->d_tasks;
+    P.task_lo = task_lo;
+    P.task_hi = task_hi;
+    P.nbands_max = nbands_max;
+    P.band = band;
+    P.block_cols = block_cols;
+    P.lf = lf;
+    P.nt = (int)nt;
+    P.lstride = lstride;
+    P.istride = istride;
+
+    b->device_plan = true;
+    b->cap_n = cap_n;
+    b->cap_N = cap_N;
+    b->greeks = greeks;
+    b->tune = t;
+    b->device = dev;
+    b->n = cap_n; b->n_max = cap_N; b->n_items = (int)n_items;
+    b->nbands_max = nbands_max;
+    b->n_fill = n_fill;
+    b->grid = grid; b->grid_p0 = grid_p0;
     HIPCHK(hipStreamCreateWithFlags(&b->s_ask, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&b->s_p0, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
@@ -951,25 +1311,50 @@ namespace {
 constexpr int NEV = 7;
 
 template <typename T>
-int launch_all(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream)
+int launch_all(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream, const bt_params *d_params = nullptr,
+               int n_call = 0, int max_N_call = 0)
 {
     hipStream_t s = (hipStream_t)stream;
     KArgs a = book->args;
     a.out = d_out;
     a.grad = d_grad;
+    int64_t n_fill = book->n_fill;
+    int n_opts = book->n;
+    if (book->device_plan) {
+        // plan on the device: constants, orders, tree sides, task lists
+        PlanArgs P = book->plan;
+        P.params = d_params;
+        P.n = n_call;
+        P.max_N = max_N_call;
+        a.n_opts = n_call;
+        a.n_items = 2 * n_call;
+        a.p0_sched = book->d_order + 2 * (int64_t)n_call;
+        n_fill = (int64_t)a.n_items * (book->nbands_max + 1);
+        n_opts = n_call;
+        const int g1 = (n_call + WG - 1) / WG, g2 = (2 * n_call + WG - 1) / WG;
+        hipLaunchKernelGGL(bt_derive_kernel, dim3(g1), dim3(WG), 0, s, P);
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(bt_rank_kernel, dim3(g1), dim3(WG), 0, s, P);
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(bt_items_kernel, dim3(g2), dim3(WG), 0, s, P);
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(bt_tasks_kernel, dim3(book->nbands_max, 2), dim3(WG), 0, s, P);
+        HIPCHK(hipGetLastError());
+    }
     hipEvent_t ev[NEV];
     if (book->timing) {
         for (int i = 0; i < NEV; i++) HIPCHK(hipEventCreate(&ev[i]));
         for (int i = 0; i < NEV; i++) book->events.push_back(ev[i]);
         HIPCHK(hipEventRecord(ev[0], s));
     }
-    const int64_t nr = std::max<int64_t>({(int64_t)book->n, 2 * (int64_t)book->nbands_max, book->n_fill,
-                                          (int64_t)book->n_items, 1});
+    const int64_t nr = std::max<int64_t>({(int64_t)n_opts, 2 * (int64_t)book->nbands_max, n_fill,
+                                          (int64_t)a.n_items, 1});
     const int rb = (int)std::min<int64_t>((nr + 255) / 256, 1024);
-    hipLaunchKernelGGL(bt_reset_kernel, dim3(rb), dim3(256), 0, s, a, book->n_fill);
+    hipLaunchKernelGGL(bt_reset_kernel, dim3(rb), dim3(256), 0, s, a, n_fill);
     HIPCHK(hipGetLastError());
-    if (book->n_items > 0) {
-        hipLaunchKernelGGL(bt_init_kernel<T>, dim3((book->n_max + 2 + 255) / 256, book->n_items), dim3(256), 0, s, a);
+    if (a.n_items > 0) {
+        hipLaunchKernelGGL(bt_init_kernel<T>, dim3((book->n_max + 2 + 255) / 256, std::min(a.n_items, 65535)), dim3(256),
+                           0, s, a);
         HIPCHK(hipGetLastError());
     }
     if (book->timing) HIPCHK(hipEventRecord(ev[1], s));
@@ -977,24 +1362,28 @@ int launch_all(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream)
     HIPCHK(hipStreamWaitEvent(book->s_ask, book->ev_fork, 0));
     HIPCHK(hipStreamWaitEvent(book->s_p0, book->ev_fork, 0));
     // buyer
+    // (a batch planned on the device runs every launch; its task counts are
+    // on the device)
+    const auto wgs = [&](int r, int side) {
+        return book->device_plan ? book->grid : std::min(book->grid, book->ntasks[2 * r + side]);
+    };
     for (int r = 0; r < book->nbands_max; r++) {
-        if (book->ntasks[2 * r + 1] == 0) continue;
-        hipLaunchKernelGGL((bt_band_kernel<1, T>), dim3(std::min(book->grid, book->ntasks[2 * r + 1])), dim3(WG), 0, s, a, r);
+        if (wgs(r, 1) == 0) continue;
+        hipLaunchKernelGGL((bt_band_kernel<1, T>), dim3(wgs(r, 1)), dim3(WG), 0, s, a, r);
         HIPCHK(hipGetLastError());
     }
     if (book->timing) HIPCHK(hipEventRecord(ev[2], s));
     // seller
     if (book->timing) HIPCHK(hipEventRecord(ev[3], book->s_ask));
     for (int r = 0; r < book->nbands_max; r++) {
-        if (book->ntasks[2 * r] == 0) continue;
-        hipLaunchKernelGGL((bt_band_kernel<0, T>), dim3(std::min(book->grid, book->ntasks[2 * r])), dim3(WG), 0,
-                           book->s_ask, a, r);
+        if (wgs(r, 0) == 0) continue;
+        hipLaunchKernelGGL((bt_band_kernel<0, T>), dim3(wgs(r, 0)), dim3(WG), 0, book->s_ask, a, r);
         HIPCHK(hipGetLastError());
     }
     if (book->timing) HIPCHK(hipEventRecord(ev[4], book->s_ask));
     // zero-cost recursion
     if (book->timing) HIPCHK(hipEventRecord(ev[5], book->s_p0));
-    if (book->args.n_p0 > 0) {
+    if (book->device_plan || book->n_items > 0) {
         hipLaunchKernelGGL(bt_price0_kernel, dim3(book->grid_p0), dim3(WG), 0, book->s_p0, a);
         HIPCHK(hipGetLastError());
     }
@@ -1003,6 +1392,8 @@ int launch_all(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream)
     HIPCHK(hipEventRecord(book->ev_p0, book->s_p0));
     HIPCHK(hipStreamWaitEvent(s, book->ev_ask, 0));
     HIPCHK(hipStreamWaitEvent(s, book->ev_p0, 0));
+    hipLaunchKernelGGL(bt_finalize_kernel, dim3((int)std::min<int64_t>((n_opts + 255) / 256, 1024)), dim3(256), 0, s, a);
+    HIPCHK(hipGetLastError());
     return BT_OK;
 }
 
@@ -1039,6 +1430,84 @@ int launch(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream)
 
 }  // namespace
 
+namespace {
+
+// Batch workspaces, one per (device, stream, number type), kept until
+// bt_shutdown.
+struct WsEntry {
+    int device;
+    hipStream_t stream;
+    bool greeks;
+    bt_book *ws;
+};
+std::mutex g_ws_mu;
+std::vector<WsEntry> g_ws;
+
+bool same_tune(const bt_tune &x, const bt_tune &y)
+{
+    return x.wgs_per_cu == y.wgs_per_cu && x.level_factor == y.level_factor && x.pool_points == y.pool_points &&
+           x.band_levels == y.band_levels && x.flags == y.flags;
+}
+
+// The workspace for a call of n options with N up to max_N on `stream`;
+// (re)built when there is none or it is too small or differently tuned.
+int batch_workspace(hipStream_t stream, int n, int max_N, const bt_tune *tune, bool greeks, bt_book **out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    const bt_tune t = batch_tune(tune, greeks);
+    WsEntry *e = nullptr;
+    for (WsEntry &w : g_ws)
+        if (w.device == dev && w.stream == stream && w.greeks == greeks) e = &w;
+    if (e && e->ws->cap_n >= n && e->ws->cap_N >= max_N && same_tune(e->ws->tune, t)) {
+        *out = e->ws;
+        return BT_OK;
+    }
+    // growing allocates and waits for the device: not allowed under capture
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIPCHK(hipStreamIsCapturing(stream, &cs));
+    if (cs != hipStreamCaptureStatusNone) return BT_ENOSUPP;
+    int cap_n = n, cap_N = max_N;
+    if (e) {
+        if (same_tune(e->ws->tune, t)) {
+            cap_n = std::max(cap_n, e->ws->cap_n);
+            cap_N = std::max(cap_N, e->ws->cap_N);
+        }
+        bt_book_destroy(e->ws);
+        e->ws = nullptr;
+    }
+    bt_book *b = new (std::nothrow) bt_book();
+    if (!b) return BT_ENOMEM;
+    Carver cv;
+    const int rc = batch_build(b, cap_n, cap_N, t, 0, (int64_t)1 << 31, cv);
+    if (rc != BT_OK) {
+        book_free(b);
+        delete b;
+        if (e) g_ws.erase(g_ws.begin() + (e - g_ws.data()));
+        return rc;
+    }
+    if (e) e->ws = b;
+    else g_ws.push_back(WsEntry{dev, stream, greeks, b});
+    *out = b;
+    return BT_OK;
+}
+
+int price_batch(const bt_params *d_params, int32_t n, int32_t max_N, bt_result *d_out, bt_grad *d_grad, void *stream,
+                const bt_tune *tune)
+{
+    if (n < 0 || max_N < 1 || max_N > BT_MAX_N || (n > 0 && (!d_params || !d_out))) return BT_EINVAL;
+    if (tune && tune->band_levels != 0 && (tune->band_levels < MIN_BAND || tune->band_levels > BAND)) return BT_EINVAL;
+    if (n == 0) return BT_OK;
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    bt_book *ws = nullptr;
+    const int rc = batch_workspace((hipStream_t)stream, n, max_N, tune, d_grad != nullptr, &ws);
+    if (rc != BT_OK) return rc;
+    return d_grad ? launch_all<D4>(ws, d_out, d_grad, stream, d_params, n, max_N)
+                  : launch_all<double>(ws, d_out, nullptr, stream, d_params, n, max_N);
+}
+
+}  // namespace
+
 extern "C" {
 
 int bt_book_price(bt_book *book, bt_result *d_out, void *stream)
@@ -1052,6 +1521,19 @@ int bt_book_price_grad(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *s
     if (!book || !d_out || !d_grad) return BT_EINVAL;
     if (!book->greeks) return BT_ENOSUPP;
     return launch<D4>(book, d_out, d_grad, stream);
+}
+
+int bt_price_batch(const bt_params *d_params, int32_t n, int32_t max_N, bt_result *d_out, void *stream,
+                   const bt_tune *tune)
+{
+    return price_batch(d_params, n, max_N, d_out, nullptr, stream, tune);
+}
+
+int bt_price_grad_batch(const bt_params *d_params, int32_t n, int32_t max_N, bt_result *d_out, bt_grad *d_grad,
+                        void *stream, const bt_tune *tune)
+{
+    if (n > 0 && !d_grad) return BT_EINVAL;
+    return price_batch(d_params, n, max_N, d_out, d_grad, stream, tune);
 }
 
 int bt_book_resolve_overflow(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream,
@@ -1082,10 +1564,19 @@ int bt_book_resolve_overflow(bt_book *book, bt_result *d_out, bt_grad *d_grad, v
     const std::function<int(const std::vector<int> &, int)> price_set = [&](const std::vector<int> &ids,
                                                                             int mult) -> int {
         std::vector<bt_params> sub;
-        for (int i : ids) sub.push_back(book->params[i]);
+        int sub_N = 1;
+        for (int i : ids) {
+            sub.push_back(book->params[i]);
+            sub_N = std::max(sub_N, (int)book->params[i].N);
+        }
         bt_tune t = book->tune;
         t.flags = d_grad ? BT_TUNE_GREEKS : 0;
         t.level_factor = base_lf * mult;
+        // a level that large would need offsets beyond int: these stay overflowed
+        if ((int64_t)t.level_factor * (sub_N + 2) * 3 + (sub_N + 2) > INT32_MAX) {
+            still.insert(still.end(), ids.begin(), ids.end());
+            return BT_OK;
+        }
         t.pool_points = (int32_t)std::min<int64_t>(base_pool * mult, (int64_t)1 << 22);
         t.wgs_per_cu = 1;
         bt_book *sb = nullptr;
@@ -1282,6 +1773,16 @@ int bt_price(const bt_params *p, bt_result *out)
 
 int bt_shutdown(void)
 {
+    {
+        std::lock_guard<std::mutex> lock(g_ws_mu);
+        int cur = 0;
+        const bool have_dev = hipGetDevice(&cur) == hipSuccess;
+        for (WsEntry &w : g_ws) {
+            if (hipSetDevice(w.device) == hipSuccess) bt_book_destroy(w.ws);
+        }
+        g_ws.clear();
+        if (have_dev) (void)hipSetDevice(cur);
+    }
     if (t_price_book) {
         bt_book_destroy(t_price_book);
         t_price_book = nullptr;

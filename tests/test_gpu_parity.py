@@ -157,8 +157,23 @@ def test_repeat_is_bitwise_deterministic():
     r1 = book.results()
     book.price()
     r2 = book.results()
+    # which options outgrow the shared big-node arena can depend on how the
+    # GPU schedules a launch's workgroups (include/bt.h); every option that
+    # ends BT_OK has the same bits in both calls, and re-pricing the others
+    # gives those same bits too
+    for r in (r1, r2):
+        assert np.all((r["status"] == 0) | (r["status"] == bt.BT_EOVERFLOW)), r["status"]
+    ok = (r1["status"] == 0) & (r2["status"] == 0)
+    say(f"  BT_OK in both calls: {int(ok.sum())}/{len(b)}")
+    assert r1[ok].tobytes() == r2[ok].tobytes()
+    book.resolve_overflow()
+    r3 = book.results()
+    book.price()
+    book.resolve_overflow()
+    r4 = book.results()
     book.close()
-    assert r1.tobytes() == r2.tobytes()
+    assert np.all(r3["status"] == 0) and r3.tobytes() == r4.tobytes()
+    assert r3[ok].tobytes() == r1[ok].tobytes()
 
 
 def test_small_work_buffers_still_exact_or_overflow():
@@ -177,7 +192,10 @@ def test_small_work_buffers_still_exact_or_overflow():
         if res[i]["status"] == 0:
             check(b, res, [i])
         else:
-            assert np.isnan(res[i]["ask"]) or np.isnan(res[i]["bid"])
+            # no partial result: both prices NaN, counts zero
+            assert np.isnan(res[i]["ask"]) and np.isnan(res[i]["bid"]) and np.isnan(res[i]["price0"])
+            assert res[i]["bp_total_ask"] == 0 and res[i]["bp_total_bid"] == 0
+            assert res[i]["bp_max_ask"] == 0 and res[i]["bp_max_bid"] == 0
     say("case: level factor 1, overflow resolved")
     check(b, bt.price_book(b, tune=dict(level_factor=1)))
 
