@@ -235,6 +235,25 @@ int bt_price_batch(const bt_params *d_params, int32_t n, int32_t max_N, bt_resul
 int bt_price_grad_batch(const bt_params *d_params, int32_t n, int32_t max_N, bt_result *d_out, bt_grad *d_grad,
                         void *stream, const bt_tune *tune);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: as
+ * bt_price_batch (prices only, the library's tuning with level_factor 8 and
+ * pool_points 16384), but every buffer comes from one device array of
+ * BT_STATIC_SCRATCH_BYTES that the library defines; no call allocates or
+ * frees device memory.  Each GPU the library runs on holds its own copy of
+ * the array until the process ends.  Limits: n <= BT_STATIC_MAX_OPTIONS and
+ * max_N <= BT_STATIC_MAX_N, else BT_EINVAL; 32 persistent workgroups per
+ * party, and the seller, buyer and zero-cost recursions run one after the
+ * other on `stream`.  Every call on a GPU shares that GPU's array (its
+ * counters are cleared at the start of each call): calls that overlap on
+ * one GPU -- on different streams, or from different threads without
+ * ordering -- race and give wrong results.  Options that outgrow the array's
+ * buffers end BT_EOVERFLOW with NaN prices. */
+#define BT_STATIC_SCRATCH_BYTES (256u << 20)
+#define BT_STATIC_MAX_OPTIONS 64
+#define BT_STATIC_MAX_N 1024
+int bt_price_batch_static(const bt_params *d_params, int32_t n, int32_t max_N, bt_result *d_out, void *stream);
+
 /* Completes a pricing call whose options overflowed the book's buffers
  * (status BT_EOVERFLOW: a tree whose band levels, private levels or
  * big-node temporaries outgrew what the book sized for them): waits for

@@ -24,7 +24,8 @@ EUROPEAN, COST_AT_T0 = 1, 2
 # Function names declared in include/bt.h.
 ABI_FUNCTIONS = ("bt_autotune", "bt_book_create", "bt_book_info", "bt_book_price", "bt_book_price_grad",
                  "bt_book_resolve_overflow", "bt_book_timings", "bt_book_destroy", "bt_price", "bt_shutdown",
-                 "bt_price_batch", "bt_price_grad_batch", "bt_model_constants", "bt_strerror",
+                 "bt_price_batch", "bt_price_grad_batch", "bt_price_batch_static", "bt_model_constants",
+                 "bt_strerror",
                  "bt_version", "bt_last_hip_error")
 
 
@@ -81,6 +82,7 @@ def lib():
     L.bt_price.argtypes = [vp, vp]
     L.bt_price_batch.argtypes = [vp, i32, i32, vp, vp, vp]
     L.bt_price_grad_batch.argtypes = [vp, i32, i32, vp, vp, vp, vp]
+    L.bt_price_batch_static.argtypes = [vp, i32, i32, vp, vp]
     L.bt_shutdown.argtypes = []
     L.bt_model_constants.argtypes = [vp, dp, dp, dp, dp, dp]
     L.bt_strerror.argtypes = [ctypes.c_int]
@@ -89,7 +91,7 @@ def lib():
     L.bt_last_hip_error.argtypes = []
     for f in ("bt_autotune", "bt_book_create", "bt_book_info", "bt_book_price", "bt_book_price_grad", "bt_book_timings", "bt_book_resolve_overflow",
               "bt_price", "bt_shutdown", "bt_model_constants", "bt_version", "bt_last_hip_error",
-              "bt_price_batch", "bt_price_grad_batch"):
+              "bt_price_batch", "bt_price_grad_batch", "bt_price_batch_static"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -229,6 +231,19 @@ def bt_price_grad_batch(d_params_ptr, n, max_N, d_out_ptr, d_grad_ptr, stream=No
                                      ctypes.c_void_p(d_out_ptr), ctypes.c_void_p(d_grad_ptr),
                                      ctypes.c_void_p(_stream_ptr(stream)),
                                      ctypes.byref(t) if t is not None else None), "bt_price_grad_batch")
+
+
+def bt_price_batch_static(d_params_ptr, n, max_N, d_out_ptr, stream=None):
+    """The no-allocation variant of bt_price_batch (include/bt.h): the
+    library's fixed device scratch array, at most BT_STATIC_MAX_OPTIONS
+    options of at most BT_STATIC_MAX_N steps."""
+    _check(lib().bt_price_batch_static(ctypes.c_void_p(d_params_ptr), int(n), int(max_N),
+                                       ctypes.c_void_p(d_out_ptr), ctypes.c_void_p(_stream_ptr(stream))),
+           "bt_price_batch_static")
+
+
+BT_STATIC_MAX_OPTIONS = 64
+BT_STATIC_MAX_N = 1024
 
 
 def params_tensor(params, device="cuda"):

@@ -1131,7 +1131,8 @@ bt_tune batch_tune(const bt_tune *tune, bool greeks)
 // for min(cap_n, resident workgroups) such tree sides, between the book's
 // floor and arena_cap doubles.  The buffers come from `carve` (hipMalloc, or a
 // caller's region).  `grid_cap` (0: none) bounds the persistent workgroups.
-int batch_build(bt_book *b, int cap_n, int cap_N, const bt_tune &t, int grid_cap, int64_t arena_cap, Carver &cv)
+int batch_build(bt_book *b, int cap_n, int cap_N, const bt_tune &t, int grid_cap, int64_t arena_cap, Carver &cv,
+                int64_t min_private = MIN_PRIVATE_POINTS, bool streams = true)
 {
     const bool greeks = (t.flags & BT_TUNE_GREEKS) != 0;
     const int64_t nt = greeks ? (int64_t)(sizeof(D4) / sizeof(double)) : 1;
@@ -1140,7 +1141,7 @@ int batch_build(bt_book *b, int cap_n, int cap_N, const bt_tune &t, int grid_cap
     const int nbands_max = (cap_N + band) / band;
     const int64_t pool = (int64_t)t.pool_points * 4 * nt;
     const int64_t arena_floor = std::min(std::max<int64_t>(DEFAULT_ARENA_DOUBLES * nt, 64 * pool), arena_cap);
-    int64_t ppts = std::max({(int64_t)lf * (WG + 1), MIN_PRIVATE_POINTS * std::max(1, lf / DEFAULT_LEVEL_FACTOR),
+    int64_t ppts = std::max({(int64_t)lf * (WG + 1), min_private * std::max(1, lf / DEFAULT_LEVEL_FACTOR),
                              16 * (int64_t)cap_N});
     if ((int64_t)lf * (cap_N + 2) * 3 + (cap_N + 2) > INT32_MAX || ppts * 3 + (WG + 1) > INT32_MAX) return BT_EINVAL;
     // task capacity: cap_n tree sides per party, launch_blocks each
@@ -1260,6 +1261,7 @@ int batch_build(bt_book *b, int cap_n, int cap_N, const bt_tune &t, int grid_cap
     b->nbands_max = nbands_max;
     b->n_fill = n_fill;
     b->grid = grid; b->grid_p0 = grid_p0;
+    if (!streams) return BT_OK;
     HIPCHK(hipStreamCreateWithFlags(&b->s_ask, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&b->s_p0, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
@@ -1358,9 +1360,15 @@ int launch_all(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream, c
         HIPCHK(hipGetLastError());
     }
     if (book->timing) HIPCHK(hipEventRecord(ev[1], s));
-    HIPCHK(hipEventRecord(book->ev_fork, s));
-    HIPCHK(hipStreamWaitEvent(book->s_ask, book->ev_fork, 0));
-    HIPCHK(hipStreamWaitEvent(book->s_p0, book->ev_fork, 0));
+    // a workspace without streams of its own runs the three recursions one
+    // after the other on the caller's stream
+    const bool fork = book->s_ask != nullptr;
+    hipStream_t s_ask = fork ? book->s_ask : s, s_p0 = fork ? book->s_p0 : s;
+    if (fork) {
+        HIPCHK(hipEventRecord(book->ev_fork, s));
+        HIPCHK(hipStreamWaitEvent(s_ask, book->ev_fork, 0));
+        HIPCHK(hipStreamWaitEvent(s_p0, book->ev_fork, 0));
+    }
     // buyer
     // (a batch planned on the device runs every launch; its task counts are
     // on the device)
@@ -1374,24 +1382,26 @@ int launch_all(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream, c
     }
     if (book->timing) HIPCHK(hipEventRecord(ev[2], s));
     // seller
-    if (book->timing) HIPCHK(hipEventRecord(ev[3], book->s_ask));
+    if (book->timing) HIPCHK(hipEventRecord(ev[3], s_ask));
     for (int r = 0; r < book->nbands_max; r++) {
         if (wgs(r, 0) == 0) continue;
-        hipLaunchKernelGGL((bt_band_kernel<0, T>), dim3(wgs(r, 0)), dim3(WG), 0, book->s_ask, a, r);
+        hipLaunchKernelGGL((bt_band_kernel<0, T>), dim3(wgs(r, 0)), dim3(WG), 0, s_ask, a, r);
         HIPCHK(hipGetLastError());
     }
-    if (book->timing) HIPCHK(hipEventRecord(ev[4], book->s_ask));
+    if (book->timing) HIPCHK(hipEventRecord(ev[4], s_ask));
     // zero-cost recursion
-    if (book->timing) HIPCHK(hipEventRecord(ev[5], book->s_p0));
+    if (book->timing) HIPCHK(hipEventRecord(ev[5], s_p0));
     if (book->device_plan || book->n_items > 0) {
-        hipLaunchKernelGGL(bt_price0_kernel, dim3(book->grid_p0), dim3(WG), 0, book->s_p0, a);
+        hipLaunchKernelGGL(bt_price0_kernel, dim3(book->grid_p0), dim3(WG), 0, s_p0, a);
         HIPCHK(hipGetLastError());
     }
-    if (book->timing) HIPCHK(hipEventRecord(ev[6], book->s_p0));
-    HIPCHK(hipEventRecord(book->ev_ask, book->s_ask));
-    HIPCHK(hipEventRecord(book->ev_p0, book->s_p0));
-    HIPCHK(hipStreamWaitEvent(s, book->ev_ask, 0));
-    HIPCHK(hipStreamWaitEvent(s, book->ev_p0, 0));
+    if (book->timing) HIPCHK(hipEventRecord(ev[6], s_p0));
+    if (fork) {
+        HIPCHK(hipEventRecord(book->ev_ask, s_ask));
+        HIPCHK(hipEventRecord(book->ev_p0, s_p0));
+        HIPCHK(hipStreamWaitEvent(s, book->ev_ask, 0));
+        HIPCHK(hipStreamWaitEvent(s, book->ev_p0, 0));
+    }
     hipLaunchKernelGGL(bt_finalize_kernel, dim3((int)std::min<int64_t>((n_opts + 255) / 256, 1024)), dim3(256), 0, s, a);
     HIPCHK(hipGetLastError());
     return BT_OK;
@@ -1492,6 +1502,64 @@ int batch_workspace(hipStream_t stream, int n, int max_N, const bt_tune *tune, b
     return BT_OK;
 }
 
+// The device array behind bt_price_batch_static: every buffer of its
+// workspace is carved out of it, so that entry point allocates nothing.
+// Each GPU holds its own copy until the process ends; in host code the name
+// is only a stand-in, its device address comes from hipGetSymbolAddress.
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)256 << 20;
+__device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+struct StaticWs {
+    void *ptr = nullptr;       // this device's address of `scratch`
+    bt_book *ws = nullptr;     // the workspace carved out of it
+};
+std::mutex g_static_mu;
+StaticWs g_static[MAX_DEVICES];
+
+// Set-up on the current device, once: the scratch array's device address,
+// then the workspace carved from it (bt.h: BT_STATIC_MAX_OPTIONS options of
+// up to BT_STATIC_MAX_N steps, 32 persistent workgroups per party, the
+// recursions one after the other on the caller's stream).
+int static_workspace(bt_book **out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return BT_ENOSUPP;
+    StaticWs &e = g_static[dev];
+    if (e.ws) {
+        *out = e.ws;
+        return BT_OK;
+    }
+    if (!e.ptr) {
+        void *p = nullptr;
+        const hipError_t err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (err != hipSuccess || !p) {
+            g_last_hip = (int)err;
+            return BT_EHIP;
+        }
+        e.ptr = p;
+    }
+    bt_book *b = new (std::nothrow) bt_book();
+    if (!b) return BT_ENOMEM;
+    b->carved = true;
+    Carver cv;
+    cv.base = (char *)e.ptr;
+    cv.cap = STATIC_SCRATCH_BYTES;
+    bt_tune t = batch_tune(nullptr, false);
+    t.level_factor = 8;
+    t.pool_points = 16384;
+    const int rc = batch_build(b, BT_STATIC_MAX_OPTIONS, BT_STATIC_MAX_N, t, 32, (int64_t)1 << 22, cv, 0, false);
+    if (rc != BT_OK) {
+        book_free(b);
+        delete b;
+        return rc;
+    }
+    e.ws = b;
+    *out = b;
+    return BT_OK;
+}
+
 int price_batch(const bt_params *d_params, int32_t n, int32_t max_N, bt_result *d_out, bt_grad *d_grad, void *stream,
                 const bt_tune *tune)
 {
@@ -1527,6 +1595,18 @@ int bt_price_batch(const bt_params *d_params, int32_t n, int32_t max_N, bt_resul
                    const bt_tune *tune)
 {
     return price_batch(d_params, n, max_N, d_out, nullptr, stream, tune);
+}
+
+int bt_price_batch_static(const bt_params *d_params, int32_t n, int32_t max_N, bt_result *d_out, void *stream)
+{
+    if (n < 0 || n > BT_STATIC_MAX_OPTIONS || max_N < 1 || max_N > BT_STATIC_MAX_N || (n > 0 && (!d_params || !d_out)))
+        return BT_EINVAL;
+    if (n == 0) return BT_OK;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    bt_book *ws = nullptr;
+    const int rc = static_workspace(&ws);
+    if (rc != BT_OK) return rc;
+    return launch_all<double>(ws, d_out, nullptr, stream, d_params, n, max_N);
 }
 
 int bt_price_grad_batch(const bt_params *d_params, int32_t n, int32_t max_N, bt_result *d_out, bt_grad *d_grad,
