@@ -8,12 +8,20 @@ recursions (ask, bid) and the zero-cost recursion (price0) of every tree.
 Inputs are resident on the GPU before timing starts.
 
 Printed: one JSON line with tree nodes/s (value), per-kernel HIP-event
-times, the roofline of the dominant kernel, batched options/s on a mixed
-4096-option book, plain single-option forward on the same GPU, batched
-prices with Greeks on a 1024-option book, and the CPU oracle timed on the
-host on a bounded sample.
+times, the roofline of the dominant kernel (algorithmic and counter-based
+figures, and the latency chain that binds it), batched options/s on the
+mixed 4096-option book against plain single-option forward on the same
+options, the Greeks book through the autograd Function, the stress mix (a
+stated subset of its 16384 options in graph-captured batches, Greeks, and
+the N = 20000 put), and the CPU oracle timed on the host on a bounded
+sample, compared element by element with the GPU.
+
+``--counter-summary DIR`` instead prints per-kernel means of the counters
+in a rocprofv3 ``--pmc`` output directory (how profiles/ is written).
 """
 import argparse
+import csv
+import glob
 import json
 import os
 import sys
@@ -29,6 +37,8 @@ if ROOT not in sys.path:
 # two operations; this path performs no FMAs).
 PEAK_FP64_NONFMA_TFLOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
+CLOCK_HZ = 2.4e9
+N_CU = 256
 
 
 def log(*a):
@@ -42,20 +52,52 @@ def cpu_cores():
         return os.cpu_count() or 1
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def oracle_leg(sample, cores):
     """Times the CPU oracle on a bounded sample: every option of the sample
-    (ask, bid and price0), one option per task on `cores` threads."""
+    (ask, bid and price0), one option per task on `cores` threads; returns
+    the timing and the oracle's results in sample order."""
     from concurrent.futures import ThreadPoolExecutor
 
     import oracle
     from paper_1110_2477_amd import workloads as W
 
+    order = sorted(range(len(sample)), key=lambda i: -int(sample[i]["N"]))
     t0 = time.perf_counter()
     with ThreadPoolExecutor(max_workers=cores) as ex:
-        list(ex.map(oracle.price_params, sorted(sample, key=lambda p: -int(p["N"]))))
+        outs = list(ex.map(lambda i: oracle.price_params(sample[i]), order))
     dt = time.perf_counter() - t0
+    res = [None] * len(sample)
+    for i, o in zip(order, outs):
+        res[i] = o
     nodes = W.nodes(sample)
-    return dict(seconds=dt, nodes=nodes, nodes_per_s=nodes / dt, options_per_s=len(sample) / dt)
+    return dict(seconds=dt, nodes=nodes, nodes_per_s=nodes / dt, options_per_s=len(sample) / dt), res
+
+
+def compare_with_oracle(gpu, ref):
+    """Largest relative difference of ask, bid, price0 and whether every
+    breakpoint count is equal, GPU results against oracle results."""
+    worst, counts_equal, bitexact = 0.0, True, 0
+    for r, o in zip(gpu, ref):
+        for key in ("ask", "bid", "price0"):
+            b = o[key]
+            e = abs(r[key] - b) / abs(b) if b != 0 else abs(r[key])
+            worst = max(worst, float(e))
+        bitexact += int(r["ask"] == o["ask"] and r["bid"] == o["bid"] and r["price0"] == o["price0"])
+        for key in ("bp_total_ask", "bp_total_bid", "bp_max_ask", "bp_max_bid"):
+            counts_equal &= int(r[key]) == int(o[key])
+    return dict(max_rel_err=worst, counts_equal=bool(counts_equal), bit_exact_options=bitexact, options=len(ref))
 
 
 def kernel_source_digest():
@@ -72,21 +114,59 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter's reading for
-    a plain copy of known size), or None when the summary is missing or was
-    taken on other kernel sources."""
-    path = os.path.join(ROOT, "profiles", "band_kernel_traffic_paper_grid.txt")
+def _profile_kv(name):
+    path = os.path.join(ROOT, "profiles", name)
     try:
         with open(path) as f:
             kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
     except OSError:
         return None
     kv = {k.strip(): v.strip() for k, v in kv.items()}
-    if kv.get("kernel_source_sha256") != kernel_source_digest() or kv.get("kernel") != kernel:
+    if kv.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    return kv
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter's reading for
+    a plain copy of known size), or None when the summary is missing or was
+    taken on other kernel sources."""
+    kv = _profile_kv("band_kernel_traffic_paper_grid.txt")
+    if not kv or kv.get("kernel") != kernel:
         return None
     return float(kv["hbm_bytes_per_launch"])
+
+
+def measured_counters(kernel):
+    """Per-launch SQ counters of `kernel` from the committed summary
+    (profiles/band_kernel_counters_paper_grid.txt), or None when missing or
+    taken on other kernel sources."""
+    kv = _profile_kv("band_kernel_counters_paper_grid.txt")
+    if not kv:
+        return None
+    key = kernel.replace(" ", "")
+    out = {k.split("|", 1)[1]: float(v) for k, v in kv.items() if k.startswith(key + "|")}
+    return out or None
+
+
+def counter_summary(d):
+    """Per-kernel means of every counter in a rocprofv3 --pmc csv directory."""
+    rows = []
+    for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as f:
+            rows += list(csv.DictReader(f))
+    acc = {}
+    for r in rows:
+        k = (r["Kernel_Name"], r["Counter_Name"])
+        acc.setdefault(k, {})
+        disp = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        acc[k][disp] = acc[k].get(disp, 0.0) + float(r["Counter_Value"])
+    out = {}
+    for (kern, ctr), per in sorted(acc.items()):
+        vals = list(per.values())
+        out.setdefault(kern, {})[ctr] = dict(dispatches=len(vals), mean=sum(vals) / len(vals))
+    return out
 
 
 def timed_job(bk, greeks, torch, np, bt):
@@ -106,41 +186,77 @@ def timed_job(bk, greeks, torch, np, bt):
     return time.perf_counter() - t0, t1 - t0, n_over
 
 
-def stress_leg(bt, W, np, torch):
-    """One batch of 2048 options of the stress generator, and the long put."""
+def plain_leg(bt, W, np, sample):
+    """bt_price one option at a time (host in, host out, synchronous) over
+    `sample`, after one untimed call per distinct N (bt_price rebuilds its
+    cached one-option book when N changes, which is timed as part of the
+    plain path)."""
+    bt.bt_price(sample[0])
+    t0 = time.perf_counter()
+    res = [bt.bt_price(p) for p in sample]
+    dt = time.perf_counter() - t0
+    return dt, res
+
+
+def stress_leg(bt, W, np, torch, n_batches):
+    """The stress mix (16384 options, N log-uniform in [64, 8192]): its first
+    n_batches batches of 2048 options as books replayed from captured HIP
+    graphs with the autotuner's tuning, Greeks of its first 256 options
+    through bt_price_grad_batch, and the N = 20000 put with and without
+    Greeks.  Every job is timed whole (re-pricing of overflowed options
+    included)."""
     res = {}
-    batch = W.stress_book(16384, seed=5)[:2048]
-    pick = np.random.default_rng(66).choice(len(batch), 256, replace=False)
-    best, _ = bt.bt_autotune(batch[np.sort(pick)], reps=1)
+    stress = W.stress_book(16384, seed=5)
+    pick = np.random.default_rng(66).choice(2048, 256, replace=False)
+    t0 = time.perf_counter()
+    best, _ = bt.bt_autotune(stress[:2048][np.sort(pick)], reps=1)
     tune = {k: best[k] for k in ("band_levels", "wgs_per_cu")}
-    for greeks in (False, True):
-        # Greeks on the first 512 options of the batch (four times the work per option)
-        b = batch[:512] if greeks else batch
-        name = "batch_512_greeks" if greeks else "batch_2048_prices"
-        bk = bt.Book(b, tune=tune, greeks=greeks, graph=True)
-        call = bk.price_grad if greeks else bk.price
-        log(f"{name}: capture and first call")
-        call()
-        torch.cuda.synchronize()
-        log(f"{name}: timed call")
-        dt, dt_call, n_over = timed_job(bk, greeks, torch, np, bt)
-        log(f"{name}: {dt:.1f} s, of which {dt - dt_call:.1f} s re-pricing {n_over} options with larger levels")
-        ok = bool(np.all(bk.results()["status"] == 0))
+    res["batch_tune"] = dict(tune, autotune_seconds=time.perf_counter() - t0)
+    total_s, total_nodes, total_opts, repriced, ok = 0.0, 0, 0, 0, True
+    per_batch = []
+    for bi in range(n_batches):
+        b = stress[2048 * bi:2048 * (bi + 1)]
+        bk = bt.Book(b, tune=tune, graph=True)
+        # one pass: the call captures the launch sequence and replays it
+        dt, dt_call, n_over = timed_job(bk, False, torch, np, bt)
+        ok &= bool(np.all(bk.results()["status"] == 0))
         bk.close()
-        res[name] = dict(options_per_s=len(b) / dt, ms=dt * 1e3, tree_nodes_per_s=W.nodes(b) / dt, ok=ok,
-                         pricing_call_ms=dt_call * 1e3, options_repriced=n_over)
-        log(f"stress {name}: {res[name]}")
-    res["batch_tune"] = tune
+        log(f"stress batch {bi}: {dt:.1f} s ({n_over} re-priced)")
+        per_batch.append(dt * 1e3)
+        total_s += dt
+        total_nodes += W.nodes(b)
+        total_opts += len(b)
+        repriced += n_over
+    res["forward_graph_batches"] = dict(
+        options=total_opts, batches=n_batches, batch_size=2048, ms_per_batch=per_batch,
+        options_per_s=total_opts / total_s, tree_nodes_per_s=total_nodes / total_s, ok=ok,
+        options_repriced=repriced,
+        subset=f"options 0..{total_opts - 1} of the 16384 (the first {n_batches} of 8 batches of 2048)")
+    g = stress[:256]
+    d = bt.params_tensor(g)
+    # a call of the same size on short trees builds the workspace
+    cheap = g.copy()
+    cheap["N"] = 64
+    bt.price_batch(bt.params_tensor(cheap), max_N=8192, grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out, gr = bt.price_batch(d, max_N=8192, grad=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    r = bt.as_results(out)
+    res["greeks_batch_256"] = dict(options_per_s=len(g) / dt, ms=dt * 1e3, tree_nodes_per_s=W.nodes(g) / dt,
+                                   ok=bool(np.all(r["status"] == 0)), entry="bt_price_grad_batch",
+                                   subset="options 0..255 of the 16384")
+    bt.bt_shutdown()
     lp = W.long_put()
     for greeks in (False, True):
         log(f"put N=20000, greeks={greeks}")
         bk = bt.Book(lp, greeks=greeks)
-        call = bk.price_grad if greeks else bk.price
-        call()
+        (bk.price_grad if greeks else bk.price)()
         torch.cuda.synchronize()
         dt, _, _ = timed_job(bk, greeks, torch, np, bt)
-        res["put_N20000_" + ("greeks" if greeks else "prices")] = dict(ms=dt * 1e3, tree_nodes_per_s=W.nodes(lp) / dt,
-                                                                    ok=bool(np.all(bk.results()["status"] == 0)))
+        res["put_N20000_" + ("greeks" if greeks else "prices")] = dict(
+            ms=dt * 1e3, tree_nodes_per_s=W.nodes(lp) / dt, ok=bool(np.all(bk.results()["status"] == 0)))
         bk.close()
     log(f"stress: {res}")
     return res
@@ -152,15 +268,20 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--no-extra", action="store_true", help="skip the mixed-book and plain legs")
-    ap.add_argument("--stress", action="store_true",
-                    help="also time the stress mix: one batch of 2048 options of the 16384-option "
-                         "generator (N log-uniform in [64, 8192]) through a captured graph with the "
-                         "autotuner's choice (prices; Greeks on its first 512), and the N=20000 put")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the mixed-book, plain, Greeks-book and stress legs")
+    ap.add_argument("--stress-batches", type=int, default=2, metavar="B",
+                    help="batches of 2048 stress options timed in the stress leg (1..8; default 2)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB from one device buffer to another (the known-size "
                          "reference for the FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--counter-summary", metavar="DIR",
+                    help="only print per-kernel means of the counters in a rocprofv3 --pmc output "
+                         "directory (csv) and exit")
     args = ap.parse_args()
+    if args.counter_summary:
+        print(json.dumps(counter_summary(args.counter_summary), indent=1))
+        return
     if args.copy_calibration:
         import torch
         n = args.copy_calibration << 20
@@ -188,6 +309,7 @@ def main():
     nodes = W.nodes(grid)
     book = bt.Book(grid, tune=dict(flags=bt.BT_TUNE_TIMING))
     log(f"workload: 48-tree grid, {nodes} nodes; warmup {args.warmup}")
+
     def step():
         # one complete pricing of the book: the kernels, then the host check
         # for options that outgrew the level buffers (re-priced with larger
@@ -208,8 +330,8 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kms, calls = book.timings()
-    res = book.results()
-    assert remaining == 0 and np.all(res["status"] == 0), res["status"]
+    grid_res = book.results()
+    assert remaining == 0 and np.all(grid_res["status"] == 0), grid_res["status"]
     # how many options needed the second pass (same every step)
     book.price()
     n_resolved = int(np.sum(book.results()["status"] == bt.BT_EOVERFLOW))
@@ -241,6 +363,18 @@ def main():
         "kernel_ms": kernel_ms,
         "options_repriced_with_larger_levels_per_step": n_resolved,
     }
+
+    # the latency chain: the grid's costliest tree (the N = 5000 call with
+    # k = 1 %) priced alone; a step cannot end before its buyer recursion
+    crit = grid[(grid["N"] == 5000) & (grid["payoff"] == W.CALL) & (grid["K"] == 100.0) & (grid["k"] == 0.01)]
+    cb = bt.Book(crit)
+    cb.price()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cb.price()
+    torch.cuda.synchronize()
+    crit_ms = (time.perf_counter() - t0) * 1e3
+    cb.close()
 
     extra = {}
     if not args.no_extra:
@@ -276,58 +410,113 @@ def main():
             tune={k: best[k] for k in ("band_levels", "wgs_per_cu")}, autotune_seconds=tune_s,
             candidates_ms_on_sample=[[c["band_levels"], c["wgs_per_cu"], m] for c, m in timed])
         log(f"autotuned mixed book: {extra['batched_mixed_4096_autotuned']}")
-        # plain single-option forward: bt_price per option, synchronous
-        sub = grid[[0, 5, 11, 18]]  # four N=1500 trees (put and call, several k)
-        bt.bt_price(sub[0])
-        t0 = time.perf_counter()
-        for p in sub:
-            bt.bt_price(p)
-        dt = time.perf_counter() - t0
-        extra["plain_single_option_forward"] = dict(options_per_s=len(sub) / dt,
-                                                    tree_nodes_per_s=W.nodes(sub) / dt,
-                                                    sample="4 N=1500 trees of the grid, bt_price one at a time")
-        log(f"plain: {extra['plain_single_option_forward']}")
-        # batched forward + Greeks (d ask, d bid / d S0, sigma, R, k) on the
-        # 1024-option book with N in [500, 1500]
-        gb = W.greeks_book(1024, seed=4)
-        gk = bt.Book(gb, greeks=True)
-        gk.price_grad()
+        # plain single-option forward against batched forward on the same
+        # options: a seeded 32-option sample of the mixed book, priced one at
+        # a time by bt_price, then as one book; the full book's rate above is
+        # the batched figure at scale
+        sp = np.sort(np.random.default_rng(34).choice(len(mixed), 32, replace=False))
+        sample = mixed[sp]
+        dt_plain, plain_res = plain_leg(bt, W, np, sample)
+        sb = bt.Book(sample)
+        sb.price()
         torch.cuda.synchronize()
-        dt_g, _, n_retry = timed_job(gk, True, torch, np, bt)
-        ok = bool(np.all(gk.results()["status"] == 0))
+        dt_b, _, _ = timed_job(sb, False, torch, np, bt)
+        same = all(plain_res[i].tobytes() == sb.results()[i].tobytes() for i in range(len(sample)))
+        sb.close()
+        bt.bt_shutdown()
+        extra["plain_vs_batched"] = dict(
+            sample="32 options of the mixed 4096 book (numpy default_rng(34).choice)",
+            plain_options_per_s=len(sample) / dt_plain, plain_tree_nodes_per_s=W.nodes(sample) / dt_plain,
+            batched_same_options_per_s=len(sample) / dt_b,
+            batched_full_book_options_per_s=extra["batched_mixed_4096"]["options_per_s"],
+            batched_over_plain_same_options=dt_plain / dt_b,
+            batched_full_book_over_plain=(len(mixed) / dt) / (len(sample) / dt_plain),
+            same_results=bool(same))
+        log(f"plain vs batched: {extra['plain_vs_batched']}")
+        # batched forward + Greeks on the 1024-option Greeks book (N 500..1500)
+        # through the autograd Function (bt_price_grad_batch on torch's
+        # stream, parameters resident on the GPU), against the price-only
+        # batch entry point on the same options
+        from paper_1110_2477_amd.autograd import bt_autograd
+        gb = W.greeks_book(1024, seed=4)
+        spec = bt.params_tensor(gb)
+        S0 = torch.tensor(gb["S0"], dtype=torch.float64, device="cuda", requires_grad=True)
+        sig = torch.tensor(gb["sigma"], dtype=torch.float64, device="cuda", requires_grad=True)
+        Rr = torch.tensor(gb["R"], dtype=torch.float64, device="cuda", requires_grad=True)
+        kk = torch.tensor(gb["k"], dtype=torch.float64, device="cuda", requires_grad=True)
+
+        def fwd_bwd():
+            for t in (S0, sig, Rr, kk):
+                t.grad = None
+            ask, bid = bt_autograd(S0, sig, Rr, kk, spec, max_N=1500)
+            (ask.sum() + bid.sum()).backward()
+            return ask, bid
+
+        fwd_bwd()   # builds the workspace
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        gk.price()
+        ask, bid = fwd_bwd()
+        torch.cuda.synchronize()
+        dt_g = time.perf_counter() - t0
+        ok = bool(torch.isfinite(ask).all().item() and torch.isfinite(bid).all().item())
+        bt.price_batch(spec, max_N=1500)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bt.price_batch(spec, max_N=1500)
         torch.cuda.synchronize()
         dt_p = time.perf_counter() - t0
-        gk.close()
+        bt.bt_shutdown()
         extra["batched_greeks_1024"] = dict(options_per_s=len(gb) / dt_g, ms=dt_g * 1e3,
                                             price_only_ms=dt_p * 1e3, greeks_over_price=dt_g / dt_p,
-                                            ok=ok, options_repriced=n_retry)
+                                            ok=ok, entry="autograd Function over bt_price_grad_batch "
+                                                         "(forward + backward), price-only via bt_price_batch",
+                                            plain_options_per_s=extra["plain_vs_batched"]["plain_options_per_s"])
         log(f"greeks book: {extra['batched_greeks_1024']}")
+        extra["stress"] = stress_leg(bt, W, np, torch, max(1, min(8, args.stress_batches)))
     out.update(extra)
 
-    # roofline of the dominant kernel: binary64 operations of the canonical
-    # algorithm for every tree of the workload (counted by the oracle and
-    # stored by oracle/count_flops.py) over the kernel's HIP-event time; one
-    # launch is one band of one party, so flops / time over all launches is
-    # the average flops per launch over the average launch duration
+    # roofline of the dominant kernel.  achieved: binary64 operations of the
+    # canonical algorithm for every tree of the workload (counted by the
+    # oracle, stored by oracle/count_flops.py) per launch, over the kernel's
+    # average launch time; one launch is one band of one party.  The counter
+    # fields come from the committed rocprofv3 summary of the same sources.
     with open(os.path.join(ROOT, "oracle", "counts", "paper_grid_flops.json")) as f:
         counts = json.load(f)
     dom = max(("bid", "ask"), key=lambda k: kernel_ms[k])
     flops = counts[dom + "_flops"]
-    achieved = flops / (kernel_ms[dom] * 1e-3) / 1e12
-    # one launch per band of the longest tree: bands of 32 levels over N+1 levels
     n_launch = (int(grid["N"].max()) + 1 + 31) // 32
+    ms_launch = kernel_ms[dom] / n_launch
+    achieved = flops / n_launch / (ms_launch * 1e-3) / 1e12
     kernel = f"bt_band_kernel<{1 if dom == 'bid' else 0}, double>"
-    out["roofline"] = {"bound": "alu", "kernel": kernel,
-                       "achieved": achieved, "peak": PEAK_FP64_NONFMA_TFLOPS, "unit": "TFLOP/s",
-                       "frac": achieved / PEAK_FP64_NONFMA_TFLOPS, "traffic": measured_traffic(kernel),
-                       "flops_per_step": flops, "launches_per_step": n_launch,
-                       "flops_per_launch": flops / n_launch,
-                       "ms_per_launch": kernel_ms[dom] / n_launch}
-
-    if args.stress:
-        out["stress"] = stress_leg(bt, W, np, torch)
+    roof = {"bound": "latency", "kernel": kernel,
+            "achieved": achieved, "peak": PEAK_FP64_NONFMA_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_NONFMA_TFLOPS, "traffic": measured_traffic(kernel),
+            "flops_per_step": flops, "launches_per_step": n_launch,
+            "flops_per_launch": flops / n_launch, "ms_per_launch": ms_launch,
+            "binding": "the dependent chain of one tree's buyer recursion: each level waits for its "
+                       "largest node, updated by one wavefront",
+            "critical_tree_alone_ms": crit_ms, "step_over_critical_tree": ms_step / crit_ms}
+    c = measured_counters(kernel)
+    if c:
+        f64 = sum(c.get(k, 0.0) for k in ("SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64",
+                                           "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_TRANS_F64"))
+        # wave instructions x 64 lanes (an upper bound: masked lanes count)
+        roof["counters"] = {
+            "fp64_valu_wave_insts_per_launch": f64,
+            "fp64_valu_lane_ops_frac": f64 * 64 / (ms_launch * 1e-3) / (PEAK_FP64_NONFMA_TFLOPS * 1e12),
+            "valu_wave_insts_per_launch": c.get("SQ_INSTS_VALU"),
+            "lds_wave_insts_per_launch": c.get("SQ_INSTS_LDS"),
+            "lds_active_frac": (c["SQ_LDS_IDX_ACTIVE"] / (c["GRBM_GUI_ACTIVE"] * N_CU)
+                                if c.get("SQ_LDS_IDX_ACTIVE") and c.get("GRBM_GUI_ACTIVE") else None),
+            "lds_bank_conflict_per_access": (c["SQ_LDS_BANK_CONFLICT"] / max(1.0, c["SQ_LDS_IDX_ACTIVE"]
+                                                                           - c["SQ_LDS_BANK_CONFLICT"])
+                                             if c.get("SQ_LDS_IDX_ACTIVE") else None),
+            "valu_busy_frac": (c["SQ_ACTIVE_INST_VALU"] / (c["GRBM_GUI_ACTIVE"] * N_CU * 4)
+                               if c.get("SQ_ACTIVE_INST_VALU") and c.get("GRBM_GUI_ACTIVE") else None),
+            "mean_waves_per_cu": (c["SQ_WAVE_CYCLES"] / (c["GRBM_GUI_ACTIVE"] * N_CU)
+                                  if c.get("SQ_WAVE_CYCLES") and c.get("GRBM_GUI_ACTIVE") else None),
+            "source": "profiles/band_kernel_counters_paper_grid.txt"}
+    out["roofline"] = roof
 
     cores = cpu_cores()
     if not args.no_cpu:
@@ -344,15 +533,17 @@ def main():
         torch.cuda.synchronize()
         gpu_sample_s = time.perf_counter() - t0
         sample_ok = sb.resolve_overflow() == 0 and bool(np.all(sb.results()["status"] == 0))
+        gpu_res = sb.results()
         sb.close()
-        leg = oracle_leg(sample, cores)
+        leg, ref = oracle_leg(sample, cores)
         out["cpu_baseline"] = {"value": leg["nodes_per_s"], "unit": "tree nodes/s", "cores": cores,
-                               "kind": "oracle",
+                               "kind": "oracle", "cpu_model": cpu_model(),
                                "sample": "the 24 N=1500 trees of the grid and its 18 N=5000 trees other than "
                                          "the calls with k >= 0.5% (ask, bid, price0), one option per thread",
                                "options_per_s": leg["options_per_s"], "seconds": leg["seconds"],
                                "gpu_same_sample": {"value": W.nodes(sample) / gpu_sample_s,
-                                                   "seconds": gpu_sample_s, "ok": sample_ok}}
+                                                   "seconds": gpu_sample_s, "ok": sample_ok},
+                               "gpu_vs_oracle": compare_with_oracle(gpu_res, ref)}
     print(json.dumps(out), flush=True)
 
 

@@ -134,3 +134,24 @@ def nodes(b):
     """Tree nodes sum (N+1)(N+2)/2 of a book (levels 0..N)."""
     N = b["N"].astype(np.int64)
     return int(((N + 1) * (N + 2) // 2).sum())
+
+
+def greeks_fd_subset(n=1024):
+    """The 32 options of the Greeks book that the finite-difference and the
+    tangent checks use: PCG64(44).choice(n, 32) without replacement."""
+    return np.sort(np.random.Generator(np.random.PCG64(44)).choice(n, 32, replace=False))
+
+
+def stress_sample(s):
+    """Indices of a seeded sample of a stress book spanning its N range:
+    8 costly calls and bull spreads (N >= 4000, k >= 1 %), and 8 options from
+    each of the N bands [64, 256), [256, 2048), [2048, 8192] (any payoff),
+    drawn with PCG64(56) in that order."""
+    g = np.random.Generator(np.random.PCG64(56))
+    N, k, pay = s["N"], s["k"], s["payoff"]
+    heavy = np.flatnonzero((N >= 4000) & (k >= 0.01) & (pay != PUT))
+    pick = [g.choice(heavy, 8, replace=False)]
+    for lo, hi in ((64, 256), (256, 2048), (2048, 8193)):
+        band = np.setdiff1d(np.flatnonzero((N >= lo) & (N < hi)), pick[0])
+        pick.append(g.choice(band, 8, replace=False))
+    return np.sort(np.concatenate(pick))
