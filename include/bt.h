@@ -235,6 +235,37 @@ int bt_price_batch(const bt_params *d_params, int32_t n, int32_t max_N, bt_resul
 int bt_price_grad_batch(const bt_params *d_params, int32_t n, int32_t max_N, bt_result *d_out, bt_grad *d_grad,
                         void *stream, const bt_tune *tune);
 
+/* Prices and reverse-mode Greeks of a batch of options held in device
+ * memory: ask, bid, price0 and breakpoint counts into d_out[0..n-1] (the
+ * same bits as bt_price_batch) and d(ask, bid)/d(S0, sigma, R, k) into
+ * d_grad[0..n-1], asynchronous on `stream`.  The Greeks come from a reverse
+ * sweep through each tree (Section 3's recursion run backwards), not from
+ * carried tangents: one workgroup sweeps one tree side forward from level
+ * N+1, keeping every s-th level (s = ceil(sqrt(N+2))) as a checkpoint, then
+ * goes back from the root segment by segment, recomputing the levels
+ * between two checkpoints from the upper one and stepping the adjoint of
+ * each level back to the level below it through every node's merge,
+ * discount, slope restriction and exercise (each node recomputed on numbers
+ * that record their operations, its record read backwards).  Memory per
+ * tree side is O(sqrt(N)) levels instead of the N levels of the tree.
+ * Derivatives are those of the branch of the piecewise-smooth price active
+ * at the given parameters, as for bt_price_grad_batch (equal to its values
+ * up to rounding).
+ *   max_N  1..BT_MAX_N, bounds every option's N (larger: BT_EINVAL status);
+ * Workspace: one per (device, stream), kept until bt_shutdown, sized for n
+ * options and max_N: per workgroup two level slots and two adjoint slots of
+ * 32 points per node on average plus three large nodes, checkpoint and
+ * segment regions of half a slot per level they hold, the per-lane scratch
+ * and four large-node slots (nodes whose children hold up to 4 max_N + 64
+ * points), on at most one workgroup per compute unit and within a third of
+ * the free device memory.  A call that fits the existing
+ * workspace allocates nothing and can be captured; one that needs a larger
+ * workspace is refused with BT_ENOSUPP while the stream is capturing.
+ * Errors as bt_price_batch; an option whose levels or nodes outgrow the
+ * workspace ends BT_EOVERFLOW with NaN prices and Greeks. */
+int bt_price_adjoint_batch(const bt_params *d_params, int32_t n, int32_t max_N, bt_result *d_out, bt_grad *d_grad,
+                           void *stream);
+
 /* For callers that cannot allocate device memory -- code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc: as
  * bt_price_batch (prices only, the library's tuning with level_factor 8 and

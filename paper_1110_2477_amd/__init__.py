@@ -24,7 +24,8 @@ EUROPEAN, COST_AT_T0 = 1, 2
 # Function names declared in include/bt.h.
 ABI_FUNCTIONS = ("bt_autotune", "bt_book_create", "bt_book_info", "bt_book_price", "bt_book_price_grad",
                  "bt_book_resolve_overflow", "bt_book_timings", "bt_book_destroy", "bt_price", "bt_shutdown",
-                 "bt_price_batch", "bt_price_grad_batch", "bt_price_batch_static", "bt_model_constants",
+                 "bt_price_batch", "bt_price_grad_batch", "bt_price_adjoint_batch", "bt_price_batch_static",
+                 "bt_model_constants",
                  "bt_strerror",
                  "bt_version", "bt_last_hip_error")
 
@@ -83,6 +84,7 @@ def lib():
     L.bt_price_batch.argtypes = [vp, i32, i32, vp, vp, vp]
     L.bt_price_grad_batch.argtypes = [vp, i32, i32, vp, vp, vp, vp]
     L.bt_price_batch_static.argtypes = [vp, i32, i32, vp, vp]
+    L.bt_price_adjoint_batch.argtypes = [vp, i32, i32, vp, vp, vp]
     L.bt_shutdown.argtypes = []
     L.bt_model_constants.argtypes = [vp, dp, dp, dp, dp, dp]
     L.bt_strerror.argtypes = [ctypes.c_int]
@@ -91,7 +93,7 @@ def lib():
     L.bt_last_hip_error.argtypes = []
     for f in ("bt_autotune", "bt_book_create", "bt_book_info", "bt_book_price", "bt_book_price_grad", "bt_book_timings", "bt_book_resolve_overflow",
               "bt_price", "bt_shutdown", "bt_model_constants", "bt_version", "bt_last_hip_error",
-              "bt_price_batch", "bt_price_grad_batch", "bt_price_batch_static"):
+              "bt_price_batch", "bt_price_grad_batch", "bt_price_batch_static", "bt_price_adjoint_batch"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -233,6 +235,14 @@ def bt_price_grad_batch(d_params_ptr, n, max_N, d_out_ptr, d_grad_ptr, stream=No
                                      ctypes.byref(t) if t is not None else None), "bt_price_grad_batch")
 
 
+def bt_price_adjoint_batch(d_params_ptr, n, max_N, d_out_ptr, d_grad_ptr, stream=None):
+    """Prices and reverse-mode Greeks (checkpointed reverse sweep) of n
+    bt_params records in device memory."""
+    _check(lib().bt_price_adjoint_batch(ctypes.c_void_p(d_params_ptr), int(n), int(max_N),
+                                        ctypes.c_void_p(d_out_ptr), ctypes.c_void_p(d_grad_ptr),
+                                        ctypes.c_void_p(_stream_ptr(stream))), "bt_price_adjoint_batch")
+
+
 def bt_price_batch_static(d_params_ptr, n, max_N, d_out_ptr, stream=None):
     """The no-allocation variant of bt_price_batch (include/bt.h): the
     library's fixed device scratch array, at most BT_STATIC_MAX_OPTIONS
@@ -254,11 +264,12 @@ def params_tensor(params, device="cuda"):
     return torch.from_numpy(p.view(np.uint8).copy()).to(device)
 
 
-def price_batch(d_params, max_N, grad=False, stream=None, tune=None):
+def price_batch(d_params, max_N, grad=False, stream=None, tune=None, mode="forward"):
     """Prices the bt_params records of the uint8 device tensor ``d_params``
     (see params_tensor) on the GPU; returns uint8 device tensors of bt_result
-    records (and of bt_grad records with grad=True).  Asynchronous on
-    ``stream``; nothing is copied to the host."""
+    records (and of bt_grad records with grad=True: carried tangents with
+    mode="forward", the checkpointed reverse sweep with mode="adjoint").
+    Asynchronous on ``stream``; nothing is copied to the host."""
     import torch
     n = d_params.numel() // PARAMS_DTYPE.itemsize
     if d_params.dtype != torch.uint8 or not d_params.is_cuda or not d_params.is_contiguous() \
@@ -269,7 +280,12 @@ def price_batch(d_params, max_N, grad=False, stream=None, tune=None):
         bt_price_batch(d_params.data_ptr(), n, max_N, out.data_ptr(), stream, tune)
         return out
     g = torch.empty(n * GRAD_DTYPE.itemsize, dtype=torch.uint8, device=d_params.device)
-    bt_price_grad_batch(d_params.data_ptr(), n, max_N, out.data_ptr(), g.data_ptr(), stream, tune)
+    if mode == "adjoint":
+        bt_price_adjoint_batch(d_params.data_ptr(), n, max_N, out.data_ptr(), g.data_ptr(), stream)
+    elif mode == "forward":
+        bt_price_grad_batch(d_params.data_ptr(), n, max_N, out.data_ptr(), g.data_ptr(), stream, tune)
+    else:
+        raise ValueError(f"mode must be 'forward' or 'adjoint', not {mode!r}")
     return out, g
 
 

@@ -40,6 +40,7 @@
 #include "../../include/bt.h"
 #include "bt_device.hpp"
 #include "bt_wave.hpp"
+#include "bt_adjoint.hpp"
 
 using namespace bt;
 
@@ -570,6 +571,528 @@ __global__ void bt_reset_kernel(KArgs A, int64_t n_fill)
     for (int64_t k = i; k < n_fill; k += stride) A.fill[k] = 0;
     for (int64_t k = i; k < A.n_items; k += stride) A.failed[k] = 0;
     if (i == 0) *A.p0_queue = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Reverse-mode Greeks (bt_price_adjoint_batch).  One workgroup sweeps one
+// tree side at a time:
+//   forward   levels N+1 .. 1 from the leaves, keeping the levels
+//             t = N+1, N+1-s, N+1-2s, ... (s = ceil(sqrt(N+2))) as
+//             checkpoints;
+//   reverse   segment by segment from the root: the levels between a
+//             checkpoint and the next lower one are recomputed from the
+//             checkpoint, then the reverse steps t = lo .. hi-1 carry the
+//             adjoint from level t to level t+1 (bt_adjoint.hpp); finally the
+//             leaves' adjoint gives their stock prices' and the cost rate's
+//             contributions.
+// Nodes whose children hold at most SMALL_CAP points are stepped by one lane
+// each; larger ones are queued and stepped by the first lane of a wave with
+// that wave's large-node slot.  The adjoint of a child is the sum of what its
+// two parents give it; parents of even and of odd columns run in two passes,
+// so no two lanes add to one child at once and the sums have a fixed order.
+// ---------------------------------------------------------------------------
+constexpr int ADJ_SMALL_TAPE = 1024;
+
+struct AdjArgs {
+    const Model *models;
+    const int *order;       // options, longest tree first
+    const int *count;       // number of options in `order`
+    int *queue;             // [2]: next position per party
+    bt_result *out;
+    bt_grad *grad;
+    double *ws;             // per workgroup, ws_doubles each
+    int64_t ws_doubles;
+    int *wsi;               // per workgroup, wsi_ints each
+    int64_t wsi_ints;
+    int Ncap, big_pts;      // largest N; largest child points of a queued node
+    int64_t lwn;            // numbers per level slot (W0, W1, A0, A1)
+    int64_t cp_nums, sg_nums;   // numbers of the checkpoint and segment regions
+    int cp_max, sg_max;     // levels they index
+    // offsets in a workgroup's doubles
+    int64_t oStab, oSfac, oW0, oW1, oA0, oA1, oCP, oSG, oLane, oBig;
+    int64_t lane_doubles, big_doubles;
+    // offsets in a workgroup's ints: off/cnt of W0, W1, the checkpoints and
+    // the segment levels ((N+2) each), then the checkpoint table
+    int64_t iW0, iW1, iCP, iSG, iTab;
+};
+
+struct LevelRef {
+    double *rec;
+    int *off, *cnt;
+};
+
+// Scratch of one stepper (a lane's, or a wave's large-node slot).
+struct Stepper {
+    double *fwd;            // forward stages (doubles)
+    Caps fcp;
+    TN *tn;
+    RevCaps rc;
+    Tape *tape;
+    double *adj, *gd, *gu;
+};
+
+BTHD int64_t stepper_doubles(int stage_cap, int child_cap, int tape)
+{
+    const Caps f = make_caps(stage_cap, stage_cap, stage_cap, stage_cap, stage_cap);
+    const RevCaps r = rev_caps(stage_cap, child_cap, tape);
+    int64_t d = (f.total + 1) & ~(int64_t)1;
+    d += 3 * r.tn;                                  // TN: 24 bytes each
+    d += 8;                                         // Tape (48 bytes)
+    d += tape;                                      // ia, ib (ints)
+    d += 2 * (int64_t)tape;                         // pa, pb
+    d += 3 * 2 * (int64_t)child_cap + 5 + tape;     // adj
+    d += 2 * (3 * (int64_t)child_cap + 1);          // gd, gu
+    return (d + 31) & ~(int64_t)31;
+}
+
+__device__ Stepper make_stepper(double *p, int stage_cap, int child_cap, int tape)
+{
+    Stepper S;
+    S.fcp = make_caps(stage_cap, stage_cap, stage_cap, stage_cap, stage_cap);
+    S.rc = rev_caps(stage_cap, child_cap, tape);
+    S.fwd = p;
+    p += (S.fcp.total + 1) & ~(int64_t)1;
+    S.tn = (TN *)p;
+    p += 3 * S.rc.tn;
+    S.tape = (Tape *)p;
+    p += 8;
+    S.tape->ia = (int32_t *)p;
+    S.tape->ib = (int32_t *)p + tape;
+    p += tape;
+    S.tape->pa = p;
+    p += tape;
+    S.tape->pb = p;
+    p += tape;
+    S.tape->cap = tape;
+    S.adj = p;
+    p += 3 * 2 * (int64_t)child_cap + 5 + tape;
+    S.gd = p;
+    p += 3 * (int64_t)child_cap + 1;
+    S.gu = p;
+    return S;
+}
+
+__device__ __forceinline__ View<double> level_view(const LevelRef &L, int c)
+{
+    const double *r = L.rec + L.off[c];
+    return View<double>{r + 1, r + 2, r, L.cnt[c], 3};
+}
+
+// Level t (t+1 columns) from level `up` into `dst` (records from offset 0,
+// at most cap numbers).  Returns the numbers written, or -1 on overflow
+// (uniform over the workgroup).
+template <int SIDE>
+__device__ int64_t adj_fwd_level(const AdjArgs &A, const Model &md, int t, const double *Stab, const LevelRef &up,
+                                 const LevelRef &dst, int64_t cap, const Stepper &lane, const Stepper &big,
+                                 int64_t *bp_sum, int *bp_max, int64_t *sh, int *sbig, int64_t *srun, int *sflag)
+{
+    const int tid = threadIdx.x, w = tid >> 6, ln = tid & 63;
+    const int N = md.N;
+    const Inputs<double> in = inputs_of(md, 0.0);
+    const double kt = (t >= 1 || (md.flags & F_COST_AT_T0)) ? md.k : 0.0;
+    const bool ex = !((md.flags & F_EUROPEAN) && t < N);
+    const Caps sc = small_caps();
+    int64_t run = 0;
+    if (tid == 0) *sflag = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 <= t; c0 += WG) {
+        const int c = c0 + tid;
+        const bool act = c <= t;
+        int mz = 0;
+        bool bigq = false;
+        Arr<double> Z{};
+        if (act) {
+            const View<double> Zd = level_view(up, c), Zu = level_view(up, c + 1);
+            if (Zd.m + Zu.m > SMALL_CAP) {
+                bigq = true;
+            } else {
+                const double S = Stab[2 * c - t + N + 1];
+                double xi, ze;
+                payoff(md, in, S, xi, ze);
+                mz = node_update<SIDE, double>(Zu, Zd, S, kt, md.rho, xi, ze, ex, lane.fwd, 1, sc, &Z);
+                bigq = mz < 0;
+            }
+        }
+        const int64_t sz = (act && !bigq) ? 3 * (int64_t)mz + 1 : 0;
+        const int64_t LOW = ((int64_t)1 << 40) - 1;
+        int64_t tot;
+        const int64_t exs = block_scan(sz + (bigq ? ((int64_t)1 << 40) : 0), &tot, sh);
+        const int nbig = (int)(tot >> 40), bix = (int)(exs >> 40);
+        tot &= LOW;
+        const int64_t pos = run + (exs & LOW);
+        if (run + tot > cap) {
+            if (tid == 0) *sflag = 1;
+        } else if (sz) {
+            double *d = dst.rec + pos;
+            d[0] = Z.S(0);
+            for (int j = 0; j < mz; j++) {
+                d[1 + 3 * j] = Z.X(j);
+                d[2 + 3 * j] = Z.V(j);
+                d[3 + 3 * j] = Z.S(j + 1);
+            }
+            dst.off[c] = (int)pos;
+            dst.cnt[c] = mz;
+            const int bp = (mz == 1 && Z.S(0) == Z.S(1)) ? 0 : mz;
+            *bp_sum += bp;
+            *bp_max = bp > *bp_max ? bp : *bp_max;
+        }
+        if (bigq) sbig[bix] = c;
+        if (tid == 0) *srun = run + tot;
+        __syncthreads();
+        if (*sflag) return -1;
+        for (int bi = w; bi < nbig; bi += NWAVE) {
+            if (ln != 0) continue;
+            const int cc = sbig[bi];
+            const View<double> Zd = level_view(up, cc), Zu = level_view(up, cc + 1);
+            const double S = Stab[2 * cc - t + N + 1];
+            double xi, ze;
+            payoff(md, in, S, xi, ze);
+            Arr<double> Zb;
+            const int mb = (Zd.m + Zu.m <= A.big_pts)
+                               ? node_update<SIDE, double>(Zu, Zd, S, kt, md.rho, xi, ze, ex, big.fwd, 1, big.fcp, &Zb)
+                               : -1;
+            if (mb < 0) { *sflag = 1; continue; }
+            const int64_t rec = 3 * (int64_t)mb + 1;
+            const int64_t p = (int64_t)atomicAdd((unsigned long long *)srun, (unsigned long long)rec);
+            if (p + rec > cap) { *sflag = 1; continue; }
+            double *d = dst.rec + p;
+            d[0] = Zb.S(0);
+            for (int j = 0; j < mb; j++) {
+                d[1 + 3 * j] = Zb.X(j);
+                d[2 + 3 * j] = Zb.V(j);
+                d[3 + 3 * j] = Zb.S(j + 1);
+            }
+            dst.off[cc] = (int)p;
+            dst.cnt[cc] = mb;
+            const int bp = (mb == 1 && Zb.S(0) == Zb.S(1)) ? 0 : mb;
+            *bp_sum += bp;
+            *bp_max = bp > *bp_max ? bp : *bp_max;
+        }
+        __syncthreads();
+        run = *srun;
+        if (*sflag) return -1;
+        __syncthreads();
+    }
+    return run;
+}
+
+// Greeks accumulators of one lane.
+struct GAcc {
+    double S0, sig, R, k;
+};
+
+// One reverse step of node (t, c): adds its children's adjoints into Anxt
+// and its parameters' into g.  false when a capacity was too small.
+template <int SIDE>
+__device__ bool adj_node(const AdjArgs &A, const Model &md, int t, int c, const double *Stab, const double *Sfac,
+                         const LevelRef &Lt, const LevelRef &Lc, const double *Acur, double *Anxt, const Stepper &st,
+                         GAcc &g, double *price)
+{
+    const int N = md.N;
+    const bool t0cost = (md.flags & F_COST_AT_T0) != 0;
+    const double kt = (t >= 1 || t0cost) ? md.k : 0.0;
+    const bool ex = !((md.flags & F_EUROPEAN) && t < N);
+    const View<double> Zd = level_view(Lc, c), Zu = level_view(Lc, c + 1);
+    const double S = Stab[2 * c - t + N + 1];
+    const double *zbar = t >= 1 ? Acur + Lt.off[c] : nullptr;
+    const int mz = t >= 1 ? Lt.cnt[c] : 0;
+    double gp[3];
+    if (node_reverse<SIDE>(md, Zd, Zu, S, kt, md.rho, ex, zbar, mz, st.rc, st.tn, *st.tape, st.adj, st.gd, st.gu, gp,
+                           price))
+        return false;
+    double *ad = Anxt + Lc.off[c], *au = Anxt + Lc.off[c + 1];
+    for (int q = 0; q < 3 * Zd.m + 1; q++) ad[q] += st.gd[q];
+    for (int q = 0; q < 3 * Zu.m + 1; q++) au[q] += st.gu[q];
+    const int j = 2 * c - t;
+    g.S0 += gp[0] * Sfac[j + N + 1];
+    g.sig += gp[0] * (S * (double)j * md.sq);
+    g.R += gp[2] * (-md.dt * md.rho);
+    if (t >= 1 || t0cost) g.k += gp[1];
+    return true;
+}
+
+// Reverse step of level t: Acur (adjoint of level t, layout Lt; unused at
+// t = 0) to Anxt (adjoint of level t+1, layout Lc, `nn` numbers).  false
+// when a node did not fit (uniform over the workgroup).
+template <int SIDE>
+__device__ bool adj_rev_level(const AdjArgs &A, const Model &md, int t, const double *Stab, const double *Sfac,
+                              const LevelRef &Lt, const LevelRef &Lc, int64_t nn, const double *Acur, double *Anxt,
+                              const Stepper &lane, const Stepper &big, GAcc &g, double *price, int64_t *sh, int *sbig,
+                              int *sflag)
+{
+    const int tid = threadIdx.x, w = tid >> 6, ln = tid & 63;
+    for (int64_t q = tid; q < nn; q += WG) Anxt[q] = 0.0;
+    if (tid == 0) *sflag = 0;
+    __syncthreads();
+    for (int par = 0; par < 2; par++) {
+        for (int c0 = par; c0 <= t; c0 += 2 * WG) {
+            const int c = c0 + 2 * tid;
+            bool bigq = false;
+            if (c <= t) {
+                const int M = Lc.cnt[c] + Lc.cnt[c + 1];
+                bigq = M > SMALL_CAP || !adj_node<SIDE>(A, md, t, c, Stab, Sfac, Lt, Lc, Acur, Anxt, lane, g, price);
+            }
+            int64_t tot;
+            const int64_t bix = block_scan(bigq ? 1 : 0, &tot, sh);
+            if (bigq) sbig[bix] = c;
+            __syncthreads();
+            for (int bi = w; bi < (int)tot; bi += NWAVE) {
+                if (ln != 0) continue;
+                const int cc = sbig[bi];
+                const bool ok = Lc.cnt[cc] + Lc.cnt[cc + 1] <= A.big_pts &&
+                                adj_node<SIDE>(A, md, t, cc, Stab, Sfac, Lt, Lc, Acur, Anxt, big, g, price);
+                if (!ok) *sflag = 1;
+            }
+            __syncthreads();
+            if (*sflag) return false;
+        }
+    }
+    return true;
+}
+
+// Integer ceil(sqrt(x)) for x >= 1.
+BTHD int isqrt_ceil(int x)
+{
+    int s = 1;
+    while ((int64_t)s * s < x) s++;
+    return s;
+}
+
+// Copies a level (records, offsets, counts of `ncol` columns, `nn` numbers)
+// to dst.
+__device__ void copy_level(const LevelRef &src, const LevelRef &dst, int ncol, int64_t nn)
+{
+    for (int64_t q = threadIdx.x; q < nn; q += WG) dst.rec[q] = src.rec[q];
+    for (int c = threadIdx.x; c < ncol; c += WG) {
+        dst.off[c] = src.off[c];
+        dst.cnt[c] = src.cnt[c];
+    }
+    __syncthreads();
+}
+
+template <int SIDE>
+__device__ void adjoint_tree(const AdjArgs &A, int opt, int64_t *sh, int *sbig, int64_t *srun, int *sflag)
+{
+    const int tid = threadIdx.x, w = tid >> 6;
+    const Model md = A.models[opt];
+    const int N = md.N;
+    double *ws = A.ws + (int64_t)blockIdx.x * A.ws_doubles;
+    int *wsi = A.wsi + (int64_t)blockIdx.x * A.wsi_ints;
+    double *Stab = ws + A.oStab, *Sfac = ws + A.oSfac;
+    const Inputs<double> in = inputs_of(md, 0.0);
+    for (int idx = tid; idx < 2 * N + 3; idx += WG) {
+        const int j = idx - (N + 1);
+        Sfac[idx] = j >= 0 ? upow(md.u, j) : upow(md.d, -j);
+        Stab[idx] = stock_at(in, j);
+    }
+    __syncthreads();
+    const int64_t NN = N + 2;
+    LevelRef W[2] = {{ws + A.oW0, wsi + A.iW0, wsi + A.iW0 + NN}, {ws + A.oW1, wsi + A.iW1, wsi + A.iW1 + NN}};
+    double *Abuf[2] = {ws + A.oA0, ws + A.oA1};
+    // checkpoint table: per checkpoint, its record offset in the region;
+    // then per segment level, its record offset
+    int64_t *cp_base = (int64_t *)(wsi + A.iTab);
+    int64_t *sg_base = cp_base + A.cp_max + 1;
+    const Stepper lane = make_stepper(ws + A.oLane + (int64_t)tid * A.lane_doubles, SMALL_CAP, SMALL_CAP, ADJ_SMALL_TAPE);
+    const Stepper big = make_stepper(ws + A.oBig + (int64_t)w * A.big_doubles, 2 * A.big_pts + 16, A.big_pts,
+                                     40 * A.big_pts + 4096);
+    const int s = isqrt_ceil(N + 2);
+    const int ncp = N / s + 1;   // checkpoints t = N+1 - j s >= 1, j = 0 .. ncp-1
+    const auto cp_level = [&](int j) {
+        return LevelRef{ws + A.oCP + cp_base[j], wsi + A.iCP + 2 * NN * j, wsi + A.iCP + 2 * NN * j + NN};
+    };
+    bool fail = ncp > A.cp_max || s - 1 > A.sg_max || N > A.Ncap;
+    int64_t bp_sum = 0;
+    int bp_max = 0;
+    // forward: leaves into W[(N+1) & 1] and checkpoint 0
+    if (!fail) {
+        const LevelRef L = W[(N + 1) & 1];
+        for (int c = tid; c <= N + 1; c += WG) {
+            const double S = Stab[2 * c];
+            double *r = L.rec + 4 * (int64_t)c;
+            r[0] = -((1.0 + md.k) * S); r[1] = 0.0; r[2] = 0.0; r[3] = -((1.0 - md.k) * S);
+            L.off[c] = 4 * c;
+            L.cnt[c] = 1;
+        }
+        if (tid == 0) cp_base[0] = 0;
+        __syncthreads();
+        copy_level(L, cp_level(0), N + 2, 4 * NN);
+        if (tid == 0) cp_base[1] = 4 * NN;
+        __syncthreads();
+    }
+    for (int t = N; t >= 1 && !fail; t--) {
+        const int64_t nn = adj_fwd_level<SIDE>(A, md, t, Stab, W[(t + 1) & 1], W[t & 1], A.lwn, lane, big, &bp_sum,
+                                               &bp_max, sh, sbig, srun, sflag);
+        if (nn < 0) { fail = true; break; }
+        if ((N + 1 - t) % s == 0) {
+            const int j = (N + 1 - t) / s;
+            if (cp_base[j] + nn > A.cp_nums) { fail = true; break; }
+            copy_level(W[t & 1], cp_level(j), t + 1, nn);
+            if (tid == 0 && j + 1 < A.cp_max + 1) cp_base[j + 1] = cp_base[j] + nn;
+            __syncthreads();
+        }
+    }
+    // reverse, root side first
+    GAcc g{0.0, 0.0, 0.0, 0.0};
+    double price = 0.0;
+    int cur = 0;
+    int lo = 0;
+    for (int jj = ncp - 1; jj >= 0 && !fail; jj--) {
+        const int hi = N + 1 - jj * s;
+        // levels lo+1 .. hi-1 recomputed from checkpoint jj into the segment
+        // region: level t at slot hi-1-t
+        int64_t seg_used = 0;
+        const auto seg_level = [&](int t, int64_t base) {
+            const int slot = hi - 1 - t;
+            return LevelRef{ws + A.oSG + base, wsi + A.iSG + 2 * NN * slot, wsi + A.iSG + 2 * NN * slot + NN};
+        };
+        LevelRef up = cp_level(jj);
+        for (int t = hi - 1; t >= lo + 1; t--) {
+            const LevelRef dst = seg_level(t, seg_used);
+            int64_t dsum = 0;
+            int dmax = 0;
+            const int64_t nn = adj_fwd_level<SIDE>(A, md, t, Stab, up, dst, A.sg_nums - seg_used, lane, big, &dsum,
+                                                   &dmax, sh, sbig, srun, sflag);
+            if (nn < 0) { fail = true; break; }
+            if (tid == 0) sg_base[hi - 1 - t] = seg_used;
+            seg_used += nn;
+            up = dst;
+        }
+        __syncthreads();
+        if (fail) break;
+        const auto level_at = [&](int t) {
+            if (t == hi) return cp_level(jj);
+            if (t == lo) return cp_level(jj + 1);
+            const int slot = hi - 1 - t;
+            return seg_level(t, sg_base[slot]);
+        };
+        for (int t = lo; t <= hi - 1; t++) {
+            const LevelRef Lc = level_at(t + 1);
+            const LevelRef Lt = t >= 1 ? level_at(t) : Lc;
+            // numbers of level t+1: the last column's record ends the level
+            // only when records are in column order, so sum the sizes
+            int64_t nn = 0;
+            for (int c = tid; c <= t + 1; c += WG) {
+                const int64_t e = Lc.off[c] + 3 * (int64_t)Lc.cnt[c] + 1;
+                nn = e > nn ? e : nn;
+            }
+            int64_t tmp;
+            {
+                // maximum over the workgroup
+                for (int o = 32; o > 0; o >>= 1) {
+                    const int64_t y = __shfl_down(nn, o, 64);
+                    nn = y > nn ? y : nn;
+                }
+                if ((tid & 63) == 0) sh[tid >> 6] = nn;
+                __syncthreads();
+                tmp = 0;
+                for (int q = 0; q < NWAVE; q++) tmp = sh[q] > tmp ? sh[q] : tmp;
+                __syncthreads();
+            }
+            nn = tmp;
+            if (nn > A.lwn) { fail = true; break; }
+            double *Anxt = Abuf[cur ^ 1];
+            if (!adj_rev_level<SIDE>(A, md, t, Stab, Sfac, Lt, Lc, nn, Abuf[cur], Anxt, lane, big, g, &price, sh, sbig,
+                                     sflag)) {
+                fail = true;
+                break;
+            }
+            if (t == 0 && tid == 0) {
+                // breakpoints of z_0 (the forward pass stopped at level 1)
+                const View<double> Zd = level_view(Lc, 0), Zu = level_view(Lc, 1);
+                const double S0 = Stab[N + 1];
+                double xi, ze;
+                payoff(md, in, S0, xi, ze);
+                Arr<double> Z;
+                const double kt0 = (md.flags & F_COST_AT_T0) ? md.k : 0.0;
+                const bool ex0 = !((md.flags & F_EUROPEAN) && N > 0);
+                const int m0 = node_update<SIDE, double>(Zu, Zd, S0, kt0, md.rho, xi, ze, ex0, big.fwd, 1, big.fcp, &Z);
+                if (m0 < 0) *sflag = 1;
+                else {
+                    const int bp = (m0 == 1 && Z.S(0) == Z.S(1)) ? 0 : m0;
+                    bp_sum += bp;
+                    bp_max = bp > bp_max ? bp : bp_max;
+                }
+            }
+            __syncthreads();
+            if (*sflag) { fail = true; break; }
+            cur ^= 1;
+        }
+        lo = hi;
+    }
+    if (!fail) {
+        // the leaves: [-(1+k) S, 0, 0, -(1-k) S] per column
+        const double *Al = Abuf[cur];
+        for (int c = tid; c <= N + 1; c += WG) {
+            const double S = Stab[2 * c];
+            const double a0 = Al[4 * (int64_t)c], a1 = Al[4 * (int64_t)c + 3];
+            const double gS = -(1.0 + md.k) * a0 - (1.0 - md.k) * a1;
+            const int j = 2 * c - (N + 1);
+            g.S0 += gS * Sfac[j + N + 1];
+            g.sig += gS * (S * (double)j * md.sq);
+            g.k += -S * a0 + S * a1;
+        }
+    }
+    // workgroup sums in a fixed order
+    __shared__ double s_g[NWAVE][4];
+    __shared__ int64_t s_bp[NWAVE];
+    __shared__ int s_bm[NWAVE];
+    double v[4] = {g.S0, g.sig, g.R, g.k};
+    int64_t bs = bp_sum;
+    int bm = bp_max;
+    for (int o = 32; o > 0; o >>= 1) {
+        for (int q = 0; q < 4; q++) v[q] += __shfl_down(v[q], o, 64);
+        bs += __shfl_down(bs, o, 64);
+        const int y = __shfl_down(bm, o, 64);
+        bm = y > bm ? y : bm;
+    }
+    __syncthreads();
+    if ((tid & 63) == 0) {
+        for (int q = 0; q < 4; q++) s_g[tid >> 6][q] = v[q];
+        s_bp[tid >> 6] = bs;
+        s_bm[tid >> 6] = bm;
+    }
+    __syncthreads();
+    // the root step (column 0) ran on thread 0, as a small node or as wave
+    // 0's large node: the price is in its register
+    if (tid == 0) {
+        double tg[4] = {0, 0, 0, 0};
+        int64_t tb = 0;
+        int tm = 0;
+        for (int q = 0; q < NWAVE; q++) {
+            for (int r = 0; r < 4; r++) tg[r] += s_g[q][r];
+            tb += s_bp[q];
+            tm = s_bm[q] > tm ? s_bm[q] : tm;
+        }
+        bt_result &o = A.out[opt];
+        bt_grad4 &gg = SIDE == 0 ? A.grad[opt].ask : A.grad[opt].bid;
+        if (fail) {
+            atomicMin(&o.status, BT_EOVERFLOW);
+        } else {
+            if (SIDE == 0) { o.ask = price; o.bp_total_ask = tb; o.bp_max_ask = tm; }
+            else { o.bid = -price; o.bp_total_bid = tb; o.bp_max_bid = tm; }
+            gg.dS0 = tg[0]; gg.dsigma = tg[1]; gg.dR = tg[2]; gg.dk = tg[3];
+        }
+    }
+    __syncthreads();
+}
+
+template <int SIDE>
+__global__ __launch_bounds__(WG) void bt_adjoint_kernel(AdjArgs A)
+{
+    __shared__ int64_t sh[NWAVE];
+    __shared__ int sbig[WG];
+    __shared__ int64_t srun;
+    __shared__ int sflag;
+    __shared__ int s_q;
+    for (;;) {
+        if (threadIdx.x == 0) s_q = atomicAdd(A.queue + SIDE, 1);
+        __syncthreads();
+        const int q = s_q;
+        __syncthreads();
+        if (q >= *A.count) break;
+        adjoint_tree<SIDE>(A, A.order[q], sh, sbig, &srun, &sflag);
+    }
 }
 
 // Options whose pricing failed (status other than BT_OK: invalid, or a
@@ -1560,6 +2083,208 @@ int static_workspace(bt_book **out)
     return BT_OK;
 }
 
+// Workspace of the reverse-mode Greeks: the per-workgroup buffers of
+// adjoint_tree, for tree sides of up to cap_N steps, on as many workgroups
+// as fit a budget of device memory (at most one per compute unit).
+struct AdjWs {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int cap_n = 0, cap_N = 0, grid = 0, grid_p0 = 0;
+    double *d_ws = nullptr;
+    int *d_wsi = nullptr;
+    // the device planner's constants and order, and the zero-cost kernel's
+    // buffers, for cap_n options
+    Model *d_models = nullptr;
+    int2 *d_keys = nullptr;
+    int *d_order = nullptr;
+    int *d_ints = nullptr;          // valid count, queues, zero-cost queue
+    unsigned long long *d_ctr = nullptr;
+    double *d_wsp = nullptr;
+    AdjArgs args{};
+    KArgs k{};
+    PlanArgs plan{};
+};
+std::vector<AdjWs *> g_adj;
+
+void adj_free(AdjWs *w)
+{
+    if (!w) return;
+    void *ptrs[] = {w->d_ws, w->d_wsi, w->d_models, w->d_keys, w->d_order, w->d_ints, w->d_ctr, w->d_wsp};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    delete w;
+}
+
+int adj_build(AdjWs *w, int cap_n, int cap_N)
+{
+    AdjArgs a{};
+    const int64_t NN = cap_N + 2;
+    const int B = 4 * cap_N + 64;
+    const int s = isqrt_ceil(cap_N + 2);
+    a.Ncap = cap_N;
+    a.big_pts = B;
+    // a level slot holds 32 points per node on average (a book's default
+    // level factor) plus three large nodes
+    a.lwn = round_up((3 * DEFAULT_LEVEL_FACTOR + 1) * NN + 6 * (int64_t)B, 32);
+    a.cp_max = s + 2;
+    a.sg_max = s;
+    a.cp_nums = round_up((int64_t)a.cp_max * a.lwn / 2, 32);
+    a.sg_nums = round_up((int64_t)a.sg_max * a.lwn / 2, 32);
+    a.lane_doubles = stepper_doubles(SMALL_CAP, SMALL_CAP, ADJ_SMALL_TAPE);
+    a.big_doubles = stepper_doubles(2 * B + 16, B, 40 * B + 4096);
+    a.oStab = 0;
+    a.oSfac = round_up(2 * NN, 32);
+    a.oW0 = a.oSfac + round_up(2 * NN, 32);
+    a.oW1 = a.oW0 + a.lwn;
+    a.oA0 = a.oW1 + a.lwn;
+    a.oA1 = a.oA0 + a.lwn;
+    a.oCP = a.oA1 + a.lwn;
+    a.oSG = a.oCP + a.cp_nums;
+    a.oLane = a.oSG + a.sg_nums;
+    a.oBig = a.oLane + (int64_t)WG * a.lane_doubles;
+    a.ws_doubles = a.oBig + NWAVE * a.big_doubles;
+    a.iW0 = 0;
+    a.iW1 = 2 * NN;
+    a.iCP = 4 * NN;
+    a.iSG = a.iCP + 2 * NN * a.cp_max;
+    a.iTab = round_up(a.iSG + 2 * NN * a.sg_max, 2);
+    a.wsi_ints = round_up(a.iTab + 2 * (int64_t)(a.cp_max + 1 + a.sg_max), 64);
+    if (a.lwn > INT32_MAX || a.cp_nums > INT32_MAX || a.sg_nums > INT32_MAX || 40 * (int64_t)B + 4096 > INT32_MAX)
+        return BT_EINVAL;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        (void)hipGetLastError();
+        free_b = (size_t)1 << 34;
+    }
+    const double per_wg = (double)a.ws_doubles * 8 + (double)a.wsi_ints * 4;
+    const double budget = std::min((double)free_b / 3.0, 48.0 * (1 << 30));
+    const int grid = (int)std::max(1.0, std::min((double)prop.multiProcessorCount, budget / per_wg));
+    const int grid_p0 = std::max(1, std::min(cap_n, prop.multiProcessorCount));
+    KArgs k{};
+    k.p0_stab = round_up(2 * NN - 1, 32);
+    k.p0_doubles = k.p0_stab + round_up(2 * NN - 2, 32);
+    int rc = BT_OK;
+    if ((rc = dalloc(&w->d_ws, (size_t)a.ws_doubles * grid)) || (rc = dalloc(&w->d_wsi, (size_t)a.wsi_ints * grid)) ||
+        (rc = dalloc(&w->d_models, cap_n)) || (rc = dalloc(&w->d_keys, cap_n)) ||
+        (rc = dalloc(&w->d_order, 3 * (size_t)cap_n)) || (rc = dalloc(&w->d_ints, 72)) ||
+        (rc = dalloc(&w->d_ctr, 2)) || (rc = dalloc(&w->d_wsp, (size_t)k.p0_doubles * grid_p0)))
+        return rc;
+    a.ws = w->d_ws;
+    a.wsi = w->d_wsi;
+    a.models = w->d_models;
+    a.count = w->d_ints;
+    a.queue = w->d_ints + 2;          // zeroed by the reset kernel (its band counters)
+    k.models = w->d_models;
+    k.band_ctr = w->d_ints + 2;
+    k.nbands_max = 1;
+    k.arena_ctr = w->d_ctr;
+    k.p0_queue = w->d_ints + 8;
+    k.p0_count = w->d_ints;
+    k.wsp = w->d_wsp;
+    PlanArgs P{};
+    P.models = w->d_models;
+    P.keys = w->d_keys;
+    P.order = w->d_order;
+    P.count = w->d_ints;
+    w->args = a;
+    w->k = k;
+    w->plan = P;
+    w->cap_n = cap_n;
+    w->cap_N = cap_N;
+    w->grid = grid;
+    w->grid_p0 = grid_p0;
+    w->device = dev;
+    return BT_OK;
+}
+
+int adjoint_workspace(hipStream_t stream, int n, int max_N, AdjWs **out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    AdjWs *e = nullptr;
+    size_t ei = 0;
+    for (size_t i = 0; i < g_adj.size(); i++)
+        if (g_adj[i]->device == dev && g_adj[i]->stream == stream) { e = g_adj[i]; ei = i; }
+    if (e && e->cap_N >= max_N && e->cap_n >= n) {
+        *out = e;
+        return BT_OK;
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIPCHK(hipStreamIsCapturing(stream, &cs));
+    if (cs != hipStreamCaptureStatusNone) return BT_ENOSUPP;
+    int cap_n = n, cap_N = max_N;
+    if (e) {
+        cap_n = std::max(cap_n, e->cap_n);
+        cap_N = std::max(cap_N, e->cap_N);
+        HIPCHK(hipDeviceSynchronize());
+        adj_free(e);
+        g_adj.erase(g_adj.begin() + ei);
+    }
+    AdjWs *w = new (std::nothrow) AdjWs();
+    if (!w) return BT_ENOMEM;
+    const int rc = adj_build(w, cap_n, cap_N);
+    if (rc != BT_OK) {
+        adj_free(w);
+        return rc;
+    }
+    w->stream = stream;
+    g_adj.push_back(w);
+    *out = w;
+    return BT_OK;
+}
+
+// Prices, counts and reverse-mode Greeks of a device-resident batch: the
+// device planner's constants and order, the zero-cost kernel, then the
+// buyer's and the seller's reverse sweeps, all on the caller's stream.
+int price_adjoint(const bt_params *d_params, int32_t n, int32_t max_N, bt_result *d_out, bt_grad *d_grad,
+                  void *stream)
+{
+    if (n < 0 || max_N < 1 || max_N > BT_MAX_N || (n > 0 && (!d_params || !d_out || !d_grad))) return BT_EINVAL;
+    if (n == 0) return BT_OK;
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    hipStream_t s = (hipStream_t)stream;
+    AdjWs *aw = nullptr;
+    int rc = adjoint_workspace(s, n, max_N, &aw);
+    if (rc != BT_OK) return rc;
+    PlanArgs P = aw->plan;
+    P.params = d_params;
+    P.n = n;
+    P.max_N = max_N;
+    KArgs a = aw->k;
+    a.out = d_out;
+    a.grad = d_grad;
+    a.n_opts = n;
+    a.n_items = 0;
+    a.p0_sched = aw->d_order + 2 * (int64_t)n;
+    const int g1 = (n + WG - 1) / WG;
+    hipLaunchKernelGGL(bt_derive_kernel, dim3(g1), dim3(WG), 0, s, P);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(bt_rank_kernel, dim3(g1), dim3(WG), 0, s, P);
+    HIPCHK(hipGetLastError());
+    const int rb = (int)std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(bt_reset_kernel, dim3(rb), dim3(256), 0, s, a, (int64_t)0);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(bt_price0_kernel, dim3(std::min(aw->grid_p0, n)), dim3(WG), 0, s, a);
+    HIPCHK(hipGetLastError());
+    AdjArgs A = aw->args;
+    A.out = d_out;
+    A.grad = d_grad;
+    const int gb = std::min(aw->grid, n);
+    A.order = aw->d_order;   // the buyer's order: costly tree sides first
+    hipLaunchKernelGGL(bt_adjoint_kernel<1>, dim3(gb), dim3(WG), 0, s, A);
+    HIPCHK(hipGetLastError());
+    A.order = aw->d_order + n;
+    hipLaunchKernelGGL(bt_adjoint_kernel<0>, dim3(gb), dim3(WG), 0, s, A);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(bt_finalize_kernel, dim3((int)std::min<int64_t>((n + 255) / 256, 1024)), dim3(256), 0, s, a);
+    HIPCHK(hipGetLastError());
+    return BT_OK;
+}
+
 int price_batch(const bt_params *d_params, int32_t n, int32_t max_N, bt_result *d_out, bt_grad *d_grad, void *stream,
                 const bt_tune *tune)
 {
@@ -1607,6 +2332,12 @@ int bt_price_batch_static(const bt_params *d_params, int32_t n, int32_t max_N, b
     const int rc = static_workspace(&ws);
     if (rc != BT_OK) return rc;
     return launch_all<double>(ws, d_out, nullptr, stream, d_params, n, max_N);
+}
+
+int bt_price_adjoint_batch(const bt_params *d_params, int32_t n, int32_t max_N, bt_result *d_out, bt_grad *d_grad,
+                           void *stream)
+{
+    return price_adjoint(d_params, n, max_N, d_out, d_grad, stream);
 }
 
 int bt_price_grad_batch(const bt_params *d_params, int32_t n, int32_t max_N, bt_result *d_out, bt_grad *d_grad,
@@ -1861,6 +2592,13 @@ int bt_shutdown(void)
             if (hipSetDevice(w.device) == hipSuccess) bt_book_destroy(w.ws);
         }
         g_ws.clear();
+        for (AdjWs *w : g_adj) {
+            if (hipSetDevice(w->device) == hipSuccess) {
+                (void)hipDeviceSynchronize();
+                adj_free(w);
+            }
+        }
+        g_adj.clear();
         if (have_dev) (void)hipSetDevice(cur);
     }
     if (t_price_book) {

@@ -76,7 +76,7 @@ def _step(p, key, h_rel):
     return h_rel * abs(p[key]) if key == "S0" else h_rel
 
 
-def _fd_check(book, idx, h_rels=(1e-5, 1e-6, 1e-7, 1e-8)):
+def _fd_check(book, idx, h_rels=(1e-5, 1e-6, 1e-7, 1e-8), greeks=None):
     """Finite differences of GPU prices against the Greeks of the same GPU.
 
     A binomial price is piecewise smooth in every parameter (a node switching
@@ -87,9 +87,10 @@ def _fd_check(book, idx, h_rels=(1e-5, 1e-6, 1e-7, 1e-8)):
     with the derivative; a bracket whose forward and backward one-sided
     differences disagree holds a kink and moves on to a smaller h; at the
     smallest h a kinked bracket passes if the derivative equals one of the
-    one-sided slopes (the branch active at theta).  Returns (passed,
-    kink_passed, failed)."""
-    base_res, base_g = bt.price_book_grad(book[idx])
+    one-sided slopes (the branch active at theta).  ``greeks`` (default:
+    a Greeks book) maps a parameter array to its (results, Greeks).  Returns
+    (passed, kink_passed, failed)."""
+    base_res, base_g = (greeks or bt.price_book_grad)(book[idx])
     todo = [(j, n, side) for j in range(len(idx)) for n in range(len(KEYS)) for side in ("ask", "bid")]
     passed = kinked = failed = 0
     for level, h_rel in enumerate(h_rels):
