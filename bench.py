@@ -467,6 +467,35 @@ def main():
         torch.cuda.synchronize()
         dt_p = time.perf_counter() - t0
         bt.bt_shutdown()
+        # the same Greeks by the checkpointed reverse sweep
+        # (bt_price_adjoint_batch) on the first 64 options, against forward
+        # mode on the same options; device memory of each workspace from
+        # the free-memory difference around its first call
+        sub = bt.params_tensor(gb[:64])
+        fa = {}
+        for mode in ("forward", "adjoint"):
+            torch.cuda.synchronize()
+            free0, _ = torch.cuda.mem_get_info()
+            bt.price_batch(sub, max_N=1500, grad=True, mode=mode)
+            torch.cuda.synchronize()
+            free1, _ = torch.cuda.mem_get_info()
+            t0 = time.perf_counter()
+            o_, g_ = bt.price_batch(sub, max_N=1500, grad=True, mode=mode)
+            torch.cuda.synchronize()
+            fa[mode] = dict(ms=(time.perf_counter() - t0) * 1e3, workspace_gib=(free0 - free1) / 2 ** 30,
+                            grads=bt.as_grads(g_), ok=bool(np.all(bt.as_results(o_)["status"] == 0)))
+            bt.bt_shutdown()
+        ga, gf = fa["adjoint"]["grads"], fa["forward"]["grads"]
+        diff = max(float(np.max(np.abs(ga[k] - gf[k]) / np.maximum(1.0, np.abs(gf[k])))) for k in ga.dtype.names)
+        extra["greeks_adjoint_vs_forward_64"] = dict(
+            sample="options 0..63 of the Greeks book (N 500..1500)", max_rel_diff=diff,
+            adjoint=dict(options_per_s=64 / (fa["adjoint"]["ms"] * 1e-3), ms=fa["adjoint"]["ms"],
+                         workspace_gib=fa["adjoint"]["workspace_gib"], ok=fa["adjoint"]["ok"],
+                         entry="bt_price_adjoint_batch (reverse sweep, sqrt(N) checkpoints)"),
+            forward=dict(options_per_s=64 / (fa["forward"]["ms"] * 1e-3), ms=fa["forward"]["ms"],
+                         workspace_gib=fa["forward"]["workspace_gib"], ok=fa["forward"]["ok"],
+                         entry="bt_price_grad_batch (tangents carried forward)"))
+        log(f"adjoint vs forward: {extra['greeks_adjoint_vs_forward_64']}")
         extra["batched_greeks_1024"] = dict(options_per_s=len(gb) / dt_g, ms=dt_g * 1e3,
                                             price_only_ms=dt_p * 1e3, greeks_over_price=dt_g / dt_p,
                                             ok=ok, entry="autograd Function over bt_price_grad_batch "

@@ -24,17 +24,32 @@ namespace bt {
 // dr/da, dr/db); r gets the id base + e.  Ids below base name the node's
 // inputs (its children's record numbers, then S, k_t, rho); -1 is a
 // constant.  ovf is set when an entry did not fit (the step then fails).
-struct Tape {
-    int32_t *ia, *ib;
-    double *pa, *pb;
-    int32_t n, cap, base, ovf;
+// The entries live in global memory; each lane's header (count, capacity,
+// base, entries) lives in LDS on the GPU, so that recording an operation
+// costs no round trip to memory for the count.
+struct TapeEnt {
+    int32_t ia, ib;
+    double pa, pb;
 };
 
+struct TapeHdr {
+    int32_t n, cap, base, ovf;
+    TapeEnt *ent;
+};
+
+constexpr int TAPE_SLOTS = 256;   // one per lane of a workgroup
+#ifdef BT_HOST_DEBUG
+inline TapeHdr bt_tape[TAPE_SLOTS];
+#else
+__shared__ TapeHdr bt_tape[TAPE_SLOTS];
+#endif
+
+// A number that records the operations that made it on the tape of slot
+// `lane` (-1: a constant).
 struct TN {
     double v;
     int32_t id;
-    int32_t pad;
-    Tape *tp;
+    int32_t lane;
 };
 
 BTD double val(const TN &x) { return x.v; }
@@ -43,8 +58,7 @@ template <> BTD TN mk<TN>(double x)
     TN r;
     r.v = x;
     r.id = -1;
-    r.pad = 0;
-    r.tp = nullptr;
+    r.lane = -1;
     return r;
 }
 
@@ -53,19 +67,21 @@ BTD TN tn_rec(double v, const TN &a, double pa, const TN &b, double pb)
     TN r;
     r.v = v;
     r.id = -1;
-    r.pad = 0;
-    r.tp = a.tp ? a.tp : b.tp;
-    if (!r.tp || (a.id < 0 && b.id < 0)) return r;
-    Tape &t = *r.tp;
-    if (t.n >= t.cap) {
+    r.lane = a.lane >= 0 ? a.lane : b.lane;
+    if (r.lane < 0 || (a.id < 0 && b.id < 0)) return r;
+    TapeHdr &t = bt_tape[r.lane];
+    const int e = t.n;
+    if (e >= t.cap) {
         t.ovf = 1;
         return r;
     }
-    const int e = t.n++;
-    t.ia[e] = a.id;
-    t.ib[e] = b.id;
-    t.pa[e] = pa;
-    t.pb[e] = pb;
+    t.n = e + 1;
+    TapeEnt q;
+    q.ia = a.id;
+    q.ib = b.id;
+    q.pa = pa;
+    q.pb = pb;
+    t.ent[e] = q;
     r.id = t.base + e;
     return r;
 }
@@ -104,7 +120,8 @@ BTHD RevCaps rev_caps(int cap, int child_cap, int tape)
 //            nullptr at the root (seed d price / d z_0(0));
 //   mz       the point count of z_t(c) in the forward pass (nullptr zbar:
 //            ignored);
-//   tn       TN scratch of rc.tn numbers; tp a tape with rc.tape entries;
+//   tn       TN scratch of rc.tn numbers; ent room for rc.tape tape
+//            entries, recorded through tape slot `slot`;
 //   adj      scratch of 3 (mu + md) + 5 + rc.tape doubles;
 //   gd, gu   out: the adjoints of the children's record numbers
 //            (3 md + 1 and 3 mu + 1 of them);
@@ -114,8 +131,8 @@ BTHD RevCaps rev_caps(int cap, int child_cap, int tape)
 // recomputed record does not have mz points).
 template <int SIDE>
 BTD int node_reverse(const Model &md, const View<double> &Zd, const View<double> &Zu, double S, double kt,
-                     double rho, bool exercise, const double *zbar, int mz, const RevCaps &rc, TN *tn, Tape &tp,
-                     double *adj, double *gd, double *gu, double *g, double *price)
+                     double rho, bool exercise, const double *zbar, int mz, const RevCaps &rc, TN *tn, int slot,
+                     TapeEnt *ent, double *adj, double *gd, double *gu, double *g, double *price)
 {
     const int nd = 3 * Zd.m + 1, nu = 3 * Zu.m + 1;
     if (nd + nu > rc.tn - rc.cp.total) return -1;
@@ -126,21 +143,24 @@ BTD int node_reverse(const Model &md, const View<double> &Zd, const View<double>
     for (int k = 0; k < nd; k++) {
         const double x = k == 0 ? Zd.S(0) : ((k - 1) % 3 == 0 ? Zd.X((k - 1) / 3)
                                                              : ((k - 1) % 3 == 1 ? Zd.V((k - 1) / 3) : Zd.S((k - 1) / 3 + 1)));
-        cd[k].v = x; cd[k].id = k; cd[k].pad = 0; cd[k].tp = &tp;
+        cd[k].v = x; cd[k].id = k; cd[k].lane = slot;
     }
     for (int k = 0; k < nu; k++) {
         const double x = k == 0 ? Zu.S(0) : ((k - 1) % 3 == 0 ? Zu.X((k - 1) / 3)
                                                              : ((k - 1) % 3 == 1 ? Zu.V((k - 1) / 3) : Zu.S((k - 1) / 3 + 1)));
-        cu[k].v = x; cu[k].id = nd + k; cu[k].pad = 0; cu[k].tp = &tp;
+        cu[k].v = x; cu[k].id = nd + k; cu[k].lane = slot;
     }
     const int pS = nd + nu, pK = pS + 1, pR = pS + 2;
+    TapeHdr &tp = bt_tape[slot];
     tp.n = 0;
+    tp.cap = rc.tape;
     tp.ovf = 0;
     tp.base = pS + 3;
+    tp.ent = ent;
     TN tS = mk<TN>(S), tK = mk<TN>(kt), tR = mk<TN>(rho);
-    tS.id = pS; tS.tp = &tp;
-    tK.id = pK; tK.tp = &tp;
-    tR.id = pR; tR.tp = &tp;
+    tS.id = pS; tS.lane = slot;
+    tK.id = pK; tK.lane = slot;
+    tR.id = pR; tR.lane = slot;
     Inputs<TN> in;
     in.S0 = in.u = in.d = in.rho = in.k = mk<TN>(0.0);
     in.K = mk<TN>(md.K);
@@ -171,11 +191,13 @@ BTD int node_reverse(const Model &md, const View<double> &Zd, const View<double>
             if (Z.S(j + 1).id >= 0) adj[Z.S(j + 1).id] += zbar[3 + 3 * j];
         }
     }
+    const int base = tp.base;
     for (int e = tp.n - 1; e >= 0; e--) {
-        const double a = adj[tp.base + e];
+        const double a = adj[base + e];
         if (a == 0.0) continue;
-        if (tp.ia[e] >= 0) adj[tp.ia[e]] += a * tp.pa[e];
-        if (tp.ib[e] >= 0) adj[tp.ib[e]] += a * tp.pb[e];
+        const TapeEnt q = ent[e];
+        if (q.ia >= 0) adj[q.ia] += a * q.pa;
+        if (q.ib >= 0) adj[q.ib] += a * q.pb;
     }
     for (int k = 0; k < nd; k++) gd[k] = adj[k];
     for (int k = 0; k < nu; k++) gu[k] = adj[nd + k];

@@ -585,13 +585,16 @@ __global__ void bt_reset_kernel(KArgs A, int64_t n_fill)
 //             adjoint from level t to level t+1 (bt_adjoint.hpp); finally the
 //             leaves' adjoint gives their stock prices' and the cost rate's
 //             contributions.
-// Nodes whose children hold at most SMALL_CAP points are stepped by one lane
+// Nodes whose children hold at most ADJ_LANE_PTS points are stepped by one lane
 // each; larger ones are queued and stepped by the first lane of a wave with
 // that wave's large-node slot.  The adjoint of a child is the sum of what its
 // two parents give it; parents of even and of odd columns run in two passes,
 // so no two lanes add to one child at once and the sums have a fixed order.
 // ---------------------------------------------------------------------------
-constexpr int ADJ_SMALL_TAPE = 1024;
+// a lane steps nodes whose children hold up to ADJ_LANE_PTS points (stages
+// of 2 ADJ_LANE_PTS + 16, tape of ADJ_LANE_TAPE entries)
+constexpr int ADJ_LANE_PTS = 32;
+constexpr int ADJ_LANE_TAPE = 2048;
 
 struct AdjArgs {
     const Model *models;
@@ -627,7 +630,7 @@ struct Stepper {
     Caps fcp;
     TN *tn;
     RevCaps rc;
-    Tape *tape;
+    TapeEnt *ent;
     double *adj, *gd, *gu;
 };
 
@@ -636,10 +639,8 @@ BTHD int64_t stepper_doubles(int stage_cap, int child_cap, int tape)
     const Caps f = make_caps(stage_cap, stage_cap, stage_cap, stage_cap, stage_cap);
     const RevCaps r = rev_caps(stage_cap, child_cap, tape);
     int64_t d = (f.total + 1) & ~(int64_t)1;
-    d += 3 * r.tn;                                  // TN: 24 bytes each
-    d += 8;                                         // Tape (48 bytes)
-    d += tape;                                      // ia, ib (ints)
-    d += 2 * (int64_t)tape;                         // pa, pb
+    d += 2 * r.tn;                                  // TN: 16 bytes each
+    d += 3 * (int64_t)tape;                         // tape entries: 24 bytes each
     d += 3 * 2 * (int64_t)child_cap + 5 + tape;     // adj
     d += 2 * (3 * (int64_t)child_cap + 1);          // gd, gu
     return (d + 31) & ~(int64_t)31;
@@ -653,17 +654,9 @@ __device__ Stepper make_stepper(double *p, int stage_cap, int child_cap, int tap
     S.fwd = p;
     p += (S.fcp.total + 1) & ~(int64_t)1;
     S.tn = (TN *)p;
-    p += 3 * S.rc.tn;
-    S.tape = (Tape *)p;
-    p += 8;
-    S.tape->ia = (int32_t *)p;
-    S.tape->ib = (int32_t *)p + tape;
-    p += tape;
-    S.tape->pa = p;
-    p += tape;
-    S.tape->pb = p;
-    p += tape;
-    S.tape->cap = tape;
+    p += 2 * S.rc.tn;
+    S.ent = (TapeEnt *)p;
+    p += 3 * (int64_t)tape;
     S.adj = p;
     p += 3 * 2 * (int64_t)child_cap + 5 + tape;
     S.gd = p;
@@ -691,7 +684,6 @@ __device__ int64_t adj_fwd_level(const AdjArgs &A, const Model &md, int t, const
     const Inputs<double> in = inputs_of(md, 0.0);
     const double kt = (t >= 1 || (md.flags & F_COST_AT_T0)) ? md.k : 0.0;
     const bool ex = !((md.flags & F_EUROPEAN) && t < N);
-    const Caps sc = small_caps();
     int64_t run = 0;
     if (tid == 0) *sflag = 0;
     __syncthreads();
@@ -703,13 +695,13 @@ __device__ int64_t adj_fwd_level(const AdjArgs &A, const Model &md, int t, const
         Arr<double> Z{};
         if (act) {
             const View<double> Zd = level_view(up, c), Zu = level_view(up, c + 1);
-            if (Zd.m + Zu.m > SMALL_CAP) {
+            if (Zd.m + Zu.m > ADJ_LANE_PTS) {
                 bigq = true;
             } else {
                 const double S = Stab[2 * c - t + N + 1];
                 double xi, ze;
                 payoff(md, in, S, xi, ze);
-                mz = node_update<SIDE, double>(Zu, Zd, S, kt, md.rho, xi, ze, ex, lane.fwd, 1, sc, &Z);
+                mz = node_update<SIDE, double>(Zu, Zd, S, kt, md.rho, xi, ze, ex, lane.fwd, 1, lane.fcp, &Z);
                 bigq = mz < 0;
             }
         }
@@ -797,8 +789,8 @@ __device__ bool adj_node(const AdjArgs &A, const Model &md, int t, int c, const 
     const double *zbar = t >= 1 ? Acur + Lt.off[c] : nullptr;
     const int mz = t >= 1 ? Lt.cnt[c] : 0;
     double gp[3];
-    if (node_reverse<SIDE>(md, Zd, Zu, S, kt, md.rho, ex, zbar, mz, st.rc, st.tn, *st.tape, st.adj, st.gd, st.gu, gp,
-                           price))
+    if (node_reverse<SIDE>(md, Zd, Zu, S, kt, md.rho, ex, zbar, mz, st.rc, st.tn, threadIdx.x, st.ent, st.adj, st.gd,
+                           st.gu, gp, price))
         return false;
     double *ad = Anxt + Lc.off[c], *au = Anxt + Lc.off[c + 1];
     for (int q = 0; q < 3 * Zd.m + 1; q++) ad[q] += st.gd[q];
@@ -830,7 +822,7 @@ __device__ bool adj_rev_level(const AdjArgs &A, const Model &md, int t, const do
             bool bigq = false;
             if (c <= t) {
                 const int M = Lc.cnt[c] + Lc.cnt[c + 1];
-                bigq = M > SMALL_CAP || !adj_node<SIDE>(A, md, t, c, Stab, Sfac, Lt, Lc, Acur, Anxt, lane, g, price);
+                bigq = M > ADJ_LANE_PTS || !adj_node<SIDE>(A, md, t, c, Stab, Sfac, Lt, Lc, Acur, Anxt, lane, g, price);
             }
             int64_t tot;
             const int64_t bix = block_scan(bigq ? 1 : 0, &tot, sh);
@@ -893,7 +885,8 @@ __device__ void adjoint_tree(const AdjArgs &A, int opt, int64_t *sh, int *sbig, 
     // then per segment level, its record offset
     int64_t *cp_base = (int64_t *)(wsi + A.iTab);
     int64_t *sg_base = cp_base + A.cp_max + 1;
-    const Stepper lane = make_stepper(ws + A.oLane + (int64_t)tid * A.lane_doubles, SMALL_CAP, SMALL_CAP, ADJ_SMALL_TAPE);
+    const Stepper lane = make_stepper(ws + A.oLane + (int64_t)tid * A.lane_doubles, 2 * ADJ_LANE_PTS + 16, ADJ_LANE_PTS,
+                                      ADJ_LANE_TAPE);
     const Stepper big = make_stepper(ws + A.oBig + (int64_t)w * A.big_doubles, 2 * A.big_pts + 16, A.big_pts,
                                      40 * A.big_pts + 4096);
     const int s = isqrt_ceil(N + 2);
@@ -2130,7 +2123,7 @@ int adj_build(AdjWs *w, int cap_n, int cap_N)
     a.sg_max = s;
     a.cp_nums = round_up((int64_t)a.cp_max * a.lwn / 2, 32);
     a.sg_nums = round_up((int64_t)a.sg_max * a.lwn / 2, 32);
-    a.lane_doubles = stepper_doubles(SMALL_CAP, SMALL_CAP, ADJ_SMALL_TAPE);
+    a.lane_doubles = stepper_doubles(2 * ADJ_LANE_PTS + 16, ADJ_LANE_PTS, ADJ_LANE_TAPE);
     a.big_doubles = stepper_doubles(2 * B + 16, B, 40 * B + 4096);
     a.oStab = 0;
     a.oSfac = round_up(2 * NN, 32);

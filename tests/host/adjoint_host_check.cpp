@@ -137,10 +137,9 @@ static int run_side(const Model &md, double *price, double *grad, long long *tot
                     const int tcap = 200 * M + 2000;
                     const RevCaps rc = rev_caps(cap, std::max(Zd.m, Zu.m), tcap);
                     std::vector<TN> tn(rc.tn);
-                    std::vector<int32_t> ia(tcap), ib(tcap);
-                    std::vector<double> pa(tcap), pb(tcap), adj(3 * M + 5 + tcap);
+                    std::vector<TapeEnt> ent(tcap);
+                    std::vector<double> adj(3 * M + 5 + tcap);
                     std::vector<double> gd(3 * Zd.m + 1), gu(3 * Zu.m + 1);
-                    Tape tp{ia.data(), ib.data(), pa.data(), pb.data(), 0, tcap, 0, 0};
                     const double S = Stab[2 * c - t + N + 1];
                     double g[3], pr = 0.0;
                     const double *zbar = nullptr;
@@ -150,10 +149,10 @@ static int run_side(const Model &md, double *price, double *grad, long long *tot
                         zbar = Acur.data() + Lt.off[c];
                         mz = Lt.cnt[c];
                     }
-                    if (node_reverse<SIDE>(md, Zd, Zu, S, kt, md.rho, ex, zbar, mz, rc, tn.data(), tp, adj.data(),
-                                           gd.data(), gu.data(), g, &pr))
+                    if (node_reverse<SIDE>(md, Zd, Zu, S, kt, md.rho, ex, zbar, mz, rc, tn.data(), 0, ent.data(),
+                                           adj.data(), gd.data(), gu.data(), g, &pr))
                         return -2;
-                    g_peak_tape = std::max<long long>(g_peak_tape, tp.n);
+                    g_peak_tape = std::max<long long>(g_peak_tape, bt_tape[0].n);
                     g_peak_pts = std::max<long long>(g_peak_pts, M);
                     if (t == 0) {
                         *price = SIDE == 0 ? pr : -pr;
