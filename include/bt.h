@@ -52,11 +52,20 @@ extern "C" {
 #define BT_ENOSUPP (-5)   /* feature not supported                          */
 
 /* Payoff processes (xi_t, zeta_t) of Section 3: the holder who exercises at
- * t receives xi_t in cash and zeta_t shares.
- *   BT_PUT : (K, -1), physical delivery (Section 3's example)
- *   BT_CALL: (-K, 1), physical delivery
- *   BT_BULL: ((S-K)^+ - (S-K2)^+, 0), cash settled (Section 5's bull spread) */
-enum { BT_PUT = 0, BT_CALL = 1, BT_BULL = 2 };
+ * t receives xi_t in cash and zeta_t shares (settlement by delivery of the
+ * stock or in cash).
+ *   BT_PUT      : (K, -1), physical delivery (Section 3's example)
+ *   BT_CALL     : (-K, 1), physical delivery
+ *   BT_BULL     : ((S-K)^+ - (S-K2)^+, 0), cash settled (Section 5's bull
+ *                 spread; K2 > K)
+ *   BT_PUT_CASH : ((K-S)^+, 0), cash settled
+ *   BT_CALL_CASH: ((S-K)^+, 0), cash settled
+ *   BT_BEAR     : ((K2-S)^+ - (K-S)^+, 0), cash settled (K2 > K)
+ *   BT_STRADDLE : (|S-K|, 0), cash settled
+ * With costs the settlement matters: a delivered put or call trades the
+ * share at exercise, a cash-settled one does not.  At k = 0 both give the
+ * same prices. */
+enum { BT_PUT = 0, BT_CALL = 1, BT_BULL = 2, BT_PUT_CASH = 3, BT_CALL_CASH = 4, BT_BEAR = 5, BT_STRADDLE = 6 };
 
 /* Option flags.
  *   BT_F_EUROPEAN   exercise only at N (test variant; z_t = v_t for t < N)
@@ -64,7 +73,8 @@ enum { BT_PUT = 0, BT_CALL = 1, BT_BULL = 2 };
  *                   model charges none at t = 0, Section 4.1)              */
 enum { BT_F_EUROPEAN = 1u, BT_F_COST_AT_T0 = 2u };
 
-/* One option.  S0, K, sigma, T > 0; K2 > K for BT_BULL (ignored otherwise);
+/* One option.  S0, K, sigma, T > 0; K2 > K for BT_BULL and BT_BEAR
+ * (ignored otherwise);
  * R is the continuously compounded annual rate; 0 <= k < 1;
  * 1 <= N <= BT_MAX_N; the tree must be free of arbitrage: d < r < u. */
 typedef struct {

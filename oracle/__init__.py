@@ -20,7 +20,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
-PUT, CALL, BULL = 0, 1, 2
+PUT, CALL, BULL, PUT_CASH, CALL_CASH, BEAR, STRADDLE = 0, 1, 2, 3, 4, 5, 6
 EUROPEAN, COST_AT_T0 = 1, 2
 
 _lib = None

@@ -477,7 +477,8 @@ static double exp_nearest(double x)
     while (s-- > 0) sum = sum * sum;
     return (double)sum;
 }
-enum { PAY_PUT = 0, PAY_CALL = 1, PAY_BULL = 2 };
+enum { PAY_PUT = 0, PAY_CALL = 1, PAY_BULL = 2, PAY_PUT_CASH = 3, PAY_CALL_CASH = 4, PAY_BEAR = 5,
+       PAY_STRADDLE = 6 };
 enum { FL_EUROPEAN = 1u, FL_COST_AT_T0 = 2u };
 
 /* base^n by binary powering: acc *= base^(2^i) for each set bit i, in
@@ -503,13 +504,26 @@ typedef struct {
 
 static num stock(const model *md, int j) { return md->S[j + md->N + 1]; }
 
-/* Payoff (xi, zeta) at a node with stock price S: put (K, -1), call (-K, 1)
- * (both delivered physically), bull spread ((S-K)^+ - (S-K2)^+, 0) in cash. */
+/* Payoff (xi, zeta) at a node with stock price S (Section 3: the holder
+ * who exercises receives xi in cash and zeta shares; settlement in cash or
+ * by delivery).  Delivered physically: put (K, -1), call (-K, 1).  Settled
+ * in cash (zeta = 0): bull spread (S-K)^+ - (S-K2)^+, put (K-S)^+, call
+ * (S-K)^+, bear spread (K2-S)^+ - (K-S)^+, straddle |S-K|. */
 static void payoff(const model *md, num S, num *xi, num *zeta)
 {
-    if (md->payoff == PAY_PUT) { *xi = md->K; *zeta = nc(-1.0); }
-    else if (md->payoff == PAY_CALL) { *xi = nneg(md->K); *zeta = nc(1.0); }
-    else { *xi = nsub(npos(nsub(S, md->K)), npos(nsub(S, md->K2))); *zeta = nc(0.0); }
+    *zeta = nc(0.0);
+    switch (md->payoff) {
+    case PAY_PUT: *xi = md->K; *zeta = nc(-1.0); break;
+    case PAY_CALL: *xi = nneg(md->K); *zeta = nc(1.0); break;
+    case PAY_BULL: *xi = nsub(npos(nsub(S, md->K)), npos(nsub(S, md->K2))); break;
+    case PAY_PUT_CASH: *xi = npos(nsub(md->K, S)); break;
+    case PAY_CALL_CASH: *xi = npos(nsub(S, md->K)); break;
+    case PAY_BEAR: *xi = nsub(npos(nsub(md->K2, S)), npos(nsub(md->K, S))); break;
+    default: {
+        num e = nsub(S, md->K);
+        *xi = e.v > 0.0 ? e : nneg(e);
+    }
+    }
 }
 
 static int model_init(model *md, double S0, double K, double K2, double R, double sigma,
@@ -518,8 +532,8 @@ static int model_init(model *md, double S0, double K, double K2, double R, doubl
     if (!(N >= 1 && N <= (1 << 24))) return -1;
     if (!(isfinite(S0) && isfinite(K) && isfinite(R) && isfinite(sigma) && isfinite(T) && isfinite(k))) return -1;
     if (!(S0 > 0.0 && K > 0.0 && sigma > 0.0 && T > 0.0 && k >= 0.0 && k < 1.0)) return -1;
-    if (pay < 0 || pay > 2) return -1;
-    if (pay == PAY_BULL && !(isfinite(K2) && K2 > K)) return -1;
+    if (pay < 0 || pay > 6) return -1;
+    if ((pay == PAY_BULL || pay == PAY_BEAR) && !(isfinite(K2) && K2 > K)) return -1;
     memset(md, 0, sizeof(*md));
     md->N = N; md->payoff = pay; md->flags = flags;
     md->S0 = nc(S0); md->K = nc(K); md->K2 = nc(K2); md->k = nc(k);

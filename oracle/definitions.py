@@ -26,7 +26,7 @@ import numpy as np
 import scipy.sparse as sp
 from scipy.optimize import linprog
 
-PUT, CALL, BULL = 0, 1, 2
+PUT, CALL, BULL, PUT_CASH, CALL_CASH, BEAR, STRADDLE = 0, 1, 2, 3, 4, 5, 6
 EUROPEAN, COST_AT_T0 = 1, 2
 
 
@@ -43,12 +43,23 @@ def _exercisable(t, N, flags):
 
 
 def _payoff(pay, S, K, K2):
-    """(xi, zeta) of Section 3: put (K, -1), call (-K, 1), bull spread in cash."""
+    """(xi, zeta) of Section 3: the holder receives xi in cash and zeta
+    shares.  Put (K, -1) and call (-K, 1) by delivery; in cash: bull spread
+    (S-K)^+ - (S-K2)^+, put (K-S)^+, call (S-K)^+, bear spread
+    (K2-S)^+ - (K-S)^+, straddle |S-K|."""
     if pay == PUT:
         return K, -1.0
     if pay == CALL:
         return -K, 1.0
-    return max(S - K, 0.0) - max(S - K2, 0.0), 0.0
+    if pay == BULL:
+        return max(S - K, 0.0) - max(S - K2, 0.0), 0.0
+    if pay == PUT_CASH:
+        return max(K - S, 0.0), 0.0
+    if pay == CALL_CASH:
+        return max(S - K, 0.0), 0.0
+    if pay == BEAR:
+        return max(K2 - S, 0.0) - max(K - S, 0.0), 0.0
+    return abs(S - K), 0.0
 
 
 def exp_nearest(x):

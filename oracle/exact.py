@@ -30,7 +30,7 @@ trees (N up to about 30).
 """
 from fractions import Fraction
 
-PUT, CALL, BULL = 0, 1, 2
+PUT, CALL, BULL, PUT_CASH, CALL_CASH, BEAR, STRADDLE = 0, 1, 2, 3, 4, 5, 6
 EUROPEAN, COST_AT_T0 = 1, 2
 
 
@@ -149,11 +149,22 @@ def restrict(f, a, b):
 
 
 def _payoff(pay, S, K, K2):
+    """(xi, zeta) of Section 3 for every payoff shape; works on Fractions and
+    on floats alike."""
+    zero = S - S
     if pay == PUT:
-        return K, Fraction(-1)
+        return K, zero - 1
     if pay == CALL:
-        return -K, Fraction(1)
-    return max(S - K, Fraction(0)) - max(S - K2, Fraction(0)), Fraction(0)
+        return -K, zero + 1
+    if pay == BULL:
+        return max(S - K, zero) - max(S - K2, zero), zero
+    if pay == PUT_CASH:
+        return max(K - S, zero), zero
+    if pay == CALL_CASH:
+        return max(S - K, zero), zero
+    if pay == BEAR:
+        return max(K2 - S, zero) - max(K - S, zero), zero
+    return abs(S - K), zero
 
 
 def _node_constants(S, kt, pay, K, K2, rounded):
@@ -165,12 +176,7 @@ def _node_constants(S, kt, pay, K, K2, rounded):
         return -(one + kt) * S, -(one - kt) * S, xi, ze
     s, k_, K_, K2_ = float(S), float(kt), float(K), float(K2)
     a, b = -((1.0 + k_) * s), -((1.0 - k_) * s)
-    if pay == PUT:
-        xi, ze = K_, -1.0
-    elif pay == CALL:
-        xi, ze = -K_, 1.0
-    else:
-        xi, ze = max(s - K_, 0.0) - max(s - K2_, 0.0), 0.0
+    xi, ze = _payoff(pay, s, K_, K2_)
     return Fraction(a), Fraction(b), Fraction(xi), Fraction(ze)
 
 

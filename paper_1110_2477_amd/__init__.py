@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbtprice.so")
 
 BT_OK, BT_EINVAL, BT_ENOMEM, BT_EHIP, BT_EOVERFLOW, BT_ENOSUPP = 0, -1, -2, -3, -4, -5
-PUT, CALL, BULL = 0, 1, 2
+PUT, CALL, BULL, PUT_CASH, CALL_CASH, BEAR, STRADDLE = 0, 1, 2, 3, 4, 5, 6
 EUROPEAN, COST_AT_T0 = 1, 2
 
 # Function names declared in include/bt.h.

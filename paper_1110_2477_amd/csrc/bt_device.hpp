@@ -17,7 +17,7 @@ constexpr int WG = 256;          // lanes per workgroup (4 waves of 64)
 constexpr int NWAVE = WG / 64;
 constexpr int SMALL_CAP = 12;    // points per stage on the interleaved fast path
 
-enum { PAY_PUT = 0, PAY_CALL = 1, PAY_BULL = 2 };
+enum { PAY_PUT = 0, PAY_CALL = 1, PAY_BULL = 2, PAY_PUT_CASH = 3, PAY_CALL_CASH = 4, PAY_BEAR = 5, PAY_STRADDLE = 6 };
 enum { F_EUROPEAN = 1u, F_COST_AT_T0 = 2u };
 
 // The model's inputs as numbers of type T: plain values, or for D4 the
@@ -84,17 +84,32 @@ BTD Arr<T> stage(T *base, int st, int64_t off, int cap)
     return a;
 }
 
-// Exercise payoff (xi, zeta) at stock price S (Section 3 and Section 5):
-// put (K, -1), call (-K, 1), bull spread ((S-K)^+ - (S-K2)^+, 0) in cash.
+template <typename T>
+BTD T pos_part(const T &x)
+{
+    return val(x) > 0.0 ? x : mk<T>(0.0);
+}
+
+// Exercise payoff (xi, zeta) at stock price S (Section 3: xi in cash and
+// zeta shares; settled by delivery or in cash).  Delivered: put (K, -1),
+// call (-K, 1).  In cash (zeta = 0): bull spread (S-K)^+ - (S-K2)^+
+// (Section 5), put (K-S)^+, call (S-K)^+, bear spread (K2-S)^+ - (K-S)^+,
+// straddle |S-K|.
 template <typename T>
 BTD void payoff(const Model &md, const Inputs<T> &in, const T &S, T &xi, T &zeta)
 {
-    if (md.payoff == PAY_PUT) { xi = in.K; zeta = mk<T>(-1.0); }
-    else if (md.payoff == PAY_CALL) { xi = -in.K; zeta = mk<T>(1.0); }
-    else {
-        const T e1 = S - in.K, e2 = S - in.K2;
-        xi = (val(e1) > 0.0 ? e1 : mk<T>(0.0)) - (val(e2) > 0.0 ? e2 : mk<T>(0.0));
-        zeta = mk<T>(0.0);
+    zeta = mk<T>(0.0);
+    switch (md.payoff) {
+    case PAY_PUT: xi = in.K; zeta = mk<T>(-1.0); break;
+    case PAY_CALL: xi = -in.K; zeta = mk<T>(1.0); break;
+    case PAY_BULL: xi = pos_part(S - in.K) - pos_part(S - in.K2); break;
+    case PAY_PUT_CASH: xi = pos_part(in.K - S); break;
+    case PAY_CALL_CASH: xi = pos_part(S - in.K); break;
+    case PAY_BEAR: xi = pos_part(in.K2 - S) - pos_part(in.K - S); break;
+    default: {
+        const T e = S - in.K;
+        xi = val(e) > 0.0 ? e : -e;
+    }
     }
 }
 

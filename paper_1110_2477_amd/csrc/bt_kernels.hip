@@ -1131,13 +1131,14 @@ struct PlanArgs {
     int64_t istride;     // ints of offsets and counts per tree side
 };
 
-// Bits of the tree sides whose nodes grow large: 1 = the buyer of a call or
-// a bull spread with costs, 2 = the seller of a bull spread with costs (the
-// order a book uses puts them first in each party's task list).
+// Bits of the tree sides whose nodes grow large: 1 = the buyer of anything
+// but a delivered put with costs, 2 = the seller of a cash-settled payoff
+// with costs (the order a book uses puts them first in each party's task
+// list).
 BTHD int growth_bits(const Model &m)
 {
     if (!m.valid || !(m.k > 0.0)) return 0;
-    return (m.payoff != PAY_PUT ? 1 : 0) | (m.payoff == PAY_BULL ? 2 : 0);
+    return (m.payoff != PAY_PUT ? 1 : 0) | (m.payoff >= PAY_BULL ? 2 : 0);
 }
 
 // Upper bound on the column blocks of one tree side in launch L: every tree
@@ -1392,7 +1393,7 @@ int64_t arena_estimate(const std::vector<Model> &models, const std::vector<Item>
         if (it.side != side || !(m.k > 0)) continue;
         int64_t M = 0;
         if (side == 1 && m.payoff != BT_PUT) M = 5 * (int64_t)it.N;
-        if (side == 0 && m.payoff == BT_BULL) M = it.N;
+        if (side == 0 && m.payoff >= BT_BULL) M = it.N;
         const int64_t need = (64 * M + 4096) * nt;   // as big_need on the device
         if (need > slice) needs.push_back(need);
     }
@@ -1439,7 +1440,7 @@ int book_build(bt_book *b, const bt_params *h, int n, const bt_tune *tune)
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return models[x].N > models[y].N; });
     const auto grows = [&](int i, int side) {
         const Model &m = models[i];
-        return m.k > 0 && (side == 1 ? m.payoff != BT_PUT : m.payoff == BT_BULL);
+        return m.k > 0 && (side == 1 ? m.payoff != BT_PUT : m.payoff >= BT_BULL);
     };
     std::vector<Item> items;
     int64_t lbuf = 0, ibuf = 0, ctr = 0;

@@ -161,7 +161,7 @@ BTHD double cr_sqrt(double x)
 // Derives the tree constants of one option; false (m.valid = 0) if the
 // option is invalid: N outside 1..max_N, a non-finite input, S0, K, sigma or
 // T not positive, k outside [0, 1), an unknown payoff or flag, K2 <= K for a
-// bull spread, |sigma sqrt(T/N)| or |R T/N| above 700 (the tree's prices
+// bull or bear spread, |sigma sqrt(T/N)| or |R T/N| above 700 (the tree's prices
 // would overflow), or a tree that is not free of arbitrage (d < r < u fails).
 BTHD bool derive_model(const bt_params &p, int max_N, Model &m)
 {
@@ -172,8 +172,8 @@ BTHD bool derive_model(const bt_params &p, int max_N, Model &m)
                         p.T - p.T == 0.0 && p.k - p.k == 0.0;
     if (!finite) return false;
     if (!(p.S0 > 0.0 && p.K > 0.0 && p.sigma > 0.0 && p.T > 0.0 && p.k >= 0.0 && p.k < 1.0)) return false;
-    if (p.payoff < 0 || p.payoff > 2) return false;
-    if (p.payoff == BT_BULL && !(p.K2 - p.K2 == 0.0 && p.K2 > p.K)) return false;
+    if (p.payoff < 0 || p.payoff > BT_STRADDLE) return false;
+    if ((p.payoff == BT_BULL || p.payoff == BT_BEAR) && !(p.K2 - p.K2 == 0.0 && p.K2 > p.K)) return false;
     if (p.flags & ~(uint32_t)(BT_F_EUROPEAN | BT_F_COST_AT_T0)) return false;
     const double dt = p.T / (double)p.N;
     if (!(dt >= 2.2250738585072014e-308)) return false;   // sqrt below needs a normal argument

@@ -10,7 +10,7 @@ those workloads at the sizes used by the tests and the benchmark.
 """
 import numpy as np
 
-PUT, CALL, BULL = 0, 1, 2
+PUT, CALL, BULL, PUT_CASH, CALL_CASH, BEAR, STRADDLE = 0, 1, 2, 3, 4, 5, 6
 EUROPEAN, COST_AT_T0 = 1, 2
 
 # Layout of bt_params in include/bt.h (72 bytes).
@@ -125,6 +125,23 @@ def random_small(n, seed, n_max=300):
         K = S0 * g.uniform(0.8, 1.2)
         k = float(g.choice([0.0, g.uniform(0, 0.02), g.uniform(0, 0.1)]))
         b[i] = (S0, K, K * g.uniform(1.05, 1.3) if pay == BULL else 0.0, g.uniform(0, 0.08),
+                g.uniform(0.1, 0.6), g.uniform(0.1, 2.0), k, int(g.integers(1, n_max + 1)), pay,
+                int(g.choice([0, 0, 0, EUROPEAN, COST_AT_T0])), 0)
+    return b
+
+
+def variants_book(n, seed, n_max=200):
+    """Every payoff shape (delivered and cash-settled puts and calls, bull
+    and bear spreads, straddles), every flag, costs from zero to 10 %, N from
+    1 to n_max; payoff = index mod 7 so that each shape appears."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    b = np.zeros(n, dtype=PARAMS_DTYPE)
+    for i in range(n):
+        pay = i % 7
+        S0 = 100 * np.exp(0.2 * g.standard_normal())
+        K = S0 * g.uniform(0.8, 1.2)
+        k = float(g.choice([0.0, g.uniform(0, 0.02), g.uniform(0, 0.1)]))
+        b[i] = (S0, K, K * g.uniform(1.05, 1.3) if pay in (BULL, BEAR) else 0.0, g.uniform(0, 0.08),
                 g.uniform(0.1, 0.6), g.uniform(0.1, 2.0), k, int(g.integers(1, n_max + 1)), pay,
                 int(g.choice([0, 0, 0, EUROPEAN, COST_AT_T0])), 0)
     return b

@@ -92,3 +92,23 @@ def test_cooperative_path_tangents_match_oracle(harness, lanes):
         ga = np.array([float.fromhex(x) for x in f[7:11]])
         gb = np.array([float.fromhex(x) for x in f[11:15]])
         assert np.array_equal(ga, o["grad_ask"]) and np.array_equal(gb, o["grad_bid"]), (c, ga, gb, o)
+
+
+def test_cooperative_path_every_payoff_shape(harness):
+    # cash-settled puts and calls, bear spreads and straddles as well
+    from paper_1110_2477_amd import workloads as W
+    b = W.variants_book(28, seed=104, n_max=120)
+    cases = [(float(p["S0"]), float(p["K"]), float(p["K2"]), float(p["R"]), float(p["sigma"]), float(p["T"]),
+              float(p["k"]), int(p["N"]), int(p["payoff"]), int(p["flags"])) for p in b]
+    out, _ = _run(harness, cases, grad=True, lanes=64)
+    for c, line in zip(cases, out):
+        f = line.split()
+        o = _oracle(c, grad=True)
+        assert int(f[0]) == 0, c
+        assert float.fromhex(f[1]) == o["ask"] and float.fromhex(f[2]) == o["bid"], c
+        assert (int(f[3]), int(f[4]), int(f[5]), int(f[6])) == (
+            o["bp_total_ask"], o["bp_total_bid"], o["bp_max_ask"], o["bp_max_bid"]), c
+        ga = np.array([float.fromhex(x) for x in f[7:11]])
+        gb = np.array([float.fromhex(x) for x in f[11:15]])
+        assert np.array_equal(ga, o["grad_ask"]) and np.array_equal(gb, o["grad_bid"]), c
+
