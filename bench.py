@@ -169,6 +169,30 @@ def counter_summary(d):
     return out
 
 
+def algorithm1_leg(bt, W, np, cores):
+    """The paper's own parallel algorithm (Section 4.2, Algorithm 1) on the
+    host's cores (libbtcpu): the paper's headline experiment -- the Table 2
+    American put, N = 1500, k = 0.5 %, L = 5 -- serially and on 8 threads,
+    and the grid's 24 N = 1500 trees one at a time on all cores."""
+    put = W.book([dict(S0=100.0, K=100.0, R=0.1, sigma=0.2, T=0.25, k=0.005, N=1500, payoff=W.PUT)])[0]
+    _, s1 = bt.cpu_price(put, 1, 5)
+    _, s8 = bt.cpu_price(put, min(8, cores), 5)
+    threads = min(64, cores)
+    sample = W.paper_grid(1500)
+    t = 0.0
+    for p in sample:
+        _, st = bt.cpu_price(p, threads, 5)
+        t += st["seconds"]
+    nodes = W.nodes(sample)
+    return {"value": nodes / t, "unit": "tree nodes/s", "cores": threads, "kind": "paper_algorithm1",
+            "sample": "the grid's 24 N=1500 trees (ask, bid, price0), one tree at a time on all threads, L = 5",
+            "seconds": t,
+            "table2_put_N1500": {"serial_ms": s1["seconds"] * 1e3, "threads": min(8, cores),
+                                 "parallel_ms": s8["seconds"] * 1e3, "speedup": s1["seconds"] / s8["seconds"],
+                                 "efficiency": s1["seconds"] / s8["seconds"] / min(8, cores),
+                                 "paper": "5.26x, 65.75 % on 8 cores of 2x Xeon E5405 (serial 1983.7 ms)"}}
+
+
 def timed_job(bk, greeks, torch, np, bt):
     """Times one whole pricing of a book: the pricing call, then the
     re-pricing of any option that outgrew its buffers.  Returns the total
@@ -574,6 +598,7 @@ def main():
                                "gpu_same_sample": {"value": W.nodes(sample) / gpu_sample_s,
                                                    "seconds": gpu_sample_s, "ok": sample_ok},
                                "gpu_vs_oracle": compare_with_oracle(gpu_res, ref)}
+        out["cpu_baseline_algorithm1"] = algorithm1_leg(bt, W, np, cores)
     print(json.dumps(out), flush=True)
 
 

@@ -313,6 +313,43 @@ def bt_model_constants(params):
     return dict(zip(("u", "d", "r", "rho", "p"), (v.value for v in vals)))
 
 
+CPU_LIB_PATH = os.path.join(HERE, "libbtcpu.so")
+_cpu = None
+
+
+class _CpuStats(ctypes.Structure):
+    _fields_ = [("seconds", ctypes.c_double), ("nodes", ctypes.c_int64 * 64), ("threads", ctypes.c_int32),
+                ("rounds", ctypes.c_int32)]
+
+
+def cpu_lib():
+    """The loaded libbtcpu (the paper's Algorithm 1 on host threads)."""
+    global _cpu
+    if _cpu is not None:
+        return _cpu
+    if not os.path.exists(CPU_LIB_PATH):
+        raise RuntimeError(f"{CPU_LIB_PATH} is missing: build it with paper_1110_2477_amd/build.py")
+    L = ctypes.CDLL(CPU_LIB_PATH)
+    L.bt_cpu_price.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    L.bt_cpu_price.restype = ctypes.c_int
+    _cpu = L
+    return L
+
+
+def cpu_price(params, threads, L=5):
+    """One option by Algorithm 1 (Section 4.2) on `threads` host threads with
+    at most L levels per round; returns (RESULT_DTYPE record, stats dict with
+    seconds, per-thread node counts and rounds)."""
+    p = _params(params)
+    if len(p) != 1:
+        raise ValueError("cpu_price takes one option")
+    out = np.zeros(1, dtype=RESULT_DTYPE)
+    st = _CpuStats()
+    _check(cpu_lib().bt_cpu_price(p.ctypes.data, int(threads), int(L), out.ctypes.data, ctypes.byref(st)),
+           "bt_cpu_price")
+    return out[0], dict(seconds=st.seconds, nodes=list(st.nodes[:int(threads)]), rounds=int(st.rounds))
+
+
 class Book:
     """A priced-repeatedly batch of options on the current GPU.
 

@@ -28,6 +28,25 @@ def hip_flags():
     ]
 
 
+CPU_LIB = os.path.join(HERE, "libbtcpu.so")
+CPU_SOURCES = [os.path.join(CSRC, "bt_cpu_alg1.cpp")]
+
+
+def build_cpu(verbose: bool = False) -> str:
+    """libbtcpu.so: the paper's Algorithm 1 on host threads (include/bt_cpu.h),
+    built with the host compiler from the same per-node code as the kernels
+    (contraction off, so its results are the kernels' bits)."""
+    tmp = CPU_LIB + ".tmp"
+    cmd = ["g++", "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread", "-ffp-contract=off", "-fno-fast-math",
+           "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
+           "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-o", tmp, *CPU_SOURCES]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, CPU_LIB)
+    return CPU_LIB
+
+
 def build(verbose: bool = False, extra=()) -> str:
     tmp = LIB + ".tmp"
     cmd = [HIPCC, *hip_flags(), *extra, "-shared", "-o", tmp, *SOURCES]
@@ -35,6 +54,7 @@ def build(verbose: bool = False, extra=()) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    build_cpu(verbose)
     return LIB
 
 

@@ -31,7 +31,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#ifdef BT_HOST_DEBUG
+// BT_HOST_BUILD (or BT_HOST_DEBUG, the CPU test builds) compiles every
+// operation for the host as well: the host-thread baseline of Section 4.2
+// runs the same node update as the kernels.
+#if defined(BT_HOST_DEBUG) || defined(BT_HOST_BUILD)
 #define BTD __host__ __device__ inline
 #else
 #define BTD __device__ __forceinline__
@@ -41,7 +44,7 @@
 // pool, arena).  Accessing them through a global-qualified pointer lets the
 // compiler emit global instead of flat loads and stores, which do not wait
 // on LDS traffic.
-#if defined(__HIP_DEVICE_COMPILE__) && !defined(BT_HOST_DEBUG)
+#if defined(__HIP_DEVICE_COMPILE__) && !defined(BT_HOST_DEBUG) && !defined(BT_HOST_BUILD)
 #define BT_GLOBAL __attribute__((address_space(1)))
 #else
 #define BT_GLOBAL
