@@ -105,7 +105,20 @@ typedef struct {
     bt_grad4 ask, bid;
 } bt_grad;
 
-/* Launch tuning; pass NULL for the library's choice.  Zero fields also mean
+/* The optimal stock holdings at t = 0 -- the hedges of the two parties
+ * (Section 3: the root's slope restriction is the cheapest rebalancing from
+ * no shares, v_0(0) = min over y of f(y) + S^a_0 y^+ - S^b_0 y^-, with
+ * f = rho max(z_1(1), z_1(0)) of the party).  [ask_lo, ask_hi]: the
+ * holdings the seller carries from t = 0 to t = 1 in an optimal superhedge
+ * of the ask; [bid_lo, bid_hi]: the buyer's.  The minimum is attained at a
+ * breakpoint of f or at 0; the interval spans the candidates within 1e-12
+ * (relative, floor 1) of it, a single point unless a piece is flat.  At
+ * k = 0 the seller holds the CRR delta and the buyer its opposite. */
+typedef struct {
+    double ask_lo, ask_hi, bid_lo, bid_hi;
+} bt_hedge;
+
+/* Launch tuning; pass NULL for the library's choice./* Launch tuning; pass NULL for the library's choice.  Zero fields also mean
  * "library's choice".
  *   wgs_per_cu   persistent workgroups per compute unit (default 2)
  *   level_factor capacity of one tree level, in points per node (default
@@ -294,6 +307,13 @@ int bt_price_adjoint_batch(const bt_params *d_params, int32_t n, int32_t max_N, 
 #define BT_STATIC_MAX_OPTIONS 64
 #define BT_STATIC_MAX_N 1024
 int bt_price_batch_static(const bt_params *d_params, int32_t n, int32_t max_N, bt_result *d_out, void *stream);
+
+/* As bt_book_price, and the hedges at t = 0 of every option into d_hedge
+ * (device pointer to n bt_hedge, NaN where status is not BT_OK): the root
+ * of each tree side recomputes its discounted maximum in its workgroup's
+ * temporaries and minimises the rebalancing cost over its breakpoints.  Not
+ * replayed from a graph (BT_TUNE_GRAPH does not apply). */
+int bt_book_price_hedge(bt_book *book, bt_result *d_out, bt_hedge *d_hedge, void *stream);
 
 /* Completes a pricing call whose options overflowed the book's buffers
  * (status BT_EOVERFLOW: a tree whose band levels, private levels or

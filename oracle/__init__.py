@@ -42,6 +42,8 @@ def _load():
         f.restype = ctypes.c_int
         f.argtypes = [ctypes.c_double] * 7 + [ctypes.c_int, ctypes.c_int, ctypes.c_uint,
                                               ctypes.c_int, _dp, _i64p, _dp]
+    lib.oracle_hedge_v.restype = ctypes.c_int
+    lib.oracle_hedge_v.argtypes = [ctypes.c_double] * 7 + [ctypes.c_int, ctypes.c_int, ctypes.c_uint, _dp]
     lib.oracle_flops_v.restype = ctypes.c_uint64
     lib.oracle_flops_v.argtypes = []
     lib.oracle_model_v.restype = ctypes.c_int
@@ -92,6 +94,22 @@ def price(S0, K, R, sigma, T, k, N, payoff=PUT, K2=0.0, flags=0, sides=3, grad=F
         res["grad_ask"] = g[:4].copy()
         res["grad_bid"] = g[4:].copy()
     return res
+
+
+def hedge(S0, K, R, sigma, T, k, N, payoff=PUT, K2=0.0, flags=0):
+    """The optimal stock holdings at t = 0: dict(ask=(lo, hi), bid=(lo, hi))."""
+    lib = _load()
+    out = np.zeros(4)
+    rc = lib.oracle_hedge_v(float(S0), float(K), float(K2), float(R), float(sigma), float(T), float(k),
+                            int(N), int(payoff), int(flags), out.ctypes.data_as(_dp))
+    if rc != 0:
+        raise OracleError("invalid option parameters")
+    return dict(ask=(out[0], out[1]), bid=(out[2], out[3]))
+
+
+def hedge_params(p):
+    return hedge(p["S0"], p["K"], p["R"], p["sigma"], p["T"], p["k"], int(p["N"]), payoff=int(p["payoff"]),
+                 K2=p["K2"], flags=int(p["flags"]))
 
 
 def flops():

@@ -38,6 +38,8 @@
  *   model_init, upow         13.906 (Appendix); Black-Scholes convergence
  *                            and put-call parity (European, k = 0)
  *   crr_price                k = 0 ask = bid = CRR; 13.906
+ *   root_hedge               the superhedging LP's root holding; the CRR
+ *                            delta at k = 0 (test_oracle_hedge.py)
  *   side_price               every test above; cost at t = 0 and the
  *                            European variant against their LPs and
  *                            enumerations; level N+1 against the one-step
@@ -600,7 +602,34 @@ static double crr_price(const model *md)
  *   ask = z_0(0), bid = -z_0(0).
  * Up child of (t, c) is (t+1, c+1).  European variant: z_t = v_t for t < N.
  */
-static int side_price(const model *md, int side, num *root, int64_t *bp_total, int *bp_max)
+/* The optimal stock holding at t = 0 (the hedge): with f = rho max(z_1(1),
+ * z_1(0)) and the rebalancing cost from no shares to y, the root's
+ * restriction is v_0(0) = min over y of g(y), g(y) = f(y) + S^a_0 y for
+ * y >= 0 and f(y) + S^b_0 y for y < 0 (Section 3: the cheapest portfolio
+ * from which the node's expense is covered).  g is piecewise linear with
+ * kinks at f's breakpoints and at 0, so its minimum is attained there; the
+ * hedge is the interval [lo, hi] of those candidates whose g is within
+ * 1e-12 (relative, floor 1) of the smallest. */
+static void root_hedge(const pwl *f, num Sa, num Sb, double *lo, double *hi)
+{
+    double gmin = INFINITY;
+    for (int pass = 0; pass < 2; pass++) {
+        int first = 1;
+        for (int j = 0; j <= f->m; j++) {
+            double y = j < f->m ? f->x[j].v : 0.0;
+            double g = pwl_eval(f, nc(y)).v + (y >= 0.0 ? Sa.v * y : Sb.v * y);
+            if (pass == 0) {
+                if (g < gmin) gmin = g;
+            } else if (g <= gmin + 1e-12 * fmax(1.0, fabs(gmin))) {
+                if (first || y < *lo) *lo = y;
+                if (first || y > *hi) *hi = y;
+                first = 0;
+            }
+        }
+    }
+}
+
+static int side_price_h(const model *md, int side, num *root, int64_t *bp_total, int *bp_max, double *hedge)
 {
     int N = md->N;
     pwl *cur = (pwl *)calloc(N + 2, sizeof(pwl));
@@ -622,6 +651,7 @@ static int side_price(const model *md, int side, num *root, int64_t *bp_total, i
             num b = nneg(nmul(nsub(one, kt), S));
             pwl_merge(&cur[c + 1], &cur[c], OP_MAX, &W);
             pwl_scale(&W, md->rho);
+            if (t == 0 && hedge) root_hedge(&W, nneg(a), nneg(b), &hedge[0], &hedge[1]);
             if (side == 0) pwl_clip(&W, a, b, &V);
             else pwl_env(&W, a, b, &V);
             if (euro && t < N) {
@@ -646,6 +676,11 @@ static int side_price(const model *md, int side, num *root, int64_t *bp_total, i
     free(cur); free(nxt);
     pwl_free(&W); pwl_free(&V); pwl_free(&U);
     return 0;
+}
+
+static int side_price(const model *md, int side, num *root, int64_t *bp_total, int *bp_max)
+{
+    return side_price_h(md, side, root, bp_total, bp_max, NULL);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -675,6 +710,21 @@ int API(oracle_price)(double S0, double K, double K2, double R, double sigma, do
         if (grad) for (int i = 0; i < NT && i < 4; i++) grad[4 * side + i] = price.d[i];
     }
     out[2] = crr_price(&md);
+    free(md.S);
+    return 0;
+}
+
+/* The hedges at t = 0 (root_hedge): out[0..1] = the seller's interval,
+ * out[2..3] = the buyer's.  Returns 0, or -1 for invalid parameters. */
+int API(oracle_hedge)(double S0, double K, double K2, double R, double sigma, double T, double k,
+                      int N, int pay, unsigned flags, double *out)
+{
+    model md;
+    if (model_init(&md, S0, K, K2, R, sigma, T, k, N, pay, flags) != 0) return -1;
+    for (int side = 0; side < 2; side++) {
+        num root; int64_t tot; int mx;
+        side_price_h(&md, side, &root, &tot, &mx, out + 2 * side);
+    }
     free(md.S);
     return 0;
 }

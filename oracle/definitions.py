@@ -89,7 +89,7 @@ def _nodes(N):
     return out[: 2 ** (N + 2) - 1]
 
 
-def ask_lp(S0, K, R, sigma, T, k, N, payoff=PUT, K2=0.0, flags=0):
+def ask_lp(S0, K, R, sigma, T, k, N, payoff=PUT, K2=0.0, flags=0, with_hedge=False):
     """Seller's superhedging price by linear programming on the path tree.
 
     The portfolio that arrives at a node must cover delivery there when the
@@ -145,7 +145,25 @@ def ask_lp(S0, K, R, sigma, T, k, N, payoff=PUT, K2=0.0, flags=0):
     res = linprog(c, A_ub=Aub, b_ub=bub, A_eq=Aeq, b_eq=beq, bounds=bounds, method="highs")
     if res.status != 0:
         raise RuntimeError("ask LP failed: " + res.message)
+    if with_hedge:
+        # the holding the optimal portfolio carries from t = 0 to t = 1
+        return res.fun, res.x[Y(1)]
     return res.fun
+
+
+def crr_values(S0, K, R, sigma, T, N, payoff=PUT, K2=0.0, level=1):
+    """The zero-cost American values V_t(c) at one level of the N-step tree
+    and its stock prices: V_N = max(xi + zeta S, 0), V_t = max(xi + zeta S,
+    (p V_t+1(c+1) + (1-p) V_t+1(c)) / r) (Section 3), for t = level."""
+    u, r = _tree(S0, sigma, R, T, N)
+    d = 1.0 / u
+    p = (r - d) / (u - d)
+    S = lambda t, c: S0 * u ** (2 * c - t)
+    ex = lambda t, c: max(sum(np.multiply(_payoff(payoff, S(t, c), K, K2), (1.0, S(t, c)))), 0.0)
+    V = [ex(N, c) for c in range(N + 1)]
+    for t in range(N - 1, level - 1, -1):
+        V = [max(ex(t, c), (p * V[c + 1] + (1 - p) * V[c]) / r) for c in range(t + 1)]
+    return V, [S(level, c) for c in range(level + 1)]
 
 
 def _stopping_times(N, flags=0):

@@ -12,7 +12,7 @@ import os
 
 import numpy as np
 
-from .workloads import GRAD_DTYPE, PARAMS_DTYPE, RESULT_DTYPE  # noqa: F401
+from .workloads import GRAD_DTYPE, HEDGE_DTYPE, PARAMS_DTYPE, RESULT_DTYPE  # noqa: F401
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbtprice.so")
@@ -23,6 +23,7 @@ EUROPEAN, COST_AT_T0 = 1, 2
 
 # Function names declared in include/bt.h.
 ABI_FUNCTIONS = ("bt_autotune", "bt_book_create", "bt_book_info", "bt_book_price", "bt_book_price_grad",
+                 "bt_book_price_hedge",
                  "bt_book_resolve_overflow", "bt_book_timings", "bt_book_destroy", "bt_price", "bt_shutdown",
                  "bt_price_batch", "bt_price_grad_batch", "bt_price_adjoint_batch", "bt_price_batch_static",
                  "bt_model_constants",
@@ -75,6 +76,7 @@ def lib():
     L.bt_book_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), i64p]
     L.bt_book_price.argtypes = [vp, vp, vp]
     L.bt_book_price_grad.argtypes = [vp, vp, vp, vp]
+    L.bt_book_price_hedge.argtypes = [vp, vp, vp, vp]
     L.bt_book_timings.argtypes = [vp, dp, ctypes.POINTER(i32)]
     L.bt_book_resolve_overflow.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i32)]
     L.bt_book_destroy.argtypes = [vp]
@@ -91,7 +93,8 @@ def lib():
     L.bt_strerror.restype = ctypes.c_char_p
     L.bt_version.argtypes = []
     L.bt_last_hip_error.argtypes = []
-    for f in ("bt_autotune", "bt_book_create", "bt_book_info", "bt_book_price", "bt_book_price_grad", "bt_book_timings", "bt_book_resolve_overflow",
+    for f in ("bt_autotune", "bt_book_create", "bt_book_info", "bt_book_price", "bt_book_price_grad",
+              "bt_book_price_hedge", "bt_book_timings", "bt_book_resolve_overflow",
               "bt_price", "bt_shutdown", "bt_model_constants", "bt_version", "bt_last_hip_error",
               "bt_price_batch", "bt_price_grad_batch", "bt_price_batch_static", "bt_price_adjoint_batch"):
         getattr(L, f).restype = ctypes.c_int
@@ -384,6 +387,22 @@ class Book:
             self.grad = torch.empty(self.n * GRAD_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
         bt_book_price_grad(self.handle, self.out.data_ptr(), self.grad.data_ptr(), stream)
         return self.out, self.grad
+
+    def price_hedge(self, stream=None):
+        """Prices the book and writes the hedges at t = 0 (HEDGE_DTYPE
+        records, see hedges())."""
+        import torch
+        if getattr(self, "hedge", None) is None:
+            self.hedge = torch.empty(self.n * HEDGE_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        _check(lib().bt_book_price_hedge(self.handle, ctypes.c_void_p(self.out.data_ptr()),
+                                         ctypes.c_void_p(self.hedge.data_ptr()), ctypes.c_void_p(_stream_ptr(stream))),
+               "bt_book_price_hedge")
+        return self.out, self.hedge
+
+    def hedges(self):
+        import torch
+        torch.cuda.synchronize()
+        return np.frombuffer(self.hedge.cpu().numpy().tobytes(), dtype=HEDGE_DTYPE).copy()
 
     def timings(self):
         return bt_book_timings(self.handle)

@@ -135,6 +135,45 @@ BTD T stock_at(const Inputs<T> &in, int j)
     return in.S0 * (j >= 0 ? upow(in.u, j) : upow(in.d, -j));
 }
 
+// The optimal stock holding at t = 0, the hedge (Section 3: the root's
+// restriction is the cheapest way to rebalance from no shares): with
+// f = rho max(Zu, Zd) and g(y) = f(y) + Sa y for y >= 0, f(y) + Sb y for
+// y < 0 (Sa, Sb the stock's ask and bid prices at t = 0), the minimum of g is
+// at f's breakpoints or at 0; [lo, hi] is the range of those candidates
+// whose g is within 1e-12 (relative, floor 1) of the smallest.  buf holds
+// 3 cap + 1 numbers.  false when f has more than cap points.
+template <typename T>
+BTD bool root_hedge(const View<T> &Zu, const View<T> &Zd, const T &rho, double Sa, double Sb, T *buf, int cap,
+                    double *lo, double *hi)
+{
+    Arr<T> W;
+    W.x = buf;
+    W.v = buf + cap;
+    W.s = buf + 2 * (int64_t)cap;
+    W.st = 1;
+    W.cap = cap;
+    int m = merge<OPMAX, T>(Zu, Zd, W);
+    if (m < 0) return false;
+    m = scale(W, m, rho);
+    const View<T> f = W.view(m);
+    double gmin = __builtin_huge_val();
+    for (int pass = 0; pass < 2; pass++) {
+        bool first = true;
+        for (int j = 0; j <= m; j++) {
+            const double y = j < m ? val(f.X(j)) : 0.0;
+            const double g = val(eval(f, mk<T>(y))) + (y >= 0.0 ? Sa * y : Sb * y);
+            if (pass == 0) {
+                gmin = g < gmin ? g : gmin;
+            } else if (g <= gmin + 1e-12 * fmax(1.0, fabs(gmin))) {
+                if (first || y < *lo) *lo = y;
+                if (first || y > *hi) *hi = y;
+                first = false;
+            }
+        }
+    }
+    return true;
+}
+
 // One node of the seller's (SIDE 0) or buyer's (SIDE 1) recursion,
 // Section 3: W = max(z_up, z_down); F = rho W; V = F with slopes restricted
 // to [a, b] = [-(1+k_t) S, -(1-k_t) S] (CLIP for the convex seller, ENV for

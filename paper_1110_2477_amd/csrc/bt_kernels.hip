@@ -95,6 +95,7 @@ struct KArgs {
     const int *p0_sched;
     const int *p0_count;    // number of options in p0_sched (device memory)
     bt_grad *grad;          // Greeks output (dual-number launches only)
+    bt_hedge *hedge;        // holdings at t = 0 (or nullptr)
     double *arena;          // temporaries of big nodes that outgrow a wave's pool slice
     int64_t arena_cap[2];   // doubles of the seller's (0) and the buyer's (1) arena
     int64_t arena_base[2];  // their offsets in `arena` (the buyer's follows the seller's)
@@ -407,6 +408,21 @@ __device__ __forceinline__ void band_task(const KArgs &A, int launch, int item, 
                     offout[c0 + tid] = (int)(base + offn[tid]);
                     cntout[c0 + tid] = cntn[tid];
                 }
+                if (t == 0 && tid == 0 && A.hedge) {
+                    // the hedge from the root's children, in the (now idle)
+                    // pool of this workgroup
+                    const View<T> Zd0 = record_view(Lc, offc[0], cntc[0]);
+                    const View<T> Zu0 = record_view(Lc, offc[1], cntc[1]);
+                    const T S0 = Stab[-jlo];   // column 0 at t = 0
+                    const T one = mk<T>(1.0);
+                    const int hcap = (int)std::min<int64_t>((A.pool / NT - 1) / 3, INT32_MAX);
+                    double lo = __builtin_nan(""), hi = __builtin_nan("");
+                    if (!root_hedge<T>(Zu0, Zd0, in.rho, val((one + kt) * S0), val((one - kt) * S0), (T *)pool,
+                                       hcap, &lo, &hi))
+                        lo = hi = __builtin_nan("");
+                    if (SIDE == 0) { A.hedge[I.opt].ask_lo = lo; A.hedge[I.opt].ask_hi = hi; }
+                    else { A.hedge[I.opt].bid_lo = lo; A.hedge[I.opt].bid_hi = hi; }
+                }
                 if (t == 0 && tid == 0) {
                     const T root = eval(record_view(Ln, offn[0], cntn[0]), mk<T>(0.0));
                     const T price = SIDE == 0 ? root : -root;
@@ -562,6 +578,11 @@ __global__ void bt_reset_kernel(KArgs A, int64_t n_fill)
             g.ask.dS0 = g.ask.dsigma = g.ask.dR = g.ask.dk = nan;
             g.bid = g.ask;
             A.grad[k] = g;
+        }
+        if (A.hedge) {
+            bt_hedge h;
+            h.ask_lo = h.ask_hi = h.bid_lo = h.bid_hi = nan;
+            A.hedge[k] = h;
         }
     }
     for (int64_t k = i; k < 2 * (int64_t)A.nbands_max; k += stride) {
@@ -1105,6 +1126,11 @@ __global__ void bt_finalize_kernel(KArgs A)
             g.ask.dS0 = g.ask.dsigma = g.ask.dR = g.ask.dk = nan;
             g.bid = g.ask;
             A.grad[k] = g;
+        }
+        if (A.hedge) {
+            bt_hedge h;
+            h.ask_lo = h.ask_hi = h.bid_lo = h.bid_hi = nan;
+            A.hedge[k] = h;
         }
     }
 }
@@ -1831,12 +1857,13 @@ constexpr int NEV = 7;
 
 template <typename T>
 int launch_all(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream, const bt_params *d_params = nullptr,
-               int n_call = 0, int max_N_call = 0)
+               int n_call = 0, int max_N_call = 0, bt_hedge *d_hedge = nullptr)
 {
     hipStream_t s = (hipStream_t)stream;
     KArgs a = book->args;
     a.out = d_out;
     a.grad = d_grad;
+    a.hedge = d_hedge;
     int64_t n_fill = book->n_fill;
     int n_opts = book->n;
     if (book->device_plan) {
@@ -2301,6 +2328,12 @@ int bt_book_price(bt_book *book, bt_result *d_out, void *stream)
 {
     if (!book || !d_out) return BT_EINVAL;
     return launch<double>(book, d_out, nullptr, stream);
+}
+
+int bt_book_price_hedge(bt_book *book, bt_result *d_out, bt_hedge *d_hedge, void *stream)
+{
+    if (!book || !d_out || !d_hedge || book->device_plan) return BT_EINVAL;
+    return launch_all<double>(book, d_out, nullptr, stream, nullptr, 0, 0, d_hedge);
 }
 
 int bt_book_price_grad(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream)

@@ -32,6 +32,8 @@ assert RESULT_DTYPE.itemsize == 56
 GRAD_DTYPE = np.dtype([(f"{side}_{g}", "<f8") for side in ("ask", "bid")
                        for g in ("dS0", "dsigma", "dR", "dk")])
 assert GRAD_DTYPE.itemsize == 64
+# Layout of bt_hedge (32 bytes).
+HEDGE_DTYPE = np.dtype([("ask_lo", "<f8"), ("ask_hi", "<f8"), ("bid_lo", "<f8"), ("bid_hi", "<f8")])
 
 
 def book(rows):
