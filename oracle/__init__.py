@@ -44,6 +44,9 @@ def _load():
                                               ctypes.c_int, _dp, _i64p, _dp]
     lib.oracle_hedge_v.restype = ctypes.c_int
     lib.oracle_hedge_v.argtypes = [ctypes.c_double] * 7 + [ctypes.c_int, ctypes.c_int, ctypes.c_uint, _dp]
+    lib.oracle_exercise_v.restype = ctypes.c_int
+    lib.oracle_exercise_v.argtypes = [ctypes.c_double] * 7 + [ctypes.c_int, ctypes.c_int, ctypes.c_uint,
+                                                              ctypes.c_void_p]
     lib.oracle_flops_v.restype = ctypes.c_uint64
     lib.oracle_flops_v.argtypes = []
     lib.oracle_model_v.restype = ctypes.c_int
@@ -110,6 +113,25 @@ def hedge(S0, K, R, sigma, T, k, N, payoff=PUT, K2=0.0, flags=0):
 def hedge_params(p):
     return hedge(p["S0"], p["K"], p["R"], p["sigma"], p["T"], p["k"], int(p["N"]), payoff=int(p["payoff"]),
                  K2=p["K2"], flags=int(p["flags"]))
+
+
+def exercise(S0, K, R, sigma, T, k, N, payoff=PUT, K2=0.0, flags=0):
+    """The exercise maps of the seller and the buyer: a uint8 array of shape
+    (2, (N+1)(N+2)/2), node (t, c) at t(t+1)/2 + c, 1 where exercise attains
+    the party's expense at zero stock holding."""
+    lib = _load()
+    P = (int(N) + 1) * (int(N) + 2) // 2
+    out = np.zeros((2, P), dtype=np.uint8)
+    rc = lib.oracle_exercise_v(float(S0), float(K), float(K2), float(R), float(sigma), float(T), float(k),
+                               int(N), int(payoff), int(flags), out.ctypes.data_as(ctypes.c_void_p))
+    if rc != 0:
+        raise OracleError("invalid option parameters")
+    return out
+
+
+def exercise_params(p):
+    return exercise(p["S0"], p["K"], p["R"], p["sigma"], p["T"], p["k"], int(p["N"]), payoff=int(p["payoff"]),
+                    K2=p["K2"], flags=int(p["flags"]))
 
 
 def flops():

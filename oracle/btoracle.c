@@ -40,6 +40,10 @@
  *   crr_price                k = 0 ask = bid = CRR; 13.906
  *   root_hedge               the superhedging LP's root holding; the CRR
  *                            delta at k = 0 (test_oracle_hedge.py)
+ *   exercise map             the exact-rational recursion's u_t(0) against
+ *                            v_t(0) away from ties; the zero-cost stopping
+ *                            region at k = 0; no exercise before N for the
+ *                            European variant (test_oracle_exercise.py)
  *   side_price               every test above; cost at t = 0 and the
  *                            European variant against their LPs and
  *                            enumerations; level N+1 against the one-step
@@ -629,7 +633,14 @@ static void root_hedge(const pwl *f, num Sa, num Sb, double *lo, double *hi)
     }
 }
 
-static int side_price_h(const model *md, int side, num *root, int64_t *bp_total, int *bp_max, double *hedge)
+/* The exercise map of one party (exmap, (N+1)(N+2)/2 bytes, node (t, c) at
+ * t(t+1)/2 + c): 1 where exercise attains the party's expense at zero stock
+ * holding -- the seller's z_t is max(u_t, v_t), so u_t(0) >= v_t(0); the
+ * buyer's is min(u_t, v_t), so u_t(0) <= v_t(0), both evaluated by EVAL --
+ * and 0 elsewhere, and at every t < N of the European variant, where there
+ * is no exercise (Section 3). */
+static int side_price_h(const model *md, int side, num *root, int64_t *bp_total, int *bp_max, double *hedge,
+                        unsigned char *exmap)
 {
     int N = md->N;
     pwl *cur = (pwl *)calloc(N + 2, sizeof(pwl));
@@ -663,6 +674,14 @@ static int side_price_h(const model *md, int side, num *root, int64_t *bp_total,
                 else pwl_vee(&U, nneg(ze), nneg(xi), a, b);
                 pwl_merge(&U, &V, side == 0 ? OP_MAX : OP_MIN, &nxt[c]);
             }
+            if (exmap) {
+                unsigned char e = 0;
+                if (!(euro && t < N)) {
+                    double v0 = pwl_eval(&V, nc(0.0)).v, u0 = pwl_eval(&U, nc(0.0)).v;
+                    e = side == 0 ? (u0 >= v0) : (u0 <= v0);
+                }
+                exmap[(int64_t)t * (t + 1) / 2 + c] = e;
+            }
             int bp = pwl_bp(&nxt[c]);
             tot += bp;
             if (bp > mx) mx = bp;
@@ -680,7 +699,7 @@ static int side_price_h(const model *md, int side, num *root, int64_t *bp_total,
 
 static int side_price(const model *md, int side, num *root, int64_t *bp_total, int *bp_max)
 {
-    return side_price_h(md, side, root, bp_total, bp_max, NULL);
+    return side_price_h(md, side, root, bp_total, bp_max, NULL, NULL);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -723,7 +742,24 @@ int API(oracle_hedge)(double S0, double K, double K2, double R, double sigma, do
     if (model_init(&md, S0, K, K2, R, sigma, T, k, N, pay, flags) != 0) return -1;
     for (int side = 0; side < 2; side++) {
         num root; int64_t tot; int mx;
-        side_price_h(&md, side, &root, &tot, &mx, out + 2 * side);
+        side_price_h(&md, side, &root, &tot, &mx, out + 2 * side, NULL);
+    }
+    free(md.S);
+    return 0;
+}
+
+/* The exercise maps of both parties (side_price_h): map[0 .. P-1] the
+ * seller's, map[P .. 2P-1] the buyer's, P = (N+1)(N+2)/2.  Returns 0, or -1
+ * for invalid parameters. */
+int API(oracle_exercise)(double S0, double K, double K2, double R, double sigma, double T, double k,
+                         int N, int pay, unsigned flags, unsigned char *map)
+{
+    model md;
+    if (model_init(&md, S0, K, K2, R, sigma, T, k, N, pay, flags) != 0) return -1;
+    const int64_t P = (int64_t)(N + 1) * (N + 2) / 2;
+    for (int side = 0; side < 2; side++) {
+        num root; int64_t tot; int mx;
+        side_price_h(&md, side, &root, &tot, &mx, NULL, map + side * P);
     }
     free(md.S);
     return 0;

@@ -166,6 +166,38 @@ def crr_values(S0, K, R, sigma, T, N, payoff=PUT, K2=0.0, level=1):
     return V, [S(level, c) for c in range(level + 1)]
 
 
+def crr_exercise(S0, K, R, sigma, T, N, payoff=PUT, K2=0.0, flags=0):
+    """The zero-cost stopping region of the tree with its extra level N+1 of
+    payoff (0, 0) (Section 3 and Section 4.1): exercise at (t, c) is optimal
+    when xi + zeta S >= the continuation value, which is 0 at t = N (the
+    extra level) and rho (p V_t+1(c+1) + (1-p) V_t+1(c)) before, with
+    V = max(xi + zeta S, continuation).  European: no exercise before N.
+    Returns (flags, margins) as arrays in node order t(t+1)/2 + c; margin =
+    exercise value minus continuation."""
+    u, r = _tree(S0, sigma, R, T, N)
+    d = 1.0 / u
+    p = (r - d) / (u - d)
+    euro = bool(flags & EUROPEAN)
+    P = (N + 1) * (N + 2) // 2
+    flg = np.zeros(P, dtype=np.uint8)
+    mrg = np.zeros(P)
+    S = lambda t, c: S0 * u ** (2 * c - t)
+    ex = lambda t, c: float(sum(np.multiply(_payoff(payoff, S(t, c), K, K2), (1.0, S(t, c)))))
+    V = None
+    for t in range(N, -1, -1):
+        Vt = []
+        for c in range(t + 1):
+            cont = 0.0 if t == N else (p * V[c + 1] + (1 - p) * V[c]) / r
+            e = ex(t, c)
+            allowed = not (euro and t < N)
+            i = t * (t + 1) // 2 + c
+            flg[i] = 1 if (allowed and e >= cont) else 0
+            mrg[i] = e - cont
+            Vt.append(max(e, cont) if allowed else cont)
+        V = Vt
+    return flg, mrg
+
+
 def _stopping_times(N, flags=0):
     """All stopping times of the path tree with values in 0..N+1, each as the
     set of path-tree node indices at which the buyer exercises (N+1 means the

@@ -180,14 +180,17 @@ def _node_constants(S, kt, pay, K, K2, rounded):
     return Fraction(a), Fraction(b), Fraction(xi), Fraction(ze)
 
 
-def side_price(stock, rho, k, N, pay, K, K2, side, flags=0, rounded=True):
+def side_price(stock, rho, k, N, pay, K, K2, side, flags=0, rounded=True, exmap=None):
     """Exact recursion of one party (0 seller, 1 buyer) over levels N+1..0.
     stock(j) = S0 u^j as a Fraction.  rounded: the node constants a, b, xi,
     zeta (and the slopes of level N+1) are the binary64 values of their
     formulas, as in the C oracle, so that only the recursion's own
     operations (maximum, discount, restriction, exercise) are exact.
     Returns (root value z_0(0) as a Fraction, total genuine kinks over levels
-    0..N, largest count)."""
+    0..N, largest count).  exmap (a dict, optional) receives for every node
+    (t, c) at which exercise is allowed the pair (u_t(0), v_t(0)): the
+    party's expense at zero stock holding if it exercises there, and if it
+    goes on."""
     cur = []
     for c in range(N + 2):
         a, b, _, _ = _node_constants(stock(2 * c - (N + 1)), k, pay, K, K2, rounded)
@@ -205,10 +208,10 @@ def side_price(stock, rho, k, N, pay, K, K2, side, flags=0, rounded=True):
             if (flags & EUROPEAN) and t < N:
                 z = v
             else:
-                if side == 0:
-                    z = envelope([vee(ze, xi, a, b), v], max)
-                else:
-                    z = envelope([vee(-ze, -xi, a, b), v], min)
+                u = vee(ze, xi, a, b) if side == 0 else vee(-ze, -xi, a, b)
+                z = envelope([u, v], max if side == 0 else min)
+                if exmap is not None:
+                    exmap[(t, c)] = (u(Fraction(0)), v(Fraction(0)))
             n = z.kinks()
             tot += n
             mx = max(mx, n)
