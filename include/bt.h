@@ -315,6 +315,23 @@ int bt_price_batch_static(const bt_params *d_params, int32_t n, int32_t max_N, b
  * replayed from a graph (BT_TUNE_GRAPH does not apply). */
 int bt_book_price_hedge(bt_book *book, bt_result *d_out, bt_hedge *d_hedge, void *stream);
 
+/* As bt_book_price, and the exercise maps of both parties into d_map
+ * (device memory, caller-owned): for every node (t, c), t = 0..N, one byte,
+ * 1 where exercise attains the party's expense at zero stock holding and 0
+ * elsewhere (Section 3: the seller's z_t is max(u_t, v_t), so 1 when
+ * u_t(0) >= v_t(0); the buyer's is min(u_t, v_t), so 1 when u_t(0) <=
+ * v_t(0); no exercise before N in the European variant).  At k = 0 both
+ * maps are the zero-cost stopping region {xi + zeta S >= continuation}.
+ * Layout, in book order: option i takes 2 P_i bytes, P_i = (N_i + 1)(N_i +
+ * 2) / 2 (0 when N_i is outside 1..BT_MAX_N), the seller's plane then the buyer's,
+ * node (t, c) at t (t + 1) / 2 + c of a plane; option i starts at the sum
+ * of 2 P_j over j < i.  The planes of an option whose status is not BT_OK
+ * are set to 0xff.  The first call allocates n + 1 offsets (8 bytes each)
+ * kept with the book.  Not replayed from a graph; bt_book_resolve_overflow
+ * does not write maps (price such options in a book of their own with a
+ * larger level_factor). */
+int bt_book_price_exercise(bt_book *book, bt_result *d_out, uint8_t *d_map, void *stream);
+
 /* Completes a pricing call whose options overflowed the book's buffers
  * (status BT_EOVERFLOW: a tree whose band levels, private levels or
  * big-node temporaries outgrew what the book sized for them): waits for

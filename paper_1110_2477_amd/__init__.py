@@ -23,7 +23,7 @@ EUROPEAN, COST_AT_T0 = 1, 2
 
 # Function names declared in include/bt.h.
 ABI_FUNCTIONS = ("bt_autotune", "bt_book_create", "bt_book_info", "bt_book_price", "bt_book_price_grad",
-                 "bt_book_price_hedge",
+                 "bt_book_price_hedge", "bt_book_price_exercise",
                  "bt_book_resolve_overflow", "bt_book_timings", "bt_book_destroy", "bt_price", "bt_shutdown",
                  "bt_price_batch", "bt_price_grad_batch", "bt_price_adjoint_batch", "bt_price_batch_static",
                  "bt_model_constants",
@@ -77,6 +77,7 @@ def lib():
     L.bt_book_price.argtypes = [vp, vp, vp]
     L.bt_book_price_grad.argtypes = [vp, vp, vp, vp]
     L.bt_book_price_hedge.argtypes = [vp, vp, vp, vp]
+    L.bt_book_price_exercise.argtypes = [vp, vp, vp, vp]
     L.bt_book_timings.argtypes = [vp, dp, ctypes.POINTER(i32)]
     L.bt_book_resolve_overflow.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i32)]
     L.bt_book_destroy.argtypes = [vp]
@@ -94,7 +95,7 @@ def lib():
     L.bt_version.argtypes = []
     L.bt_last_hip_error.argtypes = []
     for f in ("bt_autotune", "bt_book_create", "bt_book_info", "bt_book_price", "bt_book_price_grad",
-              "bt_book_price_hedge", "bt_book_timings", "bt_book_resolve_overflow",
+              "bt_book_price_hedge", "bt_book_price_exercise", "bt_book_timings", "bt_book_resolve_overflow",
               "bt_price", "bt_shutdown", "bt_model_constants", "bt_version", "bt_last_hip_error",
               "bt_price_batch", "bt_price_grad_batch", "bt_price_batch_static", "bt_price_adjoint_batch"):
         getattr(L, f).restype = ctypes.c_int
@@ -257,6 +258,7 @@ def bt_price_batch_static(d_params_ptr, n, max_N, d_out_ptr, stream=None):
 
 BT_STATIC_MAX_OPTIONS = 64
 BT_STATIC_MAX_N = 1024
+BT_MAX_N = 65536
 
 
 def params_tensor(params, device="cuda"):
@@ -403,6 +405,35 @@ class Book:
         import torch
         torch.cuda.synchronize()
         return np.frombuffer(self.hedge.cpu().numpy().tobytes(), dtype=HEDGE_DTYPE).copy()
+
+    def exercise_offsets(self):
+        """Byte offset of each option's exercise maps (n + 1 entries; option
+        i's seller plane at off[i], its buyer plane at (off[i] + off[i+1]) / 2)."""
+        P = np.zeros(self.n + 1, dtype=np.int64)
+        for i, p in enumerate(self.params):
+            N = int(p["N"])
+            P[i + 1] = (N + 1) * (N + 2) if 1 <= N <= BT_MAX_N else 0
+        return np.cumsum(P)
+
+    def price_exercise(self, stream=None):
+        """Prices the book and writes the exercise maps of both parties (see
+        exercise_maps())."""
+        import torch
+        off = self.exercise_offsets()
+        if getattr(self, "exmap", None) is None or self.exmap.numel() != max(1, int(off[-1])):
+            self.exmap = torch.empty(max(1, int(off[-1])), dtype=torch.uint8, device="cuda")
+        _check(lib().bt_book_price_exercise(self.handle, ctypes.c_void_p(self.out.data_ptr()),
+                                            ctypes.c_void_p(self.exmap.data_ptr()), ctypes.c_void_p(_stream_ptr(stream))),
+               "bt_book_price_exercise")
+        return self.out, self.exmap
+
+    def exercise_maps(self, i):
+        """Option i's maps as a (2, (N+1)(N+2)/2) uint8 array: row 0 the
+        seller's, row 1 the buyer's, node (t, c) at t(t+1)/2 + c."""
+        import torch
+        torch.cuda.synchronize()
+        off = self.exercise_offsets()
+        return self.exmap[int(off[i]):int(off[i + 1])].cpu().numpy().reshape(2, -1)
 
     def timings(self):
         return bt_book_timings(self.handle)

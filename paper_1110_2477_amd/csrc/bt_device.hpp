@@ -174,6 +174,22 @@ BTD bool root_hedge(const View<T> &Zu, const View<T> &Zd, const T &rho, double S
     return true;
 }
 
+// Whether exercise attains the party's expense at zero stock holding
+// (Section 3): the seller's z_t is max(u_t, v_t), so 1 when u_t(0) >=
+// v_t(0); the buyer's is min(u_t, v_t), so 1 when u_t(0) <= v_t(0).  u_t is
+// the kink at zeta (seller) or -zeta (buyer) with value xi or -xi and slopes
+// a, b; both values are taken by EVAL.
+template <int SIDE, typename T>
+BTD int exercise_flag(const View<T> &V, const T &xi, const T &zeta, const T &a, const T &b)
+{
+    const T x0 = SIDE == 0 ? zeta : -zeta;
+    const T u0 = SIDE == 0 ? xi : -xi;
+    const T y = mk<T>(0.0);
+    const double u = val(u0 + (val(x0) <= 0.0 ? b : a) * (y - x0));
+    const double v = val(eval(V, y));
+    return SIDE == 0 ? (u >= v ? 1 : 0) : (u <= v ? 1 : 0);
+}
+
 // One node of the seller's (SIDE 0) or buyer's (SIDE 1) recursion,
 // Section 3: W = max(z_up, z_down); F = rho W; V = F with slopes restricted
 // to [a, b] = [-(1+k_t) S, -(1-k_t) S] (CLIP for the convex seller, ENV for
@@ -182,11 +198,13 @@ BTD bool root_hedge(const View<T> &Zu, const View<T> &Zd, const T &rho, double S
 // seller, min(U, V) for the buyer, or Z = V when exercise is not allowed at
 // t (European variant).  Temporaries live in `base` with element stride
 // `st` and the capacities of `cp`.  Returns the point count of Z (whose
-// storage is set in *zout) or -1 when a capacity was exceeded.
+// storage is set in *zout) or -1 when a capacity was exceeded.  exf
+// (binary64 only, optional) receives exercise_flag, 0 where exercise is not
+// allowed.
 template <int SIDE, typename T>
 BTD int node_update(const View<T> &Zu, const View<T> &Zd, const T &S, const T &kt, const T &rho,
                     const T &xi, const T &zeta, bool exercise, T *base, int st,
-                    const Caps &cp, Arr<T> *zout)
+                    const Caps &cp, Arr<T> *zout, int *exf = nullptr)
 {
     const T one = mk<T>(1.0);
     const T a = -((one + kt) * S);
@@ -225,6 +243,9 @@ BTD int node_update(const View<T> &Zu, const View<T> &Zd, const T &S, const T &k
             mv = merge<OPMIN, T>(A.view(ma), B.view(mb), V);
             if (mv < 0) return -1;
         }
+    }
+    if constexpr (sizeof(T) == sizeof(double)) {
+        if (exf) *exf = exercise ? exercise_flag<SIDE, T>(V.view(mv), xi, zeta, a, b) : 0;
     }
     if (!exercise) { *zout = V; return mv; }
     Arr<T> U = stage(base, st, cp.oU, 1);

@@ -96,6 +96,8 @@ struct KArgs {
     const int *p0_count;    // number of options in p0_sched (device memory)
     bt_grad *grad;          // Greeks output (dual-number launches only)
     bt_hedge *hedge;        // holdings at t = 0 (or nullptr)
+    unsigned char *exmap;   // exercise maps (or nullptr): option i's from exoff[i]
+    const int64_t *exoff;   // n + 1 byte offsets
     double *arena;          // temporaries of big nodes that outgrow a wave's pool slice
     int64_t arena_cap[2];   // doubles of the seller's (0) and the buyer's (1) arena
     int64_t arena_base[2];  // their offsets in `arena` (the buyer's follows the seller's)
@@ -203,7 +205,7 @@ __global__ void bt_init_kernel(KArgs A)
 // band that launch runs.
 // s_chunk / s_chunk_cap: each wave's arena chunk (kept for the whole launch
 // and reused by the wave's later big nodes; grown when a node needs more).
-template <int SIDE, typename T>
+template <int SIDE, typename T, bool EX = false>
 __device__ __forceinline__ void band_task(const KArgs &A, int launch, int item, int blk, int64_t *sh, int *sflag,
                           double **s_chunk, int64_t *s_chunk_cap, T *s_win)
 {
@@ -285,9 +287,17 @@ __device__ __forceinline__ void band_task(const KArgs &A, int launch, int item, 
         Arr<T> Z{};
         int mz = 0;
         bool big = act && M > SMALL_CAP;
+        // exercise map (EX): node (t, c) of the party's plane
+        int64_t exi = 0;
+        if constexpr (EX) exi = A.exoff[I.opt] + (int64_t)SIDE * ((int64_t)(N + 1) * (N + 2) / 2) + (int64_t)t * (t + 1) / 2;
         if (act && !big) {
-            mz = node_update<SIDE, T>(Zu, Zd, S, kt, in.rho, xi, ze, exercise, small + tid, WG, sc, &Z);
+            int exf = 0;
+            mz = node_update<SIDE, T>(Zu, Zd, S, kt, in.rho, xi, ze, exercise, small + tid, WG, sc, &Z,
+                                      EX ? &exf : nullptr);
             big = mz < 0;
+            if constexpr (EX) {
+                if (!big && owned) A.exmap[exi + c] = (unsigned char)exf;
+            }
         }
         // one scan for the record sizes (low 40 bits) and the big-node count
         const int64_t sz = (act && !big) ? 3 * (int64_t)mz + 1 : 0;
@@ -329,7 +339,7 @@ __device__ __forceinline__ void band_task(const KArgs &A, int launch, int item, 
                 // a node that outgrows its slice is redone in the arena
                 const int64_t need = big_need(Zu2.m + Zd2.m, NT);
                 Arr<T> Zb;
-                int mzb = -1;
+                int mzb = -1, exf2 = 0;
 #pragma unroll 1
                 for (int attempt = need > slice ? 1 : 0; attempt < 2 && mzb < 0; attempt++) {
                     double *tb = pool + w * slice;
@@ -351,7 +361,7 @@ __device__ __forceinline__ void band_task(const KArgs &A, int launch, int item, 
                     }
                     WaveTmp WT{tb, tcap, 0};
                     mzb = wave_node_update<SIDE, T>(Zu2, Zd2, S2, kt, in.rho, xi2, ze2, exercise, WT,
-                                                    s_win + w * WaveLds<T>::NUMS, &Zb);
+                                                    s_win + w * WaveLds<T>::NUMS, &Zb, EX ? &exf2 : nullptr);
                 }
                 if (mzb < 0) {
                     if (lane == 0) *sflag = 1;
@@ -375,6 +385,9 @@ __device__ __forceinline__ void band_task(const KArgs &A, int launch, int item, 
                     dst[0] = Zb.S(0);
                     offn[ii] = (int)pos;
                     cntn[ii] = mzb;
+                    if constexpr (EX) {
+                        if (cc < c1 || last) A.exmap[exi + cc] = (unsigned char)exf2;
+                    }
                     if (cc < c1 || last) {
                         const int bp = (mzb == 1 && val(Zb.S(0)) == val(Zb.S(1))) ? 0 : mzb;
                         bp_sum += bp;
@@ -470,7 +483,7 @@ __device__ __forceinline__ void band_task(const KArgs &A, int launch, int item, 
 
 // Launch r of one party: the bands of its tree sides that this launch runs
 // (see the file header), on persistent workgroups.
-template <int SIDE, typename T>
+template <int SIDE, typename T, bool EX = false>
 __global__ __launch_bounds__(WG) void bt_band_kernel(KArgs A, int r)
 {
     __shared__ int s_task, s_skip;
@@ -500,7 +513,7 @@ __global__ __launch_bounds__(WG) void bt_band_kernel(KArgs A, int r)
         if (q >= hi) break;
         if (skip) continue;
         const Task tk = A.tasks[q];
-        band_task<SIDE, T>(A, r, tk.item, tk.block, s_scan, &s_flag, s_chunk, s_chunk_cap, s_win);
+        band_task<SIDE, T, EX>(A, r, tk.item, tk.block, s_scan, &s_flag, s_chunk, s_chunk_cap, s_win);
     }
 }
 
@@ -1109,6 +1122,16 @@ __global__ __launch_bounds__(WG) void bt_adjoint_kernel(AdjArgs A)
     }
 }
 
+// The exercise maps of options whose pricing failed are set to 0xff (one
+// workgroup per option at a time).
+__global__ void bt_exmap_fail_kernel(KArgs A)
+{
+    for (int64_t k = blockIdx.x; k < A.n_opts; k += gridDim.x) {
+        if (A.out[k].status == BT_OK) continue;
+        for (int64_t q = A.exoff[k] + threadIdx.x; q < A.exoff[k + 1]; q += blockDim.x) A.exmap[q] = 0xff;
+    }
+}
+
 // Options whose pricing failed (status other than BT_OK: invalid, or a
 // tree that outgrew its buffers on either side) get no partial result: NaN
 // prices and Greeks, zero breakpoint counts.
@@ -1354,6 +1377,7 @@ struct bt_book {
     int *d_order = nullptr;
     int *d_plan_ints = nullptr;       // valid count, task bounds
     PlanArgs plan{};
+    int64_t *d_exoff = nullptr;       // exercise-map offsets (first bt_book_price_exercise)
 };
 
 namespace {
@@ -1381,6 +1405,8 @@ void book_free(bt_book *b)
                     b->d_keys, b->d_order, b->d_plan_ints};
     for (void *p : ptrs)
         if (p && !b->carved) (void)hipFree(p);
+    if (b->d_exoff) (void)hipFree(b->d_exoff);
+    b->d_exoff = nullptr;
     b->d_keys = nullptr; b->d_order = nullptr; b->d_plan_ints = nullptr;
     b->d_models = nullptr; b->d_items = nullptr; b->d_tasks = nullptr; b->d_task_off = nullptr;
     b->d_ints = nullptr; b->d_fill = nullptr; b->d_lvl = nullptr; b->d_lvli = nullptr;
@@ -1857,13 +1883,15 @@ constexpr int NEV = 7;
 
 template <typename T>
 int launch_all(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream, const bt_params *d_params = nullptr,
-               int n_call = 0, int max_N_call = 0, bt_hedge *d_hedge = nullptr)
+               int n_call = 0, int max_N_call = 0, bt_hedge *d_hedge = nullptr, unsigned char *d_exmap = nullptr)
 {
     hipStream_t s = (hipStream_t)stream;
     KArgs a = book->args;
     a.out = d_out;
     a.grad = d_grad;
     a.hedge = d_hedge;
+    a.exmap = d_exmap;
+    a.exoff = d_exmap ? book->d_exoff : nullptr;
     int64_t n_fill = book->n_fill;
     int n_opts = book->n;
     if (book->device_plan) {
@@ -1919,9 +1947,11 @@ int launch_all(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream, c
     const auto wgs = [&](int r, int side) {
         return book->device_plan ? book->grid : std::min(book->grid, book->ntasks[2 * r + side]);
     };
+    // (with exercise maps: the kernels that also write them)
     for (int r = 0; r < book->nbands_max; r++) {
         if (wgs(r, 1) == 0) continue;
-        hipLaunchKernelGGL((bt_band_kernel<1, T>), dim3(wgs(r, 1)), dim3(WG), 0, s, a, r);
+        if (d_exmap) hipLaunchKernelGGL((bt_band_kernel<1, double, true>), dim3(wgs(r, 1)), dim3(WG), 0, s, a, r);
+        else hipLaunchKernelGGL((bt_band_kernel<1, T>), dim3(wgs(r, 1)), dim3(WG), 0, s, a, r);
         HIPCHK(hipGetLastError());
     }
     if (book->timing) HIPCHK(hipEventRecord(ev[2], s));
@@ -1929,7 +1959,8 @@ int launch_all(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream, c
     if (book->timing) HIPCHK(hipEventRecord(ev[3], s_ask));
     for (int r = 0; r < book->nbands_max; r++) {
         if (wgs(r, 0) == 0) continue;
-        hipLaunchKernelGGL((bt_band_kernel<0, T>), dim3(wgs(r, 0)), dim3(WG), 0, s_ask, a, r);
+        if (d_exmap) hipLaunchKernelGGL((bt_band_kernel<0, double, true>), dim3(wgs(r, 0)), dim3(WG), 0, s_ask, a, r);
+        else hipLaunchKernelGGL((bt_band_kernel<0, T>), dim3(wgs(r, 0)), dim3(WG), 0, s_ask, a, r);
         HIPCHK(hipGetLastError());
     }
     if (book->timing) HIPCHK(hipEventRecord(ev[4], s_ask));
@@ -1948,6 +1979,10 @@ int launch_all(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream, c
     }
     hipLaunchKernelGGL(bt_finalize_kernel, dim3((int)std::min<int64_t>((n_opts + 255) / 256, 1024)), dim3(256), 0, s, a);
     HIPCHK(hipGetLastError());
+    if (d_exmap && n_opts > 0) {
+        hipLaunchKernelGGL(bt_exmap_fail_kernel, dim3(std::min(n_opts, 1024)), dim3(256), 0, s, a);
+        HIPCHK(hipGetLastError());
+    }
     return BT_OK;
 }
 
@@ -2334,6 +2369,28 @@ int bt_book_price_hedge(bt_book *book, bt_result *d_out, bt_hedge *d_hedge, void
 {
     if (!book || !d_out || !d_hedge || book->device_plan) return BT_EINVAL;
     return launch_all<double>(book, d_out, nullptr, stream, nullptr, 0, 0, d_hedge);
+}
+
+int bt_book_price_exercise(bt_book *book, bt_result *d_out, uint8_t *d_map, void *stream)
+{
+    if (!book || !d_out || !d_map || book->device_plan) return BT_EINVAL;
+    if (!book->d_exoff) {
+        // option i's seller plane from off[i], its buyer plane after it
+        std::vector<int64_t> off(book->n + 1, 0);
+        for (int i = 0; i < book->n; i++) {
+            const int64_t N = book->params[i].N;
+            off[i + 1] = off[i] + (N >= 1 && N <= BT_MAX_N ? (N + 1) * (N + 2) : 0);
+        }
+        int64_t *d = nullptr;
+        HIPCHK(hipMalloc(&d, sizeof(int64_t) * off.size()));
+        const hipError_t e = hipMemcpy(d, off.data(), sizeof(int64_t) * off.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(d);
+            HIPCHK(e);
+        }
+        book->d_exoff = d;
+    }
+    return launch_all<double>(book, d_out, nullptr, stream, nullptr, 0, 0, nullptr, d_map);
 }
 
 int bt_book_price_grad(bt_book *book, bt_result *d_out, bt_grad *d_grad, void *stream)

@@ -4,9 +4,11 @@
 // same per-element formulas, so the same bits); only the order in which
 // elements are produced changes.
 //
-// The work goes in tiles of 64 E consecutive elements (E per lane; 4 for
-// double, 1 for the dual numbers of the Greeks), so that a tile's loads are
-// issued together and its latency is paid once per tile:
+// The work goes in tiles of 64 E consecutive elements (E per lane: for
+// CANON, CLIP and the envelope sweeps 4 for double and 1 for the dual
+// numbers of the Greeks (TileE); for MERGE 8 and 2 merged positions
+// (WaveLds)), so that a tile's loads are issued together and its latency is
+// paid once per tile:
 //   - CANON (and SCALE, CLIP, the mirror image taken by ENV, applied on the
 //     fly as accessors of its input) loads a tile into registers, counts the
 //     points each lane keeps, takes an exclusive scan over the lanes and
@@ -1583,10 +1585,11 @@ BTD int wave_env(const Arr<N> &Fa, int m, const N &a, const N &b, const Arr<N> &
 
 // One node update by a whole wave (see node_update).  The result is left in
 // *zout inside T's slice (valid until T is reset).  lds: this wave's
-// WaveLds<N>::NUMS numbers of LDS.
+// WaveLds<N>::NUMS numbers of LDS.  exf: as in node_update.
 template <int SIDE, typename N>
 BTD int wave_node_update(const View<N> &Zu, const View<N> &Zd, const N &S, const N &kt, const N &rho,
-                         const N &xi, const N &zeta, bool exercise, WaveTmp &T, N *lds, Arr<N> *zout)
+                         const N &xi, const N &zeta, bool exercise, WaveTmp &T, N *lds, Arr<N> *zout,
+                         int *exf = nullptr)
 {
     const N one = mk<N>(1.0);
     const N a = -((one + kt) * S);
@@ -1622,6 +1625,9 @@ BTD int wave_node_update(const View<N> &Zu, const View<N> &Zd, const N &S, const
         }
     }
     if (mv < 0) return -1;
+    if constexpr (sizeof(N) == sizeof(double)) {
+        if (exf) *exf = exercise ? exercise_flag<SIDE, N>(V.view(mv), xi, zeta, a, b) : 0;
+    }
     if (!exercise) { *zout = V; return mv; }
     Arr<N> U, Z;
     if (!T.arr<N>(1, &U) || !T.arr<N>(2 * mv + 3, &Z)) return -1;
