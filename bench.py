@@ -101,16 +101,22 @@ def compare_with_oracle(gpu, ref):
 
 
 def kernel_source_digest():
-    """SHA-256 over the HIP sources of the kernels (the counters below are
-    valid only for the kernels they were taken on)."""
+    """SHA-256 over the HIP sources of the kernels with comments and blank
+    space removed (the counters below are valid only for the code they were
+    taken on; a change to a comment does not change the code)."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     src = os.path.join(ROOT, "paper_1110_2477_amd", "csrc")
     for name in sorted(os.listdir(src)):
         if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(src, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+            with open(os.path.join(src, name), encoding="utf-8") as f:
+                text = f.read()
+            text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", " ", text)
+            text = " ".join(text.split())
+            h.update(name.encode() + b"\0" + text.encode())
     return h.hexdigest()
 
 
@@ -232,6 +238,7 @@ def stress_leg(bt, W, np, torch, n_batches):
     res = {}
     stress = W.stress_book(16384, seed=5)
     pick = np.random.default_rng(66).choice(2048, 48, replace=False)
+    log("stress: autotuning on 48 options of the first batch")
     t0 = time.perf_counter()
     best, _ = bt.bt_autotune(stress[:2048][np.sort(pick)], reps=1)
     tune = {k: best[k] for k in ("band_levels", "wgs_per_cu")}
@@ -261,6 +268,7 @@ def stress_leg(bt, W, np, torch, n_batches):
     # a call of the same size on short trees builds the workspace
     cheap = g.copy()
     cheap["N"] = 64
+    log("stress: Greeks of 256 options")
     bt.price_batch(bt.params_tensor(cheap), max_N=8192, grad=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -272,6 +280,7 @@ def stress_leg(bt, W, np, torch, n_batches):
                                    ok=bool(np.all(r["status"] == 0)), entry="bt_price_grad_batch",
                                    subset="options 0..255 of the 16384")
     bt.bt_shutdown()
+    log(f"stress: Greeks of 256 options {dt * 1e3:.0f} ms")
     lp = W.long_put()
     for greeks in (False, True):
         log(f"put N=20000, greeks={greeks}")
@@ -477,12 +486,15 @@ def main():
             (ask.sum() + bid.sum()).backward()
             return ask, bid
 
-        fwd_bwd()   # builds the workspace
+        log("greeks book: first call (builds the workspace)")
+        fwd_bwd()
         torch.cuda.synchronize()
+        log("greeks book: timed call")
         t0 = time.perf_counter()
         ask, bid = fwd_bwd()
         torch.cuda.synchronize()
         dt_g = time.perf_counter() - t0
+        log(f"greeks book: {dt_g * 1e3:.1f} ms")
         ok = bool(torch.isfinite(ask).all().item() and torch.isfinite(bid).all().item())
         bt.price_batch(spec, max_N=1500)
         torch.cuda.synchronize()
@@ -492,12 +504,16 @@ def main():
         dt_p = time.perf_counter() - t0
         bt.bt_shutdown()
         # the same Greeks by the checkpointed reverse sweep
-        # (bt_price_adjoint_batch) on the first 64 options, against forward
-        # mode on the same options; device memory of each workspace from
-        # the free-memory difference around its first call
-        sub = bt.params_tensor(gb[:64])
+        # (bt_price_adjoint_batch) against forward mode on the first 64 puts
+        # of the book: the reverse sweep recomputes every node with a
+        # recording tape, so books whose nodes hold many points (calls and
+        # spreads with costs) take it seconds per option.  Device memory of
+        # each workspace from the free-memory difference around its first
+        # call.
+        sub = bt.params_tensor(gb[gb["payoff"] == W.PUT][:64])
         fa = {}
         for mode in ("forward", "adjoint"):
+            log(f"greeks {mode} mode on 64 puts")
             torch.cuda.synchronize()
             free0, _ = torch.cuda.mem_get_info()
             bt.price_batch(sub, max_N=1500, grad=True, mode=mode)
@@ -512,7 +528,7 @@ def main():
         ga, gf = fa["adjoint"]["grads"], fa["forward"]["grads"]
         diff = max(float(np.max(np.abs(ga[k] - gf[k]) / np.maximum(1.0, np.abs(gf[k])))) for k in ga.dtype.names)
         extra["greeks_adjoint_vs_forward_64"] = dict(
-            sample="options 0..63 of the Greeks book (N 500..1500)", max_rel_diff=diff,
+            sample="the first 64 puts of the Greeks book (N 500..1500)", max_rel_diff=diff,
             adjoint=dict(options_per_s=64 / (fa["adjoint"]["ms"] * 1e-3), ms=fa["adjoint"]["ms"],
                          workspace_gib=fa["adjoint"]["workspace_gib"], ok=fa["adjoint"]["ok"],
                          entry="bt_price_adjoint_batch (reverse sweep, sqrt(N) checkpoints)"),
@@ -554,21 +570,24 @@ def main():
     if c:
         f64 = sum(c.get(k, 0.0) for k in ("SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64",
                                            "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_TRANS_F64"))
-        # wave instructions x 64 lanes (an upper bound: masked lanes count)
+        simds = N_CU * 4
+        # a wave64 vector instruction occupies a 16-lane SIMD for 4 cycles;
+        # GRBM_GUI_ACTIVE is summed over the 8 XCDs and SQ_WAVE_CYCLES counts
+        # in units of 4 cycles (both checked on bt_price0_kernel, whose
+        # resident waves are known)
         roof["counters"] = {
             "fp64_valu_wave_insts_per_launch": f64,
             "fp64_valu_lane_ops_frac": f64 * 64 / (ms_launch * 1e-3) / (PEAK_FP64_NONFMA_TFLOPS * 1e12),
             "valu_wave_insts_per_launch": c.get("SQ_INSTS_VALU"),
+            "valu_issue_frac": (c["SQ_INSTS_VALU"] * 4 / (ms_launch * 1e-3 * CLOCK_HZ * simds)
+                                if c.get("SQ_INSTS_VALU") else None),
             "lds_wave_insts_per_launch": c.get("SQ_INSTS_LDS"),
-            "lds_active_frac": (c["SQ_LDS_IDX_ACTIVE"] / (c["GRBM_GUI_ACTIVE"] * N_CU)
-                                if c.get("SQ_LDS_IDX_ACTIVE") and c.get("GRBM_GUI_ACTIVE") else None),
             "lds_bank_conflict_per_access": (c["SQ_LDS_BANK_CONFLICT"] / max(1.0, c["SQ_LDS_IDX_ACTIVE"]
                                                                            - c["SQ_LDS_BANK_CONFLICT"])
                                              if c.get("SQ_LDS_IDX_ACTIVE") else None),
-            "valu_busy_frac": (c["SQ_ACTIVE_INST_VALU"] / (c["GRBM_GUI_ACTIVE"] * N_CU * 4)
-                               if c.get("SQ_ACTIVE_INST_VALU") and c.get("GRBM_GUI_ACTIVE") else None),
-            "mean_waves_per_cu": (c["SQ_WAVE_CYCLES"] / (c["GRBM_GUI_ACTIVE"] * N_CU)
-                                  if c.get("SQ_WAVE_CYCLES") and c.get("GRBM_GUI_ACTIVE") else None),
+            "mean_resident_waves": (4 * c["SQ_WAVE_CYCLES"] / (c["GRBM_GUI_ACTIVE"] / 8)
+                                    if c.get("SQ_WAVE_CYCLES") and c.get("GRBM_GUI_ACTIVE") else None),
+            "wave_slots_at_this_occupancy": simds,
             "source": "profiles/band_kernel_counters_paper_grid.txt"}
     out["roofline"] = roof
 
