@@ -322,8 +322,42 @@ __device__ __forceinline__ void band_task(const KArgs &A, int launch, int item, 
         if (nbig > 0 && !fatal) {
             if (big) sbig[bix] = i;
             if (tid == 0) sloff = (unsigned long long)loff;
+            if (tid < NWAVE) bt_help[tid].state = 0;
             __syncthreads();
             const int w = tid >> 6, lane = tid & 63;
+            // binary64 buyer with at most one big node per wave: a wave
+            // without a node, or with one of the smaller nodes once it is
+            // done, takes parts of the envelope of a larger node (bt_wave.hpp,
+            // SweepHelp).  Ranks by children's points, largest first: with
+            // fewer nodes than waves, idle wave nbig + r helps the node of rank
+            // r; with one node per wave, the wave whose node has rank
+            // NWAVE - 1 - r helps the node of rank r < NWAVE / 2 once its own
+            // node is done.
+            int help = -1, helps = -1;
+            if constexpr (SIDE == 1 && NT == 1) {
+                if ((int)nbig <= NWAVE) {
+                    const auto pts = [&](int b) { return cntc[sbig[b]] + cntc[sbig[b] + 1]; };
+                    const auto rank = [&](int b) {
+                        int r = 0;
+                        for (int o = 0; o < (int)nbig; o++) {
+                            const int po = pts(o), pb = pts(b);
+                            r += (po > pb || (po == pb && o < b)) ? 1 : 0;
+                        }
+                        return r;
+                    };
+                    // (wave b holds node b; the mailbox is the helped wave's)
+                    if ((int)nbig < NWAVE) {
+                        if (w < (int)nbig && (int)nbig + rank(w) < NWAVE) help = w;
+                        for (int b = 0; b < (int)nbig; b++)
+                            if ((int)nbig + rank(b) == w) helps = b;
+                    } else {
+                        const int rw = rank(w);
+                        if (rw < NWAVE / 2) help = w;
+                        for (int b = 0; b < (int)nbig; b++)
+                            if (rw >= NWAVE / 2 && rank(b) == NWAVE - 1 - rw) helps = b;
+                    }
+                }
+            }
             const int64_t slice = A.pool / NWAVE;
             double *chunk = s_chunk[w];
             int64_t chunk_cap = s_chunk_cap[w];
@@ -361,7 +395,7 @@ __device__ __forceinline__ void band_task(const KArgs &A, int launch, int item, 
                     }
                     WaveTmp WT{tb, tcap, 0};
                     mzb = wave_node_update<SIDE, T>(Zu2, Zd2, S2, kt, in.rho, xi2, ze2, exercise, WT,
-                                                    s_win + w * WaveLds<T>::NUMS, &Zb, EX ? &exf2 : nullptr);
+                                                    s_win + w * WaveLds<T>::NUMS, &Zb, EX ? &exf2 : nullptr, help);
                 }
                 if (mzb < 0) {
                     if (lane == 0) *sflag = 1;
@@ -394,6 +428,10 @@ __device__ __forceinline__ void band_task(const KArgs &A, int launch, int item, 
                         bp_max = bp > bp_max ? bp : bp_max;
                     }
                 }
+            }
+            if constexpr (SIDE == 1 && NT == 1) {
+                if (help >= 0) help_post(help, 3);
+                if (helps >= 0) sweep_helper(helps, (double *)(s_win + w * WaveLds<T>::NUMS));
             }
             if (lane == 0) {
                 s_chunk[w] = chunk;

@@ -1287,37 +1287,29 @@ BTD bool env_schedule(const FA &A, const FB &B, int ma, int mb, const int *codes
     return carryA == ma && carryB == mb;
 }
 
-// MERGE(F, G, op) driven by a schedule instead of the merge-path walk (same
-// result as wave_merge); F and G are read from global memory, LDS holds only
-// the staging of the emitted points.
+// Merged positions [r0, r1) of MERGE(F, G, op) driven by a schedule (r0 a
+// multiple of the tile), emitted into out from position `carry`.  psl: the
+// slope arriving at the range's first union point, or NaN when it is not
+// known yet: the first union point is then kept, and *first_rs receives the
+// slope it leaves (NaN when lane 0 of the first tile starts no union point),
+// so that the caller can drop it once the slope arriving there is known.
+// Returns the count after the range or -1 on overflow; *psl_out: the slope
+// leaving the range.
 template <int OP, typename N, typename FF, typename GG>
-BTD int wave_merge_sched(const FF &F, const GG &G, const int *sF, const int *sG, const Arr<N> &out, N *lds)
+BTD int merge_sched_tiles(const FF &F, const GG &G, const int *sF, const int *sG, int Lt, int r0, int r1,
+                          const Arr<N> &out, N *lds, int carry, double psl, double *psl_out, double *first_rs)
 {
     constexpr int E = WaveLds<N>::E;
     constexpr int K = E + 2;
     const BT_GLOBAL int *gF = (const BT_GLOBAL int *)sF;
     const BT_GLOBAL int *gG = (const BT_GLOBAL int *)sG;
     const int tm = NLANES * E;
-    const int mF = F.m, mG = G.m, Lt = mF + mG;
-    if (out.cap < 1) return -1;
-    N P0;
-    int iF0, iG0;
-    {
-        const double xa = val(F.X(0)), xb = val(G.X(0));
-        if (xa < xb) { P0 = F.X(0); iF0 = 1; iG0 = 0; }
-        else if (xb < xa) { P0 = G.X(0); iF0 = 0; iG0 = 1; }
-        else { P0 = F.X(0); iF0 = 1; iG0 = 1; }
-    }
-    const N fF0 = eval_at<N>(F, iF0, P0), fG0 = eval_at<N>(G, iG0, P0);
-    const Slot<N> L = slot_left<OP, N>(F, G, P0, fF0, fG0);
-    const int keepL = (L.hc && val(L.rs) != val(L.crs)) ? 1 : 0;
-    double psl = val(L.hc ? L.crs : L.rs);   // slope arriving at the next tile's first union point
     const int SZ = 2 * E * NLANES;
     N *stg = lds;
-    int carry = keepL;
-    for (int dt = 0; dt < Lt; dt += tm) {
+    if (first_rs) *first_rs = __builtin_nan("");
+    for (int dt = r0; dt < r1; dt += tm) {
         WSYNC();   // the previous tile's reads of the staging are done
-        const int dend = dt + tm < Lt ? dt + tm : Lt;
+        const int dend = dt + tm < r1 ? dt + tm : r1;
         LV<LaneWalk<E>> wk;
         LANES(l) {
             LaneWalk<E> &w = wk(l);
@@ -1353,6 +1345,8 @@ BTD int wave_merge_sched(const FF &F, const GG &G, const int *sF, const int *sG,
                                                    &fst(l), &po, N{});
             pso(l) = po;
         }
+        if (first_rs && dt == r0)
+            *first_rs = from_lane<double>(0, [&](int l) { return fst(l).have ? val(fst(l).rs) : __builtin_nan(""); });
         const double pnext = from_lane<double>(NLANES - 1, [&](int l) { return pso(l); });
         lv_up1(pso, psl);
         LANES(l) {
@@ -1381,16 +1375,66 @@ BTD int wave_merge_sched(const FF &F, const GG &G, const int *sF, const int *sG,
         carry += tot;
         psl = pnext;
     }
+    *psl_out = psl;
+    return carry;
+}
+
+// The left end of a scheduled merge: its first union point P0, the decision
+// there, and the slope arriving at the first tile.
+template <int OP, typename N>
+struct SchedHead {
+    N P0, fF0, fG0;
+    Slot<N> L;
+    int keepL;
+    double psl;
+};
+
+template <int OP, typename N, typename FF, typename GG>
+BTD SchedHead<OP, N> sched_head(const FF &F, const GG &G)
+{
+    SchedHead<OP, N> h;
+    int iF0, iG0;
+    const double xa = val(F.X(0)), xb = val(G.X(0));
+    if (xa < xb) { h.P0 = F.X(0); iF0 = 1; iG0 = 0; }
+    else if (xb < xa) { h.P0 = G.X(0); iF0 = 0; iG0 = 1; }
+    else { h.P0 = F.X(0); iF0 = 1; iG0 = 1; }
+    h.fF0 = eval_at<N>(F, iF0, h.P0);
+    h.fG0 = eval_at<N>(G, iG0, h.P0);
+    h.L = slot_left<OP, N>(F, G, h.P0, h.fF0, h.fG0);
+    h.keepL = (h.L.hc && val(h.L.rs) != val(h.L.crs)) ? 1 : 0;
+    h.psl = val(h.L.hc ? h.L.crs : h.L.rs);
+    return h;
+}
+
+// Completes a scheduled merge whose tiles emitted `carry` points.
+template <int OP, typename N>
+BTD int sched_finish(const SchedHead<OP, N> &h, int carry, const Arr<N> &out)
+{
     if (carry == 0) {
-        LANE0((out.X(0) = L.hc ? L.cy : P0, out.V(0) = L.hc ? L.cv : pick<OP, N>(fF0, fG0),
-               out.S(0) = L.rs, out.S(1) = L.rs));
+        LANE0((out.X(0) = h.L.hc ? h.L.cy : h.P0, out.V(0) = h.L.hc ? h.L.cv : pick<OP, N>(h.fF0, h.fG0),
+               out.S(0) = h.L.rs, out.S(1) = h.L.rs));
         WSYNC();
         return 1;
     }
-    LANE0(out.S(0) = L.rs);
-    if (keepL) LANE0((out.X(0) = L.cy, out.V(0) = L.cv, out.S(1) = L.crs));
+    LANE0(out.S(0) = h.L.rs);
+    if (h.keepL) LANE0((out.X(0) = h.L.cy, out.V(0) = h.L.cv, out.S(1) = h.L.crs));
     WSYNC();
     return carry;
+}
+
+// MERGE(F, G, op) driven by a schedule instead of the merge-path walk (same
+// result as wave_merge); F and G are read from global memory, LDS holds only
+// the staging of the emitted points.
+template <int OP, typename N, typename FF, typename GG>
+BTD int wave_merge_sched(const FF &F, const GG &G, const int *sF, const int *sG, const Arr<N> &out, N *lds)
+{
+    if (out.cap < 1) return -1;
+    const SchedHead<OP, N> h = sched_head<OP, N>(F, G);
+    double pend;
+    const int carry = merge_sched_tiles<OP, N>(F, G, sF, sG, F.m + G.m, 0, F.m + G.m, out, lds, h.keepL, h.psl,
+                                               &pend, nullptr);
+    if (carry < 0) return -1;
+    return sched_finish<OP, N>(h, carry, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -1507,8 +1551,192 @@ BTD int wave_merge_d4(const FF &F, const GG &G, const Arr<D4> &out, D4 *lds, con
 }
 
 // ENV(F, a, b) into out (buyer).
+// A request from the wave that updates a node to another wave of its
+// workgroup that has no node of its own left at the level (binary64, device
+// builds): a part of the envelope's work that the helper runs while the
+// node's own wave runs the rest.  The mailbox lives in LDS; state 0 idle, 1
+// request posted, 4 taken by the helper, 2 done, 3 no more requests (the
+// node is finished).  A posted request that no helper has taken when the
+// node's wave needs its result is taken back (1 -> 0) and run by that wave,
+// so neither side ever waits on a wave that is not working for it.
+struct SweepHelp {
+    int state, kind;             // kind 1: the mirror sweep; 2: the upper half of MERGE_MIN(A, B)
+    int m, st, cap;              // 1: F's points and stride; both: the output's capacity
+    const double *fx, *fv, *fs;  // 1: F
+    double *ox, *ov, *os;        // both: the output
+    int *codes;                  // 1: the sweep's codes
+    double slope;                // 1: the sweep's slope (-b)
+    const double *ax, *av, *as, *rx, *rv, *rs;   // 2: A and RB (unit stride)
+    const int *sF, *sG;          // 2: the schedule
+    int ma, mrb, Lt, D;          // 2: point counts, merged positions, first position of the half
+    int off, line, count;        // results
+    double frs;                  // 2: the slope its first union point leaves
+};
+
+#ifndef BT_HOST_DEBUG
+// One mailbox per wave of a workgroup (indexed by the requesting wave).
+__shared__ SweepHelp bt_help[NWAVE];
+
+__device__ __forceinline__ int help_state(int i)
+{
+    return __hip_atomic_load(&bt_help[i].state, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void help_post(int i, int st)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (WLANE == 0) __hip_atomic_store(&bt_help[i].state, st, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    wave_sync();
+}
+
+// Moves mailbox i from state `from` to `to` if it is in `from` (one lane,
+// result shared by the wave).
+__device__ __forceinline__ bool help_cas(int i, int from, int to)
+{
+    int ok = 0;
+    if (WLANE == 0) {
+        int e = from;
+        ok = __hip_atomic_compare_exchange_strong(&bt_help[i].state, &e, to, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+                                                  __HIP_MEMORY_SCOPE_WORKGROUP) ? 1 : 0;
+    }
+    ok = __builtin_amdgcn_readfirstlane(ok);
+    wave_sync();
+    return ok != 0;
+}
+
+// The node's wave, after its own part: takes the request back if no helper
+// took it (true: run the helper's part itself), else waits for its result.
+__device__ __forceinline__ bool help_reclaim(int i)
+{
+    if (help_cas(i, 1, 0)) return true;
+    while (help_state(i) != 2) __builtin_amdgcn_s_sleep(1);
+    return false;
+}
+
+// The helper's side: serves the requests of wave i until it posts 3 (lds:
+// the helper's own LDS slice).
+__device__ __forceinline__ void sweep_helper(int i, double *lds)
+{
+    SweepHelp *h = &bt_help[i];
+    for (;;) {
+        int st;
+        while ((st = help_state(i)) != 1 && st != 3) __builtin_amdgcn_s_sleep(1);
+        if (st == 3) break;
+        if (!help_cas(i, 1, 4)) continue;   // taken back meanwhile
+        const Arr<double> out{h->ox, h->ov, h->os, 1, h->cap};
+        if (h->kind == 1) {
+            const View<double> F{h->fx, h->fv, h->fs, h->m, h->st};
+            int off = 0;
+            bool line = false;
+            const int n = wave_sweep_a<true, double>(F, h->slope, out, &off, h->codes, &line);
+            if (WLANE == 0) {
+                h->off = off;
+                h->line = line ? 1 : 0;
+                h->count = n;
+            }
+        } else {
+            const View<double> Av{h->ax, h->av, h->as, h->ma, 1};
+            const View<double> Rv{h->rx, h->rv, h->rs, h->mrb, 1};
+            const MirSrc<double> Bv{Rv, h->mrb};
+            double pend, frs;
+            const int n = merge_sched_tiles<OPMIN, double>(Av, Bv, h->sF, h->sG, h->Lt, h->D, h->Lt, out, lds, 0,
+                                                           __builtin_nan(""), &pend, &frs);
+            if (WLANE == 0) {
+                h->count = n;
+                h->frs = frs;
+            }
+        }
+        help_post(i, 2);
+    }
+}
+#else
+inline int bt_host_split = 0;   // host builds: run the split MERGE_MIN(A, B) on one emulated wave
+inline long long bt_host_split_stats[2];   // split merges, and first points of an upper half dropped
+#endif
+
+// MERGE_MIN(A, B) of the envelope from its schedule, the upper half of its
+// merged positions (from a tile boundary) run by the helper wave `help` on
+// the GPU, or before the lower half on the same wave in a host build with
+// bt_host_split set.  The upper half is emitted into a buffer of its own from
+// an unknown arriving slope, so its first union point is kept; the node's
+// wave drops it when the slope arriving there (the one its own half leaves)
+// equals the slope it leaves -- the decision the whole merge takes there --
+// and appends the rest.  Returns -2 when the merge is not split (no helper,
+// fewer than four tiles, or no room for the buffer).
+BTD int env_merge_split(const View<double> &Av, const View<double> &Rv, const MirSrc<double> &Bv, int ma, int mrb,
+                        const int *sF, const int *sG, const Arr<double> &out, double *lds, WaveTmp &T, int help)
+{
+    const int tm = NLANES * WaveLds<double>::E;
+    const int Lt = ma + mrb;
+#ifdef BT_HOST_DEBUG
+    const bool split = bt_host_split != 0;
+    (void)help;
+#else
+    const bool split = help >= 0;
+#endif
+    if (!split || Lt < 4 * tm || out.cap < 1) return -2;
+    const int D = (Lt / 2 / tm) * tm;
+    const int64_t mark = T.used;
+    Arr<double> o2;
+    if (!T.arr<double>(out.cap, &o2)) return -2;
+    int n2;
+    double frs;
+#ifdef BT_HOST_DEBUG
+    {
+        double pe2;
+        n2 = merge_sched_tiles<OPMIN, double>(Av, Bv, sF, sG, Lt, D, Lt, o2, lds, 0, __builtin_nan(""), &pe2, &frs);
+    }
+#else
+    SweepHelp &h = bt_help[help];
+    if (WLANE == 0) {
+        h.kind = 2;
+        h.ax = Av.x; h.av = Av.v; h.as = Av.s; h.ma = ma;
+        h.rx = Rv.x; h.rv = Rv.v; h.rs = Rv.s; h.mrb = mrb;
+        h.sF = sF; h.sG = sG; h.Lt = Lt; h.D = D;
+        h.ox = o2.x; h.ov = o2.v; h.os = o2.s; h.cap = o2.cap;
+    }
+    help_post(help, 1);
+#endif
+    const SchedHead<OPMIN, double> hd = sched_head<OPMIN, double>(Av, Bv);
+    double pend;
+    const int c1 = merge_sched_tiles<OPMIN, double>(Av, Bv, sF, sG, Lt, 0, D, out, lds, hd.keepL, hd.psl, &pend,
+                                                    nullptr);
+#ifndef BT_HOST_DEBUG
+    if (help_reclaim(help)) {
+        double pe2;
+        n2 = merge_sched_tiles<OPMIN, double>(Av, Bv, sF, sG, Lt, D, Lt, o2, lds, 0, __builtin_nan(""), &pe2, &frs);
+    } else {
+        n2 = h.count;
+        frs = h.frs;
+    }
+#endif
+    int total = -1;
+    if (c1 >= 0 && n2 >= 0) {
+        const int drop = frs == pend ? 1 : 0;
+#ifdef BT_HOST_DEBUG
+        bt_host_split_stats[0]++;
+        bt_host_split_stats[1] += drop;
+#endif
+        if (c1 + n2 - drop <= out.cap) {
+            const int n = n2 - drop;
+            LANES(l) {
+                for (int i = l; i < n; i += NLANES) {
+                    out.X(c1 + i) = o2.X(drop + i);
+                    out.V(c1 + i) = o2.V(drop + i);
+                    out.S(c1 + i + 1) = o2.S(drop + i + 1);
+                }
+            }
+            WSYNC();
+            total = sched_finish<OPMIN, double>(hd, c1 + n, out);
+        }
+    }
+    T.used = mark;
+    return total;
+}
+
 template <typename N>
-BTD int wave_env(const Arr<N> &Fa, int m, const N &a, const N &b, const Arr<N> &out, WaveTmp &T, N *lds)
+BTD int wave_env(const Arr<N> &Fa, int m, const N &a, const N &b, const Arr<N> &out, WaveTmp &T, N *lds,
+                 int help = -1)
 {
     const int64_t mark = T.used;
     const View<N> F = Fa.view(m);
@@ -1540,8 +1768,33 @@ BTD int wave_env(const Arr<N> &Fa, int m, const N &a, const N &b, const Arr<N> &
     int offA = 0, offR = 0, ma = -1, mrb = -1;
     bool lineA = false, lineR = false;
     if constexpr (sizeof(N) == sizeof(double)) {
-        ma = wave_sweep_a<false, N>(F, a, A, &offA, codesA, &lineA);
-        mrb = ma < 0 ? -1 : wave_sweep_a<true, N>(F, -b, RB, &offR, codesR, &lineR);
+#ifndef BT_HOST_DEBUG
+        if (help >= 0) {
+            // the mirror sweep goes to the helper wave, the direct one stays
+            SweepHelp &h = bt_help[help];
+            if (WLANE == 0) {
+                h.kind = 1;
+                h.m = m; h.st = F.st; h.cap = RB.cap;
+                h.fx = F.x; h.fv = F.v; h.fs = F.s;
+                h.ox = RB.x; h.ov = RB.v; h.os = RB.s;
+                h.codes = codesR;
+                h.slope = -b;
+            }
+            help_post(help, 1);
+            ma = wave_sweep_a<false, N>(F, a, A, &offA, codesA, &lineA);
+            if (help_reclaim(help)) {
+                mrb = ma < 0 ? -1 : wave_sweep_a<true, N>(F, -b, RB, &offR, codesR, &lineR);
+            } else {
+                mrb = ma < 0 ? -1 : h.count;
+                offR = h.off;
+                lineR = h.line != 0;
+            }
+        } else
+#endif
+        {
+            ma = wave_sweep_a<false, N>(F, a, A, &offA, codesA, &lineA);
+            mrb = ma < 0 ? -1 : wave_sweep_a<true, N>(F, -b, RB, &offR, codesR, &lineR);
+        }
     } else {
         // dual numbers: the decisions on the values (a binary64 sweep over
         // the value parts, several pieces per lane), then the points with
@@ -1571,7 +1824,9 @@ BTD int wave_env(const Arr<N> &Fa, int m, const N &a, const N &b, const Arr<N> &
         const int64_t nd = ((int64_t)ma + mrb + 2) / 2;   // ma + mrb ints
         int *sF = (int *)T.dbl(nd), *sG = (int *)T.dbl(nd);
         if (sF && sG && env_schedule<N>(Av, Bv, ma, mrb, codesA, codesR, m, sF, sG)) {
-            mv = wave_merge_sched<OPMIN, N>(Av, Bv, sF, sG, out, lds);
+            mv = -2;
+            if constexpr (sizeof(N) == sizeof(double)) mv = env_merge_split(Av, Rv, Bv, ma, mrb, sF, sG, out, lds, T, help);
+            if (mv == -2) mv = wave_merge_sched<OPMIN, N>(Av, Bv, sF, sG, out, lds);
             done = true;
         }
     }
@@ -1585,11 +1840,13 @@ BTD int wave_env(const Arr<N> &Fa, int m, const N &a, const N &b, const Arr<N> &
 
 // One node update by a whole wave (see node_update).  The result is left in
 // *zout inside T's slice (valid until T is reset).  lds: this wave's
-// WaveLds<N>::NUMS numbers of LDS.  exf: as in node_update.
+// WaveLds<N>::NUMS numbers of LDS.  exf: as in node_update.  help (binary64
+// buyer, device builds): the mailbox (bt_help index) an idle wave serves for
+// this node, or -1.
 template <int SIDE, typename N>
 BTD int wave_node_update(const View<N> &Zu, const View<N> &Zd, const N &S, const N &kt, const N &rho,
                          const N &xi, const N &zeta, bool exercise, WaveTmp &T, N *lds, Arr<N> *zout,
-                         int *exf = nullptr)
+                         int *exf = nullptr, int help = -1)
 {
     const N one = mk<N>(1.0);
     const N a = -((one + kt) * S);
@@ -1617,11 +1874,11 @@ BTD int wave_node_update(const View<N> &Zu, const View<N> &Zd, const N &S, const
         // practice: try a buffer of 2 mw + 8 first and fall back to the bound
         const int64_t markv = T.used;
         if (!T.arr<N>(2 * mw + 8, &V)) return -1;
-        mv = wave_env(W, mw, a, b, V, T, lds);
+        mv = wave_env(W, mw, a, b, V, T, lds, help);
         if (mv < 0) {
             T.used = markv;
             if (!T.arr<N>(8 * mw + 1, &V)) return -1;
-            mv = wave_env(W, mw, a, b, V, T, lds);
+            mv = wave_env(W, mw, a, b, V, T, lds, help);
         }
     }
     if (mv < 0) return -1;

@@ -6,7 +6,8 @@
 // stdin, one option per line: S0 K K2 R sigma T k N payoff flags
 // argv[1] = per-lane threshold (nodes whose children hold more points go to
 // the cooperative path; 0 sends every node there), argv[2] = 1 for tangents,
-// argv[3] = emulated lanes.
+// argv[3] = emulated lanes, argv[4] = 1 to run the envelope's final merge in
+// two halves as a helper wave would (binary64).
 // stdout, one line per option: error ask bid total_bp_ask total_bp_bid
 // max_bp_ask max_bp_bid [8 tangents], numbers in hexadecimal floating point.
 #define BT_HOST_DEBUG 1
@@ -73,6 +74,7 @@ int main(int argc, char** argv) {
   int thr = argc > 1 ? atoi(argv[1]) : 12;
   int grad = argc > 2 ? atoi(argv[2]) : 0;
   if (argc > 3) bt_host_lanes = atoi(argv[3]);
+  if (argc > 4) bt_host_split = atoi(argv[4]);
   while (scanf("%lf %lf %lf %lf %lf %lf %lf %d %d %u", &S0,&K,&K2,&R,&sig,&T,&k,&N,&pay,&fl) == 10) {
     bt_params p{S0, K, K2, R, sig, T, k, N, pay, fl, 0u};
     Model m{};
@@ -91,4 +93,5 @@ int main(int argc, char** argv) {
     fflush(stdout);
   }
   fprintf(stderr, "envelope merges: scheduled %lld, walked %lld\n", bt_host_env_sched[0], bt_host_env_sched[1]);
+  fprintf(stderr, "split merges: %lld, dropped %lld\n", bt_host_split_stats[0], bt_host_split_stats[1]);
 }

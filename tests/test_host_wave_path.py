@@ -50,10 +50,10 @@ def _cases(seed, n, n_max):
     return cases
 
 
-def _run(exe, cases, grad, lanes):
+def _run(exe, cases, grad, lanes, split=False):
     inp = "\n".join(" ".join(repr(x) if j < 7 else str(int(x)) for j, x in enumerate(c)) for c in cases) + "\n"
-    r = subprocess.run([exe, "0", "1" if grad else "0", str(lanes)], input=inp, capture_output=True, text=True,
-                       timeout=600)
+    r = subprocess.run([exe, "0", "1" if grad else "0", str(lanes), "1" if split else "0"], input=inp,
+                       capture_output=True, text=True, timeout=600)
     assert r.returncode == 0, r.stderr[-2000:]
     out = r.stdout.strip().split("\n")
     assert len(out) == len(cases)
@@ -64,10 +64,12 @@ def _oracle(c, grad):
     return oracle.price(c[0], c[1], c[3], c[4], c[5], c[6], c[7], payoff=c[8], K2=c[2], flags=c[9], grad=grad)
 
 
-@pytest.mark.parametrize("lanes", [64, 3])
-def test_cooperative_path_prices_match_oracle(harness, lanes):
+@pytest.mark.parametrize("lanes,split", [(64, False), (3, False), (64, True), (3, True), (2, True)])
+def test_cooperative_path_prices_match_oracle(harness, lanes, split):
+    # split: the envelope's final merge in two halves, the upper half from an
+    # unknown arriving slope, as the helper wave of a workgroup runs it
     cases = _cases(seed=101 + lanes, n=40, n_max=140)
-    out, err = _run(harness, cases, grad=False, lanes=lanes)
+    out, err = _run(harness, cases, grad=False, lanes=lanes, split=split)
     for c, line in zip(cases, out):
         f = line.split()
         o = _oracle(c, grad=False)
@@ -78,6 +80,10 @@ def test_cooperative_path_prices_match_oracle(harness, lanes):
     # the envelope's halves were merged from their schedule
     assert "envelope merges: scheduled" in err
     assert int(err.split("scheduled")[1].split(",")[0]) > 0
+    if split and lanes < 64:
+        # merges were split, and some upper half's first point was dropped
+        n_split, n_drop = (int(x) for x in err.split("split merges:")[1].split("\n")[0].split(", dropped"))
+        assert n_split > 0 and n_drop > 0, (n_split, n_drop)
 
 
 @pytest.mark.parametrize("lanes", [64, 2])
