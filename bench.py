@@ -510,20 +510,34 @@ def main():
         # spreads with costs) take it seconds per option.  Device memory of
         # each workspace from the free-memory difference around its first
         # call.
-        sub = bt.params_tensor(gb[gb["payoff"] == W.PUT][:64])
+        sb_ = gb[gb["payoff"] == W.PUT][:64]
+        sub = bt.params_tensor(sb_)
+        cols = {name: torch.tensor(sb_[name], dtype=torch.float64, device="cuda", requires_grad=True)
+                for name in ("S0", "sigma", "R", "k")}
+
+        def sub_fwd_bwd(mode):
+            for t in cols.values():
+                t.grad = None
+            a_, b_ = bt_autograd(cols["S0"], cols["sigma"], cols["R"], cols["k"], sub, max_N=1500, mode=mode)
+            (a_.sum() + b_.sum()).backward()
+            return a_, b_
+
         fa = {}
         for mode in ("forward", "adjoint"):
-            log(f"greeks {mode} mode on 64 puts")
+            log(f"greeks {mode} mode on 64 puts, through the autograd Function")
             torch.cuda.synchronize()
             free0, _ = torch.cuda.mem_get_info()
-            bt.price_batch(sub, max_N=1500, grad=True, mode=mode)
+            sub_fwd_bwd(mode)
             torch.cuda.synchronize()
             free1, _ = torch.cuda.mem_get_info()
             t0 = time.perf_counter()
-            o_, g_ = bt.price_batch(sub, max_N=1500, grad=True, mode=mode)
+            a_, b_ = sub_fwd_bwd(mode)
             torch.cuda.synchronize()
-            fa[mode] = dict(ms=(time.perf_counter() - t0) * 1e3, workspace_gib=(free0 - free1) / 2 ** 30,
-                            grads=bt.as_grads(g_), ok=bool(np.all(bt.as_results(o_)["status"] == 0)))
+            ms = (time.perf_counter() - t0) * 1e3
+            o_, g_ = bt.price_batch(sub, max_N=1500, grad=True, mode=mode)
+            fa[mode] = dict(ms=ms, workspace_gib=(free0 - free1) / 2 ** 30, grads=bt.as_grads(g_),
+                            ok=bool(np.all(bt.as_results(o_)["status"] == 0)
+                                    and torch.isfinite(cols["S0"].grad).all().item()))
             bt.bt_shutdown()
         ga, gf = fa["adjoint"]["grads"], fa["forward"]["grads"]
         diff = max(float(np.max(np.abs(ga[k] - gf[k]) / np.maximum(1.0, np.abs(gf[k])))) for k in ga.dtype.names)
@@ -531,10 +545,12 @@ def main():
             sample="the first 64 puts of the Greeks book (N 500..1500)", max_rel_diff=diff,
             adjoint=dict(options_per_s=64 / (fa["adjoint"]["ms"] * 1e-3), ms=fa["adjoint"]["ms"],
                          workspace_gib=fa["adjoint"]["workspace_gib"], ok=fa["adjoint"]["ok"],
-                         entry="bt_price_adjoint_batch (reverse sweep, sqrt(N) checkpoints)"),
+                         entry="autograd Function (forward + backward) over bt_price_adjoint_batch "
+                               "(reverse sweep, sqrt(N) checkpoints)"),
             forward=dict(options_per_s=64 / (fa["forward"]["ms"] * 1e-3), ms=fa["forward"]["ms"],
                          workspace_gib=fa["forward"]["workspace_gib"], ok=fa["forward"]["ok"],
-                         entry="bt_price_grad_batch (tangents carried forward)"))
+                         entry="autograd Function (forward + backward) over bt_price_grad_batch "
+                               "(tangents carried forward)"))
         log(f"adjoint vs forward: {extra['greeks_adjoint_vs_forward_64']}")
         extra["batched_greeks_1024"] = dict(options_per_s=len(gb) / dt_g, ms=dt_g * 1e3,
                                             price_only_ms=dt_p * 1e3, greeks_over_price=dt_g / dt_p,

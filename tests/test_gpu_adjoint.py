@@ -99,3 +99,32 @@ def test_adjoint_against_central_differences():
     say(f"  passed {passed}, passed one-sided at a kink {kinked}, failed {failed}")
     assert failed == 0
     assert passed >= 0.9 * (passed + kinked + failed)
+
+
+def test_autograd_function_in_adjoint_mode():
+    # the torch.autograd.Function over the reverse sweep: prices are the
+    # batch entry point's bits, gradients contract bt_price_adjoint_batch's
+    # Greeks with the incoming gradients, and agree with forward mode
+    import torch
+    from paper_1110_2477_amd.autograd import bt_autograd
+    b = W.random_small(24, seed=93, n_max=120)
+    say(f"case: autograd Function, adjoint mode, {len(b)} options")
+    ts = {name: torch.tensor(b[name], dtype=torch.float64, device="cuda", requires_grad=True)
+          for name in ("S0", "sigma", "R", "k")}
+    ask, bid = bt_autograd(ts["S0"], ts["sigma"], ts["R"], ts["k"], b, mode="adjoint")
+    (ask.sum() - 3.0 * bid.sum()).backward()
+    res, g = adjoint(b)
+    assert np.array_equal(ask.detach().cpu().numpy(), res["ask"])
+    assert np.array_equal(bid.detach().cpu().numpy(), res["bid"])
+    for name, gname in (("S0", "dS0"), ("sigma", "dsigma"), ("R", "dR"), ("k", "dk")):
+        want = g["ask_" + gname] - 3.0 * g["bid_" + gname]
+        assert np.array_equal(ts[name].grad.cpu().numpy(), want), name
+    fwd = {name: torch.tensor(b[name], dtype=torch.float64, device="cuda", requires_grad=True)
+           for name in ("S0", "sigma", "R", "k")}
+    fa, fb = bt_autograd(fwd["S0"], fwd["sigma"], fwd["R"], fwd["k"], b, mode="forward")
+    (fa.sum() - 3.0 * fb.sum()).backward()
+    for name in ts:
+        a_, f_ = ts[name].grad.cpu().numpy(), fwd[name].grad.cpu().numpy()
+        assert np.max(np.abs(a_ - f_) / np.maximum(1.0, np.abs(f_))) < 1e-9, name
+    with pytest.raises(ValueError):
+        bt_autograd(ts["S0"], ts["sigma"], ts["R"], ts["k"], b, mode="sideways")
