@@ -325,37 +325,45 @@ __device__ __forceinline__ void band_task(const KArgs &A, int launch, int item, 
             if (tid < NWAVE) bt_help[tid].state = 0;
             __syncthreads();
             const int w = tid >> 6, lane = tid & 63;
-            // binary64 buyer with at most one big node per wave: a wave
-            // without a node, or with one of the smaller nodes once it is
-            // done, takes parts of the envelope of a larger node (bt_wave.hpp,
-            // SweepHelp).  Ranks by children's points, largest first: with
-            // fewer nodes than waves, idle wave nbig + r helps the node of rank
-            // r; with one node per wave, the wave whose node has rank
-            // NWAVE - 1 - r helps the node of rank r < NWAVE / 2 once its own
-            // node is done.
+            // binary64 buyer: the waves with the two heaviest loads of big
+            // nodes (children's points summed over the nodes each takes) get
+            // the help of the two lightest -- a wave without a node at once,
+            // one with nodes once they are done -- for parts of their
+            // envelopes (bt_wave.hpp, SweepHelp; the mailbox is the helped
+            // wave's): the load of rank r < NWAVE / 2 is helped by the one of
+            // rank NWAVE - 1 - r
             int help = -1, helps = -1;
             if constexpr (SIDE == 1 && NT == 1) {
-                if ((int)nbig <= NWAVE) {
-                    const auto pts = [&](int b) { return cntc[sbig[b]] + cntc[sbig[b] + 1]; };
-                    const auto rank = [&](int b) {
-                        int r = 0;
-                        for (int o = 0; o < (int)nbig; o++) {
-                            const int po = pts(o), pb = pts(b);
-                            r += (po > pb || (po == pb && o < b)) ? 1 : 0;
-                        }
-                        return r;
-                    };
-                    // (wave b holds node b; the mailbox is the helped wave's)
-                    if ((int)nbig < NWAVE) {
-                        if (w < (int)nbig && (int)nbig + rank(w) < NWAVE) help = w;
-                        for (int b = 0; b < (int)nbig; b++)
-                            if ((int)nbig + rank(b) == w) helps = b;
-                    } else {
-                        const int rw = rank(w);
-                        if (rw < NWAVE / 2) help = w;
-                        for (int b = 0; b < (int)nbig; b++)
-                            if (rw >= NWAVE / 2 && rank(b) == NWAVE - 1 - rw) helps = b;
+                static_assert(NWAVE == 4, "the pairing below is written for four waves");
+                // loads of the four waves, one pass over the nodes (the lanes
+                // take the nodes, a wave-wide sum per residue)
+                int64_t ld[NWAVE] = {0, 0, 0, 0};
+                for (int b0 = 0; b0 < (int)nbig; b0 += 64) {
+                    const int b = b0 + lane;
+                    const int64_t Mb = b < (int)nbig ? (int64_t)(cntc[sbig[b]] + cntc[sbig[b] + 1]) : 0;
+#pragma unroll
+                    for (int v = 0; v < NWAVE; v++) {
+                        int64_t x = (b & 3) == v ? Mb : 0;
+#pragma unroll
+                        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+                        ld[v] += x;
                     }
+                }
+                int rk[NWAVE];
+#pragma unroll
+                for (int v = 0; v < NWAVE; v++) {
+                    int r = 0;
+#pragma unroll
+                    for (int o = 0; o < NWAVE; o++) r += (ld[o] > ld[v] || (ld[o] == ld[v] && o < v)) ? 1 : 0;
+                    rk[v] = r;
+                }
+                const int rw = rk[w];
+                if (rw < NWAVE / 2) {
+                    help = w;
+                } else {
+#pragma unroll
+                    for (int v = 0; v < NWAVE; v++)
+                        if (rk[v] == NWAVE - 1 - rw) helps = v;
                 }
             }
             const int64_t slice = A.pool / NWAVE;
