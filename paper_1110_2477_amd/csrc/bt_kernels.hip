@@ -418,10 +418,23 @@ __device__ __forceinline__ void band_task(const KArgs &A, int launch, int item, 
                     continue;
                 }
                 T *dst = Ln + pos;
-                for (int j = lane; j < mzb; j += 64) {
-                    dst[1 + 3 * j] = Zb.X(j);
-                    dst[2 + 3 * j] = Zb.V(j);
-                    dst[3 + 3 * j] = Zb.S(j + 1);
+                {
+                    // several points per lane in flight: the loads of a
+                    // group issue before its stores
+                    constexpr int U = NT == 1 ? 4 : 1;
+                    for (int j0 = 0; j0 < mzb; j0 += 64 * U) {
+                        T x[U], v[U], sl[U];
+#pragma unroll
+                        for (int u = 0; u < U; u++) {
+                            const int j = j0 + 64 * u + lane;
+                            if (j < mzb) { x[u] = Zb.X(j); v[u] = Zb.V(j); sl[u] = Zb.S(j + 1); }
+                        }
+#pragma unroll
+                        for (int u = 0; u < U; u++) {
+                            const int j = j0 + 64 * u + lane;
+                            if (j < mzb) { dst[1 + 3 * j] = x[u]; dst[2 + 3 * j] = v[u]; dst[3 + 3 * j] = sl[u]; }
+                        }
+                    }
                 }
                 if (lane == 0) {
                     dst[0] = Zb.S(0);
@@ -462,7 +475,22 @@ __device__ __forceinline__ void band_task(const KArgs &A, int launch, int item, 
                 fatal = true;
             } else {
                 const int64_t base = (int64_t)sbase;
-                for (int64_t q = tid; q < loff; q += WG) Lout[base + q] = Ln[q];
+                {
+                    constexpr int U = NT == 1 ? 4 : 1;
+                    for (int64_t q0 = 0; q0 < loff; q0 += (int64_t)WG * U) {
+                        T r[U];
+#pragma unroll
+                        for (int u = 0; u < U; u++) {
+                            const int64_t q = q0 + (int64_t)u * WG + tid;
+                            if (q < loff) r[u] = Ln[q];
+                        }
+#pragma unroll
+                        for (int u = 0; u < U; u++) {
+                            const int64_t q = q0 + (int64_t)u * WG + tid;
+                            if (q < loff) Lout[base + q] = r[u];
+                        }
+                    }
+                }
                 if (tid < c1 - c0) {
                     offout[c0 + tid] = (int)(base + offn[tid]);
                     cntout[c0 + tid] = cntn[tid];
@@ -934,7 +962,20 @@ BTHD int isqrt_ceil(int x)
 // to dst.
 __device__ void copy_level(const LevelRef &src, const LevelRef &dst, int ncol, int64_t nn)
 {
-    for (int64_t q = threadIdx.x; q < nn; q += WG) dst.rec[q] = src.rec[q];
+    constexpr int U = 4;   // loads of a group issue before its stores
+    for (int64_t q0 = 0; q0 < nn; q0 += (int64_t)WG * U) {
+        double r[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t q = q0 + (int64_t)u * WG + threadIdx.x;
+            if (q < nn) r[u] = src.rec[q];
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t q = q0 + (int64_t)u * WG + threadIdx.x;
+            if (q < nn) dst.rec[q] = r[u];
+        }
+    }
     for (int c = threadIdx.x; c < ncol; c += WG) {
         dst.off[c] = src.off[c];
         dst.cnt[c] = src.cnt[c];

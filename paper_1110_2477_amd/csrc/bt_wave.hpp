@@ -816,27 +816,50 @@ BTD int wave_merge_point(const View<N> &F, const View<N> &G, const Arr<N> &out)
     const double sF0 = val(F.S(0)), sG0 = val(G.S(0)), sF1 = val(F.S(1)), sGm = val(G.S(m));
     const bool tails = OP == OPMAX ? (sF0 >= sG0 && sF1 <= sGm) : (sF0 <= sG0 && sF1 >= sGm);
     if (!tails) return -1;
-    const N xF = F.X(0);
+    // F's one point and slopes, read once; EVAL of F (i = 0 or 1 points of F
+    // at or left of y) and of G's piece after x_j (i = j + 1) written out as
+    // eval_at computes them
+    const N xF = F.X(0), vF = F.V(0), sFa = F.S(0), sFb = F.S(1);
     const double xf = val(xF);
+    const auto evalF = [&](int i, const N &y) -> N { return vF + (i ? sFb : sFa) * (y - xF); };
     LV<int> bad;
     LANES(l) {
         int nb = 0;
-#pragma unroll 4
-        for (int j = l; j < m; j += NLANES) {
-            const N xj = G.X(j);
-            const bool dup = val(xj) == xf;
-            const N P = dup ? xF : xj;
-            // union point P: #{F points <= P} = [P >= x_F], #{G points <= P} = j + 1
-            const N fF = eval_at<N>(F, val(P) >= xf ? 1 : 0, P);
-            const N fG = eval_at<N>(G, j + 1, P);
-            if (better<OP>(val(fF) - val(fG)) != PG) nb++;
-            out.X(j) = P;
-            out.V(j) = fG;
-            out.S(j + 1) = G.S(j + 1);
-            // F's point inside G's piece after x_j
-            if (val(xj) < xf && (j + 1 == m || val(G.X(j + 1)) > xf)) {
-                const N gF = eval_at<N>(F, 1, xF), gG = eval_at<N>(G, j + 1, xF);
-                if (better<OP>(val(gF) - val(gG)) != PG) nb++;
+        // U points of G per lane loaded before any of them is written
+        constexpr int U = sizeof(N) == sizeof(double) ? 4 : 1;
+        for (int j0 = l; j0 < m; j0 += U * NLANES) {
+            N gx[U], gv[U], gs[U];
+            double gx1[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int j = j0 + u * NLANES;
+                if (j < m) {
+                    gx[u] = G.X(j);
+                    gv[u] = G.V(j);
+                    gs[u] = G.S(j + 1);
+                    gx1[u] = j + 1 < m ? val(G.X(j + 1)) : 0.0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int j = j0 + u * NLANES;
+                if (j < m) {
+                    const N xj = gx[u];
+                    const bool dup = val(xj) == xf;
+                    const N P = dup ? xF : xj;
+                    // union point P: #{F points <= P} = [P >= x_F], #{G points <= P} = j + 1
+                    const N fF = evalF(val(P) >= xf ? 1 : 0, P);
+                    const N fG = gv[u] + gs[u] * (P - gx[u]);
+                    if (better<OP>(val(fF) - val(fG)) != PG) nb++;
+                    out.X(j) = P;
+                    out.V(j) = fG;
+                    out.S(j + 1) = gs[u];
+                    // F's point inside G's piece after x_j
+                    if (val(xj) < xf && (j + 1 == m || gx1[u] > xf)) {
+                        const N gF = evalF(1, xF), gG = gv[u] + gs[u] * (xF - gx[u]);
+                        if (better<OP>(val(gF) - val(gG)) != PG) nb++;
+                    }
+                }
             }
         }
         // F's point before every point of G
@@ -1654,6 +1677,37 @@ inline int bt_host_split = 0;   // host builds: run the split MERGE_MIN(A, B) on
 inline long long bt_host_split_stats[2];   // split merges, and first points of an upper half dropped
 #endif
 
+// Copies n points (abscissa, value and the slope after each) from src's
+// point s0 on to dst's point d0 on, with four points per lane in flight.
+BTD void copy_points(const Arr<double> &dst, int d0, const Arr<double> &src, int s0, int n)
+{
+    constexpr int U = 4;
+    LANES(l) {
+        for (int i0 = 0; i0 < n; i0 += U * NLANES) {
+            double x[U], v[U], sl[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int i = i0 + u * NLANES + l;
+                if (i < n) {
+                    x[u] = src.X(s0 + i);
+                    v[u] = src.V(s0 + i);
+                    sl[u] = src.S(s0 + i + 1);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int i = i0 + u * NLANES + l;
+                if (i < n) {
+                    dst.X(d0 + i) = x[u];
+                    dst.V(d0 + i) = v[u];
+                    dst.S(d0 + i + 1) = sl[u];
+                }
+            }
+        }
+    }
+    WSYNC();
+}
+
 // MERGE_MIN(A, B) of the envelope from its schedule, the upper half of its
 // merged positions (from a tile boundary) run by the helper wave `help` on
 // the GPU, or before the lower half on the same wave in a host build with
@@ -1719,14 +1773,7 @@ BTD int env_merge_split(const View<double> &Av, const View<double> &Rv, const Mi
 #endif
         if (c1 + n2 - drop <= out.cap) {
             const int n = n2 - drop;
-            LANES(l) {
-                for (int i = l; i < n; i += NLANES) {
-                    out.X(c1 + i) = o2.X(drop + i);
-                    out.V(c1 + i) = o2.V(drop + i);
-                    out.S(c1 + i + 1) = o2.S(drop + i + 1);
-                }
-            }
-            WSYNC();
+            copy_points(out, c1, o2, drop, n);
             total = sched_finish<OPMIN, double>(hd, c1 + n, out);
         }
     }
