@@ -663,39 +663,17 @@ BTD void win_store(double *buf, const WinRegs<N> &r, XWin *wf, XWin *wg, int l)
     }
 }
 
-// lds: WaveLds<N>::NUMS numbers of this wave's LDS (in a host build, windows
-// of NLANES E + 9 points and staging of 2 E NLANES slots).
-// With SC (rho given) the result is SCALE(MERGE(F, G), rho) in one pass; a
-// scaled result that collapses to a line returns 0 (the caller then merges
-// and scales in two passes).
-// With VO the merge only decides: out receives, per emitted point p >=
-// keepL, the record merge_settle describes (F count at X(p), G count at V(p),
-// flags at S(p + 1)); S(0) and a kept left crossing are not written, and a
-// result without points returns 0.
-template <int OP, typename N, bool SC = false, bool VO = false, typename FF, typename GG>
-BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds, const N &rho = N{})
+// Merged positions [r0, r1) of MERGE(F, G, op) (r0 a multiple of the tile;
+// at0 = the number of F points among the first r0 merged positions),
+// emitted into out from position `carry`; psl, *psl_out and *first_rs as in
+// merge_sched_tiles.  Template arguments as in wave_merge.
+template <int OP, typename N, bool SC, bool VO, typename FF, typename GG>
+BTD int merge_tiles(const FF &F, const GG &G, const Arr<N> &out, N *lds, const N &rho, int r0, int r1, int at0,
+                    int carry, double psl, double *psl_out, double *first_rs)
 {
-    const auto scl = [&](const N &x) -> N {
-        if constexpr (SC) return x * rho;
-        else return x;
-    };
     constexpr int E = WaveLds<N>::E;
     const int tm = NLANES * E;
-    const int mF = F.m, mG = G.m, Lt = mF + mG;
-    if (out.cap < 1) return -1;
-    N P0;
-    int iF0, iG0;
-    {
-        const double xa = val(F.X(0)), xb = val(G.X(0));
-        if (xa < xb) { P0 = F.X(0); iF0 = 1; iG0 = 0; }
-        else if (xb < xa) { P0 = G.X(0); iF0 = 0; iG0 = 1; }
-        else { P0 = F.X(0); iF0 = 1; iG0 = 1; }
-    }
-    const N fF0 = eval_at<N>(F, iF0, P0), fG0 = eval_at<N>(G, iG0, P0);
-    const Slot<N> L = slot_left<OP, N>(F, G, P0, fF0, fG0);
-    const N Lrs = scl(L.rs), Lcrs = L.hc ? scl(L.crs) : Lrs;
-    const int keepL = (L.hc && val(Lrs) != val(Lcrs)) ? 1 : 0;
-    double psl = val(L.hc ? Lcrs : Lrs);   // slope arriving at the next tile's first union point
+    const int Lt = F.m + G.m;
     // the windows' abscissas, then the staging (slot k of lane l at
     // k * NLANES + l); a tile's windows are loaded into registers while the
     // tile before settles
@@ -703,14 +681,18 @@ BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds, const N 
     const int SZ = 2 * E * NLANES;
     N *stg = lds + WaveLds<N>::WIN;
     LV<WinRegs<N>> pre;
-    LANES(l) { win_load<N>(F, G, 0, 0, pre(l), l); }
-    int at = 0, carry = keepL;
-    for (int dt = 0; dt < Lt; dt += tm) {
+    {
+        const int bn = r0 - at0;
+        LANES(l) { win_load<N>(F, G, at0 >= 3 ? at0 - 3 : 0, bn >= 3 ? bn - 3 : 0, pre(l), l); }
+    }
+    if (first_rs) *first_rs = __builtin_nan("");
+    int at = at0;
+    for (int dt = r0; dt < r1; dt += tm) {
         WSYNC();   // the previous tile's reads of the windows and staging are done
         XWin wf, wg;
         LANES(l) { win_store<N>(xw, pre(l), &wf, &wg, l); }
         WSYNC();
-        const int dend = dt + tm < Lt ? dt + tm : Lt;
+        const int dend = dt + tm < r1 ? dt + tm : r1;
         {
             LV<LaneWalk<E>> wk;
             LANES(l) {
@@ -723,7 +705,9 @@ BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds, const N 
             if (dend < Lt) {
                 at_next = from_lane<int>((dend - dt - 1) / E, [&](int l) { return wk(l).aend; });
                 const int bn = dend - at_next;
-                LANES(l) { win_load<N>(F, G, at_next >= 3 ? at_next - 3 : 0, bn >= 3 ? bn - 3 : 0, pre(l), l); }
+                if (dend < r1) {
+                    LANES(l) { win_load<N>(F, G, at_next >= 3 ? at_next - 3 : 0, bn >= 3 ? bn - 3 : 0, pre(l), l); }
+                }
             }
             LV<int> c, own;
             LV<double> pso;
@@ -734,6 +718,8 @@ BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds, const N 
                                                                stg + 2 * SZ + l, NLANES, &fst(l), &po, rho);
                 pso(l) = po;
             }
+            if (first_rs && dt == r0)
+                *first_rs = from_lane<double>(0, [&](int l) { return fst(l).have ? val(fst(l).rs) : __builtin_nan(""); });
             // the slope arriving at each lane's first union point comes from
             // the lane before (the tile before, for lane 0)
             if constexpr (E == 1) {
@@ -782,10 +768,53 @@ BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds, const N 
             at = at_next;
         }
     }
+    *psl_out = psl;
+    return carry;
+}
+
+// The left end of MERGE(F, G, op): the first union point P0, the decision
+// there (scaled by rho with SC), and the slope arriving at the first tile.
+template <int OP, typename N>
+struct MergeHead {
+    N P0, fF0, fG0;
+    Slot<N> L;
+    N Lrs, Lcrs;
+    int keepL;
+    double psl;
+};
+
+template <int OP, typename N, bool SC, typename FF, typename GG>
+BTD MergeHead<OP, N> merge_head(const FF &F, const GG &G, const N &rho)
+{
+    MergeHead<OP, N> h;
+    int iF0, iG0;
+    const double xa = val(F.X(0)), xb = val(G.X(0));
+    if (xa < xb) { h.P0 = F.X(0); iF0 = 1; iG0 = 0; }
+    else if (xb < xa) { h.P0 = G.X(0); iF0 = 0; iG0 = 1; }
+    else { h.P0 = F.X(0); iF0 = 1; iG0 = 1; }
+    h.fF0 = eval_at<N>(F, iF0, h.P0);
+    h.fG0 = eval_at<N>(G, iG0, h.P0);
+    h.L = slot_left<OP, N>(F, G, h.P0, h.fF0, h.fG0);
+    if constexpr (SC) {
+        h.Lrs = h.L.rs * rho;
+        h.Lcrs = h.L.hc ? h.L.crs * rho : h.Lrs;
+    } else {
+        h.Lrs = h.L.rs;
+        h.Lcrs = h.L.hc ? h.L.crs : h.Lrs;
+    }
+    h.keepL = (h.L.hc && val(h.Lrs) != val(h.Lcrs)) ? 1 : 0;
+    h.psl = val(h.L.hc ? h.Lcrs : h.Lrs);   // slope arriving at the next tile's first union point
+    return h;
+}
+
+// Completes MERGE(F, G, op) whose tiles emitted `carry` points.
+template <int OP, typename N, bool SC, bool VO>
+BTD int merge_finish(const MergeHead<OP, N> &h, int carry, const Arr<N> &out, const N &rho)
+{
     if (carry == 0) {
         if constexpr (SC || VO) return 0;
-        LANE0((out.X(0) = L.hc ? L.cy : P0, out.V(0) = L.hc ? L.cv : pick<OP, N>(fF0, fG0),
-               out.S(0) = L.rs, out.S(1) = L.rs));
+        LANE0((out.X(0) = h.L.hc ? h.L.cy : h.P0, out.V(0) = h.L.hc ? h.L.cv : pick<OP, N>(h.fF0, h.fG0),
+               out.S(0) = h.L.rs, out.S(1) = h.L.rs));
         WSYNC();
         return 1;
     }
@@ -793,10 +822,32 @@ BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds, const N 
         WSYNC();
         return carry;
     }
-    LANE0(out.S(0) = Lrs);
-    if (keepL) LANE0((out.X(0) = L.cy, out.V(0) = scl(L.cv), out.S(1) = Lcrs));
+    N cv = h.L.cv;
+    if constexpr (SC) cv = h.L.cv * rho;
+    LANE0(out.S(0) = h.Lrs);
+    if (h.keepL) LANE0((out.X(0) = h.L.cy, out.V(0) = cv, out.S(1) = h.Lcrs));
     WSYNC();
     return carry;
+}
+
+// lds: WaveLds<N>::NUMS numbers of this wave's LDS (in a host build, windows
+// of NLANES E + 9 points and staging of 2 E NLANES slots).
+// With SC (rho given) the result is SCALE(MERGE(F, G), rho) in one pass; a
+// scaled result that collapses to a line returns 0 (the caller then merges
+// and scales in two passes).
+// With VO the merge only decides: out receives, per emitted point p >=
+// keepL, the record merge_settle describes (F count at X(p), G count at V(p),
+// flags at S(p + 1)); S(0) and a kept left crossing are not written, and a
+// result without points returns 0.
+template <int OP, typename N, bool SC = false, bool VO = false, typename FF, typename GG>
+BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds, const N &rho = N{})
+{
+    if (out.cap < 1) return -1;
+    const MergeHead<OP, N> h = merge_head<OP, N, SC>(F, G, rho);
+    double pend;
+    const int carry = merge_tiles<OP, N, SC, VO>(F, G, out, lds, rho, 0, F.m + G.m, 0, h.keepL, h.psl, &pend, nullptr);
+    if (carry < 0) return -1;
+    return merge_finish<OP, N, SC, VO>(h, carry, out, rho);
 }
 
 // MERGE(F, G, op) of a one-point F when G is strictly better than F at
@@ -1583,17 +1634,20 @@ BTD int wave_merge_d4(const FF &F, const GG &G, const Arr<D4> &out, D4 *lds, con
 // node's wave needs its result is taken back (1 -> 0) and run by that wave,
 // so neither side ever waits on a wave that is not working for it.
 struct SweepHelp {
-    int state, kind;             // kind 1: the mirror sweep; 2: the upper half of MERGE_MIN(A, B)
-    int m, st, cap;              // 1: F's points and stride; both: the output's capacity
-    const double *fx, *fv, *fs;  // 1: F
+    int state, kind;             // kind 1: the mirror sweep; 2: the upper half of MERGE_MIN(A, B);
+                                 // 3: the upper half of the first MERGE (with SCALE)
+    int m, st, cap;              // 1, 3: F's points and stride; all: the output's capacity
+    const double *fx, *fv, *fs;  // 1, 3: F
+    const double *gx, *gv, *gs;  // 3: G
+    int gm, gst;                 // 3: G's points and stride
     double *ox, *ov, *os;        // both: the output
     int *codes;                  // 1: the sweep's codes
-    double slope;                // 1: the sweep's slope (-b)
+    double slope;                // 1: the sweep's slope (-b); 3: rho
     const double *ax, *av, *as, *rx, *rv, *rs;   // 2: A and RB (unit stride)
     const int *sF, *sG;          // 2: the schedule
-    int ma, mrb, Lt, D;          // 2: point counts, merged positions, first position of the half
+    int ma, mrb, Lt, D;          // 2: point counts; 2, 3: merged positions, first position of the half
     int off, line, count;        // results
-    double frs;                  // 2: the slope its first union point leaves
+    double frs;                  // 2, 3: the slope its first union point leaves
 };
 
 #ifndef BT_HOST_DEBUG
@@ -1656,6 +1710,17 @@ __device__ __forceinline__ void sweep_helper(int i, double *lds)
                 h->off = off;
                 h->line = line ? 1 : 0;
                 h->count = n;
+            }
+        } else if (h->kind == 3) {
+            const View<double> F{h->fx, h->fv, h->fs, h->m, h->st}, G{h->gx, h->gv, h->gs, h->gm, h->gst};
+            const int D = h->D;
+            const int at = merge_path_in(F, G, D, D - G.m > 0 ? D - G.m : 0, D < F.m ? D : F.m);
+            double pend, frs;
+            const int n = merge_tiles<OPMAX, double, true, false>(F, G, out, (double *)lds, h->slope, D, h->Lt, at,
+                                                                  0, __builtin_nan(""), &pend, &frs);
+            if (WLANE == 0) {
+                h->count = n;
+                h->frs = frs;
             }
         } else {
             const View<double> Av{h->ax, h->av, h->as, h->ma, 1};
@@ -1775,6 +1840,80 @@ BTD int env_merge_split(const View<double> &Av, const View<double> &Rv, const Mi
             const int n = n2 - drop;
             copy_points(out, c1, o2, drop, n);
             total = sched_finish<OPMIN, double>(hd, c1 + n, out);
+        }
+    }
+    T.used = mark;
+    return total;
+}
+
+// SCALE(MERGE(Zu, Zd), rho) (the first step of a node update), split as
+// env_merge_split splits MERGE_MIN(A, B): the upper half of the merged
+// positions (from a tile boundary, with its merge-path coordinate found by
+// search) runs on the helper wave, or first on the same wave in a host build
+// with bt_host_split set.  Returns -2 when the merge is not split, and as
+// wave_merge<OPMAX, double, true> otherwise.
+BTD int merge_scale_split(const View<double> &Zu, const View<double> &Zd, const Arr<double> &out, double *lds,
+                          double rho, WaveTmp &T, int help)
+{
+    const int tm = NLANES * WaveLds<double>::E;
+    const int Lt = Zu.m + Zd.m;
+#ifdef BT_HOST_DEBUG
+    const bool split = bt_host_split != 0;
+    (void)help;
+#else
+    const bool split = help >= 0;
+#endif
+    if (!split || Lt < 4 * tm || out.cap < 1) return -2;
+    const int D = (Lt / 2 / tm) * tm;
+    const int64_t mark = T.used;
+    Arr<double> o2;
+    if (!T.arr<double>(out.cap, &o2)) return -2;
+    int n2;
+    double frs;
+#ifdef BT_HOST_DEBUG
+    {
+        double pe2;
+        const int at = merge_path_in(Zu, Zd, D, D - Zd.m > 0 ? D - Zd.m : 0, D < Zu.m ? D : Zu.m);
+        n2 = merge_tiles<OPMAX, double, true, false>(Zu, Zd, o2, lds, rho, D, Lt, at, 0, __builtin_nan(""), &pe2,
+                                                     &frs);
+    }
+#else
+    SweepHelp &h = bt_help[help];
+    if (WLANE == 0) {
+        h.kind = 3;
+        h.fx = Zu.x; h.fv = Zu.v; h.fs = Zu.s; h.m = Zu.m; h.st = Zu.st;
+        h.gx = Zd.x; h.gv = Zd.v; h.gs = Zd.s; h.gm = Zd.m; h.gst = Zd.st;
+        h.slope = rho; h.Lt = Lt; h.D = D;
+        h.ox = o2.x; h.ov = o2.v; h.os = o2.s; h.cap = o2.cap;
+    }
+    help_post(help, 1);
+#endif
+    const MergeHead<OPMAX, double> hd = merge_head<OPMAX, double, true>(Zu, Zd, rho);
+    double pend;
+    const int c1 = merge_tiles<OPMAX, double, true, false>(Zu, Zd, out, lds, rho, 0, D, 0, hd.keepL, hd.psl, &pend,
+                                                           nullptr);
+#ifndef BT_HOST_DEBUG
+    if (help_reclaim(help)) {
+        double pe2;
+        const int at = merge_path_in(Zu, Zd, D, D - Zd.m > 0 ? D - Zd.m : 0, D < Zu.m ? D : Zu.m);
+        n2 = merge_tiles<OPMAX, double, true, false>(Zu, Zd, o2, lds, rho, D, Lt, at, 0, __builtin_nan(""), &pe2,
+                                                     &frs);
+    } else {
+        n2 = h.count;
+        frs = h.frs;
+    }
+#endif
+    int total = -1;
+    if (c1 >= 0 && n2 >= 0) {
+        const int drop = frs == pend ? 1 : 0;
+#ifdef BT_HOST_DEBUG
+        bt_host_split_stats[0]++;
+        bt_host_split_stats[1] += drop;
+#endif
+        if (c1 + n2 - drop <= out.cap) {
+            const int n = n2 - drop;
+            copy_points(out, c1, o2, drop, n);
+            total = merge_finish<OPMAX, double, true, false>(hd, c1 + n, out, rho);
         }
     }
     T.used = mark;
@@ -1903,8 +2042,12 @@ BTD int wave_node_update(const View<N> &Zu, const View<N> &Zd, const N &S, const
     if (!T.arr<N>(2 * M + 1, &W)) return -1;
     // f = SCALE(MERGE(Zu, Zd), rho), in one pass unless the result is a line
     int mw;
-    if constexpr (sizeof(N) == sizeof(double)) mw = wave_merge<OPMAX, N, true>(Zu, Zd, W, lds, rho);
-    else mw = wave_merge_d4<OPMAX, true>(Zu, Zd, W, lds, rho, T);
+    if constexpr (sizeof(N) == sizeof(double)) {
+        mw = SIDE == 1 ? merge_scale_split(Zu, Zd, W, lds, rho, T, help) : -2;
+        if (mw == -2) mw = wave_merge<OPMAX, N, true>(Zu, Zd, W, lds, rho);
+    } else {
+        mw = wave_merge_d4<OPMAX, true>(Zu, Zd, W, lds, rho, T);
+    }
     if (mw == 0) {
         mw = wave_merge<OPMAX, N>(Zu, Zd, W, lds);
         if (mw < 0 || !T.arr<N>(mw, &W2)) return -1;
