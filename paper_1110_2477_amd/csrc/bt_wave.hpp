@@ -859,14 +859,12 @@ BTD int wave_merge(const FF &F, const GG &G, const Arr<N> &out, N *lds, const N 
 // writes that output into out while it checks the conditions; it returns
 // the count, or -1 when a condition fails (out is then to be overwritten by
 // the full merge).  A line G is left to the full merge.
+// merge_point_range: the checks and the output of G's points [jb, je);
+// returns the count of failed checks over the wave.
 template <int OP, typename N>
-BTD int wave_merge_point(const View<N> &F, const View<N> &G, const Arr<N> &out)
+BTD int merge_point_range(const View<N> &F, const View<N> &G, const Arr<N> &out, int jb, int je)
 {
     const int m = G.m;
-    if (out.cap < m || (m == 1 && val(G.S(0)) == val(G.S(1)))) return -1;
-    const double sF0 = val(F.S(0)), sG0 = val(G.S(0)), sF1 = val(F.S(1)), sGm = val(G.S(m));
-    const bool tails = OP == OPMAX ? (sF0 >= sG0 && sF1 <= sGm) : (sF0 <= sG0 && sF1 >= sGm);
-    if (!tails) return -1;
     // F's one point and slopes, read once; EVAL of F (i = 0 or 1 points of F
     // at or left of y) and of G's piece after x_j (i = j + 1) written out as
     // eval_at computes them
@@ -878,13 +876,13 @@ BTD int wave_merge_point(const View<N> &F, const View<N> &G, const Arr<N> &out)
         int nb = 0;
         // U points of G per lane loaded before any of them is written
         constexpr int U = sizeof(N) == sizeof(double) ? 4 : 1;
-        for (int j0 = l; j0 < m; j0 += U * NLANES) {
+        for (int j0 = jb + l; j0 < je; j0 += U * NLANES) {
             N gx[U], gv[U], gs[U];
             double gx1[U];
 #pragma unroll
             for (int u = 0; u < U; u++) {
                 const int j = j0 + u * NLANES;
-                if (j < m) {
+                if (j < je) {
                     gx[u] = G.X(j);
                     gv[u] = G.V(j);
                     gs[u] = G.S(j + 1);
@@ -894,7 +892,7 @@ BTD int wave_merge_point(const View<N> &F, const View<N> &G, const Arr<N> &out)
 #pragma unroll
             for (int u = 0; u < U; u++) {
                 const int j = j0 + u * NLANES;
-                if (j < m) {
+                if (j < je) {
                     const N xj = gx[u];
                     const bool dup = val(xj) == xf;
                     const N P = dup ? xF : xj;
@@ -913,16 +911,45 @@ BTD int wave_merge_point(const View<N> &F, const View<N> &G, const Arr<N> &out)
                 }
             }
         }
-        // F's point before every point of G
-        if (l == 0 && xf < val(G.X(0))) {
-            const N gF = eval_at<N>(F, 1, xF), gG = eval_at<N>(G, 0, xF);
-            if (better<OP>(val(gF) - val(gG)) != PG) nb++;
-        }
         bad(l) = nb;
     }
+    return lv_exscan(bad);
+}
+
+// The checks of that merge that do not belong to one of G's points: the
+// capacity, a line G and the tails (*ok false when one fails), and F's point
+// left of every point of G (the returned count of failed checks).
+template <int OP, typename N>
+BTD int wave_merge_point_head(const View<N> &F, const View<N> &G, const Arr<N> &out, bool *ok)
+{
+    const int m = G.m;
+    *ok = false;
+    if (out.cap < m || (m == 1 && val(G.S(0)) == val(G.S(1)))) return 0;
+    const double sF0 = val(F.S(0)), sG0 = val(G.S(0)), sF1 = val(F.S(1)), sGm = val(G.S(m));
+    const bool tails = OP == OPMAX ? (sF0 >= sG0 && sF1 <= sGm) : (sF0 <= sG0 && sF1 >= sGm);
+    if (!tails) return 0;
+    *ok = true;
+    // F's point before every point of G
+    const N xF = F.X(0);
+    int nb = 0;
+    if (val(xF) < val(G.X(0))) {
+        const N gF = eval_at<N>(F, 1, xF), gG = eval_at<N>(G, 0, xF);
+        if (better<OP>(val(gF) - val(gG)) != PG) nb++;
+    }
+    return nb;
+}
+
+template <int OP, typename N>
+BTD int wave_merge_point(const View<N> &F, const View<N> &G, const Arr<N> &out)
+{
+    bool ok;
+    const int nb0 = wave_merge_point_head<OP, N>(F, G, out, &ok);
+    if (!ok) return -1;
+    const int m = G.m;
+    const int nb = nb0 + merge_point_range<OP, N>(F, G, out, 0, m);
     LANE0(out.S(0) = G.S(0));
     WSYNC();
-    return lv_exscan(bad) == 0 ? m : -1;
+    return nb == 0 ? m : -1;
 }
 
 // SCALE by rho from A into out (then CANON).
@@ -1635,17 +1662,18 @@ BTD int wave_merge_d4(const FF &F, const GG &G, const Arr<D4> &out, D4 *lds, con
 // so neither side ever waits on a wave that is not working for it.
 struct SweepHelp {
     int state, kind;             // kind 1: the mirror sweep; 2: the upper half of MERGE_MIN(A, B);
-                                 // 3: the upper half of the first MERGE (with SCALE)
-    int m, st, cap;              // 1, 3: F's points and stride; all: the output's capacity
-    const double *fx, *fv, *fs;  // 1, 3: F
-    const double *gx, *gv, *gs;  // 3: G
-    int gm, gst;                 // 3: G's points and stride
+                                 // 3: the upper half of the first MERGE (with SCALE); 4: the
+                                 // upper half of the exercise merge's shortcut
+    int m, st, cap;              // 1, 3, 4: F's points and stride; all: the output's capacity
+    const double *fx, *fv, *fs;  // 1, 3, 4: F
+    const double *gx, *gv, *gs;  // 3, 4: G
+    int gm, gst;                 // 3, 4: G's points and stride
     double *ox, *ov, *os;        // both: the output
     int *codes;                  // 1: the sweep's codes
     double slope;                // 1: the sweep's slope (-b); 3: rho
     const double *ax, *av, *as, *rx, *rv, *rs;   // 2: A and RB (unit stride)
     const int *sF, *sG;          // 2: the schedule
-    int ma, mrb, Lt, D;          // 2: point counts; 2, 3: merged positions, first position of the half
+    int ma, mrb, Lt, D;          // 2: point counts; 2, 3: merged positions; 2, 3, 4: first position of the half
     int off, line, count;        // results
     double frs;                  // 2, 3: the slope its first union point leaves
 };
@@ -1711,6 +1739,10 @@ __device__ __forceinline__ void sweep_helper(int i, double *lds)
                 h->line = line ? 1 : 0;
                 h->count = n;
             }
+        } else if (h->kind == 4) {
+            const View<double> F{h->fx, h->fv, h->fs, h->m, h->st}, G{h->gx, h->gv, h->gs, h->gm, h->gst};
+            const int n = merge_point_range<OPMIN, double>(F, G, out, h->D, G.m);
+            if (WLANE == 0) h->count = n;
         } else if (h->kind == 3) {
             const View<double> F{h->fx, h->fv, h->fs, h->m, h->st}, G{h->gx, h->gv, h->gs, h->gm, h->gst};
             const int D = h->D;
@@ -1920,6 +1952,48 @@ BTD int merge_scale_split(const View<double> &Zu, const View<double> &Zd, const 
     return total;
 }
 
+// The buyer's exercise merge shortcut (wave_merge_point<OPMIN>) with the
+// upper half of V's points checked and written by the helper wave: every
+// point's output has a fixed place, so the halves need no joining.  Returns
+// -2 when not split, else as wave_merge_point.
+BTD int merge_point_split(const View<double> &F, const View<double> &G, const Arr<double> &out, int help)
+{
+#ifdef BT_HOST_DEBUG
+    const bool split = bt_host_split != 0;
+    (void)help;
+#else
+    const bool split = help >= 0;
+#endif
+    const int m = G.m, uw = 4 * NLANES;
+    if (!split || m < 4 * uw) return -2;
+    bool ok;
+    const int nb0 = wave_merge_point_head<OPMIN, double>(F, G, out, &ok);
+    if (!ok) return -1;
+    const int J = (m / 2 / uw) * uw;
+    int nb2;
+#ifdef BT_HOST_DEBUG
+    nb2 = merge_point_range<OPMIN, double>(F, G, out, J, m);
+#else
+    SweepHelp &h = bt_help[help];
+    if (WLANE == 0) {
+        h.kind = 4;
+        h.fx = F.x; h.fv = F.v; h.fs = F.s; h.m = F.m; h.st = F.st;
+        h.gx = G.x; h.gv = G.v; h.gs = G.s; h.gm = G.m; h.gst = G.st;
+        h.ox = out.x; h.ov = out.v; h.os = out.s; h.cap = out.cap;
+        h.D = J;
+    }
+    help_post(help, 1);
+#endif
+    const int nb1 = merge_point_range<OPMIN, double>(F, G, out, 0, J);
+#ifndef BT_HOST_DEBUG
+    if (help_reclaim(help)) nb2 = merge_point_range<OPMIN, double>(F, G, out, J, m);
+    else nb2 = h.count;
+#endif
+    LANE0(out.S(0) = G.S(0));
+    WSYNC();
+    return nb0 + nb1 + nb2 == 0 ? m : -1;
+}
+
 template <typename N>
 BTD int wave_env(const Arr<N> &Fa, int m, const N &a, const N &b, const Arr<N> &out, WaveTmp &T, N *lds,
                  int help = -1)
@@ -2081,7 +2155,9 @@ BTD int wave_node_update(const View<N> &Zu, const View<N> &Zd, const N &S, const
     LANE0((U.X(0) = SIDE == 0 ? zeta : -zeta, U.V(0) = SIDE == 0 ? xi : -xi, U.S(0) = a, U.S(1) = b));
     WSYNC();
     // no exercise at or near this node: the merge keeps V's points
-    int mz = wave_merge_point<SIDE == 0 ? OPMAX : OPMIN, N>(U.view(1), V.view(mv), Z);
+    int mz = -2;
+    if constexpr (SIDE == 1 && sizeof(N) == sizeof(double)) mz = merge_point_split(U.view(1), V.view(mv), Z, help);
+    if (mz == -2) mz = wave_merge_point<SIDE == 0 ? OPMAX : OPMIN, N>(U.view(1), V.view(mv), Z);
     if (mz < 0) mz = wave_merge<SIDE == 0 ? OPMAX : OPMIN, N>(U.view(1), V.view(mv), Z, lds);
     *zout = Z;
     return mz;
