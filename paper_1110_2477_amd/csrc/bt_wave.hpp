@@ -1305,18 +1305,20 @@ BTD void wave_sweep_fill(const View<N> &F, const N &a, const int *codes, const i
 // ---------------------------------------------------------------------------
 
 // Builds the schedule (sF[d] = 4 iF + src, sG[d] = iG for merged positions d
-// of the ma + mb points); returns false when the counts do not add up.
+// of the ma + mb points) of pieces [j0, j1) (j0 a multiple of the tile of
+// 4 NLANES pieces) from the carries *cAio, *cBio (the point counts of A and
+// of B before j0), which it advances to j1.
 template <typename N, typename FA, typename FB>
-BTD bool env_schedule(const FA &A, const FB &B, int ma, int mb, const int *codesA, const int *codesR, int m,
-                      int *sF, int *sG)
+BTD void env_schedule_range(const FA &A, const FB &B, int ma, int mb, const int *codesA, const int *codesR, int m,
+                            int *sF, int *sG, int j0, int j1, int *cAio, int *cBio)
 {
     constexpr int ES = 4;
     const BT_GLOBAL int *cA = (const BT_GLOBAL int *)codesA;
     const BT_GLOBAL int *cR = (const BT_GLOBAL int *)codesR;
     BT_GLOBAL int *gF = (BT_GLOBAL int *)sF;
     BT_GLOBAL int *gG = (BT_GLOBAL int *)sG;
-    int carryA = 0, carryB = 0;
-    for (int t0 = 0; t0 < m; t0 += NLANES * ES) {
+    int carryA = *cAio, carryB = *cBio;
+    for (int t0 = j0; t0 < j1; t0 += NLANES * ES) {
         LV<int> na, nb;
         LV<int> code[ES];
         LANES(l) {
@@ -1325,7 +1327,7 @@ BTD bool env_schedule(const FA &A, const FB &B, int ma, int mb, const int *codes
             for (int u = 0; u < ES; u++) {
                 const int j = t0 + l * ES + u;
                 int c = 0;
-                if (j < m) {
+                if (j < j1) {
                     const int ca = cA[j];
                     const int cb1 = cR[m - 1 - j] & 1;
                     const int cb2 = j <= m - 2 ? (cR[m - 2 - j] >> 1) & 1 : 0;
@@ -1385,7 +1387,39 @@ BTD bool env_schedule(const FA &A, const FB &B, int ma, int mb, const int *codes
         carryB += totB;
     }
     WSYNC();
-    return carryA == ma && carryB == mb;
+    *cAio = carryA;
+    *cBio = carryB;
+}
+
+// The point counts of A and of B that pieces [0, j1) contribute (the carries
+// at j1 of the schedule), from the sweeps' codes.
+BTD void env_schedule_carry(const int *codesA, const int *codesR, int m, int j1, int *ca, int *cb)
+{
+    const BT_GLOBAL int *cA = (const BT_GLOBAL int *)codesA;
+    const BT_GLOBAL int *cR = (const BT_GLOBAL int *)codesR;
+    LV<int> na, nb;
+    LANES(l) {
+        int a = 0, b = 0;
+        for (int j = l; j < j1; j += NLANES) {
+            const int c = cA[j];
+            a += (c & 1) + ((c >> 1) & 1);
+            b += (cR[m - 1 - j] & 1) + (j <= m - 2 ? (cR[m - 2 - j] >> 1) & 1 : 0);
+        }
+        na(l) = a;
+        nb(l) = b;
+    }
+    *ca = lv_exscan(na);
+    *cb = lv_exscan(nb);
+}
+
+// The whole schedule; false when the counts do not add up.
+template <typename N, typename FA, typename FB>
+BTD bool env_schedule(const FA &A, const FB &B, int ma, int mb, const int *codesA, const int *codesR, int m,
+                      int *sF, int *sG)
+{
+    int ca = 0, cb = 0;
+    env_schedule_range<N>(A, B, ma, mb, codesA, codesR, m, sF, sG, 0, m, &ca, &cb);
+    return ca == ma && cb == mb;
 }
 
 // Merged positions [r0, r1) of MERGE(F, G, op) driven by a schedule (r0 a
@@ -1663,13 +1697,16 @@ BTD int wave_merge_d4(const FF &F, const GG &G, const Arr<D4> &out, D4 *lds, con
 struct SweepHelp {
     int state, kind;             // kind 1: the mirror sweep; 2: the upper half of MERGE_MIN(A, B);
                                  // 3: the upper half of the first MERGE (with SCALE); 4: the
-                                 // upper half of the exercise merge's shortcut
+                                 // upper half of the exercise merge's shortcut; 5: the upper half
+                                 // of the envelope's schedule
     int m, st, cap;              // 1, 3, 4: F's points and stride; all: the output's capacity
     const double *fx, *fv, *fs;  // 1, 3, 4: F
     const double *gx, *gv, *gs;  // 3, 4: G
     int gm, gst;                 // 3, 4: G's points and stride
     double *ox, *ov, *os;        // both: the output
-    int *codes;                  // 1: the sweep's codes
+    int *codes;                  // 1: the sweep's codes; 5: A's sweep codes
+    int *codes2;                 // 5: RB's sweep codes
+    int *sF2, *sG2;              // 5: the schedule
     double slope;                // 1: the sweep's slope (-b); 3: rho
     const double *ax, *av, *as, *rx, *rv, *rs;   // 2: A and RB (unit stride)
     const int *sF, *sG;          // 2: the schedule
@@ -1738,6 +1775,18 @@ __device__ __forceinline__ void sweep_helper(int i, double *lds)
                 h->off = off;
                 h->line = line ? 1 : 0;
                 h->count = n;
+            }
+        } else if (h->kind == 5) {
+            const View<double> Av{h->ax, h->av, h->as, h->ma, 1};
+            const View<double> Rv{h->rx, h->rv, h->rs, h->mrb, 1};
+            const MirSrc<double> Bv{Rv, h->mrb};
+            int ca = 0, cb = 0;
+            env_schedule_carry(h->codes, h->codes2, h->m, h->D, &ca, &cb);
+            env_schedule_range<double>(Av, Bv, h->ma, h->mrb, h->codes, h->codes2, h->m, h->sF2, h->sG2, h->D, h->m,
+                                       &ca, &cb);
+            if (WLANE == 0) {
+                h->count = ca;
+                h->off = cb;
             }
         } else if (h->kind == 4) {
             const View<double> F{h->fx, h->fv, h->fs, h->m, h->st}, G{h->gx, h->gv, h->gs, h->gm, h->gst};
@@ -1952,6 +2001,51 @@ BTD int merge_scale_split(const View<double> &Zu, const View<double> &Zd, const 
     return total;
 }
 
+// The envelope's schedule with the pieces from a tile boundary J on built by
+// the helper wave, which first counts the points that pieces [0, J)
+// contribute; the schedule's positions follow from those counts, so the two
+// halves write their own entries.  Returns as env_schedule.
+BTD bool env_schedule_split(const View<double> &Av, const View<double> &Rv, const MirSrc<double> &Bv, int ma, int mrb,
+                            int *codesA, int *codesR, int m, int *sF, int *sG, int help)
+{
+#ifdef BT_HOST_DEBUG
+    const bool split = bt_host_split != 0;
+    (void)help;
+#else
+    const bool split = help >= 0;
+#endif
+    const int tile = 4 * NLANES;
+    if (!split || m < 4 * tile) return env_schedule<double>(Av, Bv, ma, mrb, codesA, codesR, m, sF, sG);
+    const int J = (m / 2 / tile) * tile;
+    int ca2 = 0, cb2 = 0;
+#ifdef BT_HOST_DEBUG
+    env_schedule_carry(codesA, codesR, m, J, &ca2, &cb2);
+    env_schedule_range<double>(Av, Bv, ma, mrb, codesA, codesR, m, sF, sG, J, m, &ca2, &cb2);
+#else
+    SweepHelp &h = bt_help[help];
+    if (WLANE == 0) {
+        h.kind = 5;
+        h.ax = Av.x; h.av = Av.v; h.as = Av.s; h.ma = ma;
+        h.rx = Rv.x; h.rv = Rv.v; h.rs = Rv.s; h.mrb = mrb;
+        h.codes = codesA; h.codes2 = codesR; h.m = m; h.sF2 = sF; h.sG2 = sG; h.D = J;
+    }
+    help_post(help, 1);
+#endif
+    int ca = 0, cb = 0;
+    env_schedule_range<double>(Av, Bv, ma, mrb, codesA, codesR, m, sF, sG, 0, J, &ca, &cb);
+#ifndef BT_HOST_DEBUG
+    if (help_reclaim(help)) {
+        ca2 = ca;
+        cb2 = cb;
+        env_schedule_range<double>(Av, Bv, ma, mrb, codesA, codesR, m, sF, sG, J, m, &ca2, &cb2);
+    } else {
+        ca2 = h.count;
+        cb2 = h.off;
+    }
+#endif
+    return ca2 == ma && cb2 == mrb;
+}
+
 // The buyer's exercise merge shortcut (wave_merge_point<OPMIN>) with the
 // upper half of V's points checked and written by the helper wave: every
 // point's output has a fixed place, so the halves need no joining.  Returns
@@ -2083,7 +2177,14 @@ BTD int wave_env(const Arr<N> &Fa, int m, const N &a, const N &b, const Arr<N> &
     if (!lineA && !lineR) {
         const int64_t nd = ((int64_t)ma + mrb + 2) / 2;   // ma + mrb ints
         int *sF = (int *)T.dbl(nd), *sG = (int *)T.dbl(nd);
-        if (sF && sG && env_schedule<N>(Av, Bv, ma, mrb, codesA, codesR, m, sF, sG)) {
+        bool sched = false;
+        if (sF && sG) {
+            if constexpr (sizeof(N) == sizeof(double))
+                sched = env_schedule_split(Av, Rv, Bv, ma, mrb, codesA, codesR, m, sF, sG, help);
+            else
+                sched = env_schedule<N>(Av, Bv, ma, mrb, codesA, codesR, m, sF, sG);
+        }
+        if (sched) {
             mv = -2;
             if constexpr (sizeof(N) == sizeof(double)) mv = env_merge_split(Av, Rv, Bv, ma, mrb, sF, sG, out, lds, T, help);
             if (mv == -2) mv = wave_merge_sched<OPMIN, N>(Av, Bv, sF, sG, out, lds);
