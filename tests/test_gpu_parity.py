@@ -93,6 +93,21 @@ def test_shutdown_releases_the_bt_price_cache():
     assert first == [bt.price_book(b[i:i + 1])[0].tobytes() for i in range(len(b))]
 
 
+def test_plain_pricing_of_invalid_and_varied_options():
+    # bt_price through the batch workspace: options of different N (the
+    # workspace sized for N rounded up to a power of two is reused), and an
+    # invalid option (NaN prices, BT_EINVAL)
+    b = W.random_small(12, seed=71, n_max=600)
+    say("case: bt_price on 12 options of different N and an invalid one")
+    ref = bt.price_book(b)
+    for i in range(len(b)):
+        assert bt.bt_price(b[i]).tobytes() == ref[i].tobytes(), i
+    bad = b[0].copy()
+    bad["N"] = 0
+    r = bt.bt_price(bad)
+    assert r["status"] == bt.BT_EINVAL and np.isnan(r["ask"]) and np.isnan(r["bid"])
+
+
 def test_random_small_book():
     b = W.random_small(240, seed=7, n_max=300)
     say("case: random small book, 240 options, N <= 300, all payoffs and flags")
