@@ -157,10 +157,15 @@ template <typename T>
 __device__ __forceinline__ void write_record(T *dst, const Arr<T> &z, int m)
 {
     dst[0] = z.S(0);
-    for (int j = 0; j < m; j++) {
-        dst[1 + 3 * j] = z.X(j);
-        dst[2 + 3 * j] = z.V(j);
-        dst[3 + 3 * j] = z.S(j + 1);
+    constexpr int B = PWL_GROUP;   // a group's loads before its stores
+    for (int j0 = 0; j0 < m; j0 += B) {
+        T x[B], v[B], sl[B];
+#pragma unroll
+        for (int u = 0; u < B; u++)
+            if (j0 + u < m) { x[u] = z.X(j0 + u); v[u] = z.V(j0 + u); sl[u] = z.S(j0 + u + 1); }
+#pragma unroll
+        for (int u = 0; u < B; u++)
+            if (j0 + u < m) { dst[1 + 3 * (j0 + u)] = x[u]; dst[2 + 3 * (j0 + u)] = v[u]; dst[3 + 3 * (j0 + u)] = sl[u]; }
     }
 }
 

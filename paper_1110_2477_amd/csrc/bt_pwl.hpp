@@ -222,21 +222,39 @@ struct Emit {
     }
 };
 
+// Points per group of the in-place loops below: a group's loads issue
+// before its stores (a store may alias a later load, so the compiler would
+// otherwise wait for each point's round trip to memory).
+constexpr int PWL_GROUP = 4;
+
 // In-place CANON of a stored function; returns the new point count.
 template <typename T>
 BTD int canon(const Arr<T> &f, int m)
 {
+    constexpr int B = PWL_GROUP;
     const T s0 = f.S(0);
     int k = 0;
-    for (int j = 0; j < m; j++) {
+    double sl = val(s0);
+    for (int j0 = 0; j0 < m; j0 += B) {
         // Writes go to indices k <= j (slopes k + 1 <= j + 1, equal only
-        // when nothing was dropped, rewriting the same value), so s[j] and
-        // s[j+1] still hold the input here.
-        const double sl = val(f.S(j)), sr = val(f.S(j + 1));
-        if (sl != sr) {
-            const T xj = f.X(j), vj = f.V(j), srj = f.S(j + 1);
-            f.X(k) = xj; f.V(k) = vj; f.S(k + 1) = srj;
-            k++;
+        // when nothing was dropped, rewriting the same value), so the group's
+        // inputs, read first, are the original ones, and s[j] is the s[j+1]
+        // read for the point before.
+        T xs[B], vs[B], ss[B];
+#pragma unroll
+        for (int u = 0; u < B; u++) {
+            if (j0 + u < m) { xs[u] = f.X(j0 + u); vs[u] = f.V(j0 + u); ss[u] = f.S(j0 + u + 1); }
+        }
+#pragma unroll
+        for (int u = 0; u < B; u++) {
+            if (j0 + u < m) {
+                const double sr = val(ss[u]);
+                if (sl != sr) {
+                    f.X(k) = xs[u]; f.V(k) = vs[u]; f.S(k + 1) = ss[u];
+                    k++;
+                }
+                sl = sr;
+            }
         }
     }
     f.S(0) = s0;
@@ -430,8 +448,20 @@ BTD int merge(const FF &F, const GG &G, const Arr<T> &out)
 template <typename T>
 BTD int scale(const Arr<T> &f, int m, const T &rho)
 {
-    for (int j = 0; j < m; j++) f.V(j) = f.V(j) * rho;
-    for (int j = 0; j <= m; j++) f.S(j) = f.S(j) * rho;
+    constexpr int B = PWL_GROUP;
+    for (int j0 = 0; j0 <= m; j0 += B) {
+        T vs[B], ss[B];
+#pragma unroll
+        for (int u = 0; u < B; u++) {
+            if (j0 + u < m) vs[u] = f.V(j0 + u);
+            if (j0 + u <= m) ss[u] = f.S(j0 + u);
+        }
+#pragma unroll
+        for (int u = 0; u < B; u++) {
+            if (j0 + u < m) f.V(j0 + u) = vs[u] * rho;
+            if (j0 + u <= m) f.S(j0 + u) = ss[u] * rho;
+        }
+    }
     return canon(f, m);
 }
 
@@ -451,10 +481,19 @@ BTD int clip(const Arr<T> &f, int m, const T &a, const T &b)
         f.X(0) = xq; f.V(0) = vq; f.S(0) = a; f.S(1) = a;
         return 1;
     }
-    for (int j = 0; j <= m; j++) {
-        const double s = val(f.S(j));
-        if (s < val(a)) f.S(j) = a;
-        else if (s > val(b)) f.S(j) = b;
+    constexpr int B = PWL_GROUP;
+    for (int j0 = 0; j0 <= m; j0 += B) {
+        double ss[B];
+#pragma unroll
+        for (int u = 0; u < B; u++)
+            if (j0 + u <= m) ss[u] = val(f.S(j0 + u));
+#pragma unroll
+        for (int u = 0; u < B; u++) {
+            if (j0 + u <= m) {
+                if (ss[u] < val(a)) f.S(j0 + u) = a;
+                else if (ss[u] > val(b)) f.S(j0 + u) = b;
+            }
+        }
     }
     return canon(f, m);
 }
@@ -537,7 +576,18 @@ BTD int sweep_a(const View<T> &F, const T &a, const Arr<T> &o)
     }
     reverse_pts(o, n);
     // s[i] now holds the right slope of point i: shift to s[i+1], left tail a
-    for (int i = n - 1; i >= 0; i--) o.S(i + 1) = o.S(i);
+    {
+        constexpr int B = PWL_GROUP;
+        for (int i1 = n - 1; i1 >= 0; i1 -= B) {
+            T ss[B];
+#pragma unroll
+            for (int u = 0; u < B; u++)
+                if (i1 - u >= 0) ss[u] = o.S(i1 - u);
+#pragma unroll
+            for (int u = 0; u < B; u++)
+                if (i1 - u >= 0) o.S(i1 - u + 1) = ss[u];
+        }
+    }
     o.S(0) = a;
     return canon(o, n);
 }
