@@ -118,7 +118,7 @@ typedef struct {
     double ask_lo, ask_hi, bid_lo, bid_hi;
 } bt_hedge;
 
-/* Launch tuning; pass NULL for the library's choice./* Launch tuning; pass NULL for the library's choice.  Zero fields also mean
+/* Launch tuning; pass NULL for the library's choice.  Zero fields also mean
  * "library's choice".
  *   wgs_per_cu   persistent workgroups per compute unit (default 2)
  *   level_factor capacity of one tree level, in points per node (default

@@ -405,14 +405,19 @@ BTD int merge(const FF &F, const GG &G, const Arr<T> &out)
     int a = 0, b = 0;
     T P, fF, fG;
     int iF, iG;
+    // the pieces of F and G that hold P (seg_at(F, iF), seg_at(G, iG)),
+    // carried from one union point to the next instead of loaded again
+    Seg<T> gF, gG;
     {
         const double xa = val(F.X(0)), xb = val(G.X(0));
         if (xa < xb) { P = F.X(0); a = 1; }
         else if (xb < xa) { P = G.X(0); b = 1; }
         else { P = F.X(0); a = 1; b = 1; }
         iF = a; iG = b;
-        fF = eval_at<T>(F, iF, P);
-        fG = eval_at<T>(G, iG, P);
+        gF = seg_at<T>(F, iF);
+        gG = seg_at<T>(G, iG);
+        fF = seg_eval<T>(gF, P);
+        fG = seg_eval<T>(gG, P);
     }
     Emit<T> e;
     {
@@ -429,11 +434,13 @@ BTD int merge(const FF &F, const GG &G, const Arr<T> &out)
             else if (xb < xa) { P1 = G.X(b); b++; }
             else { P1 = F.X(a); a++; b++; }
             const int iF1 = a, iG1 = b;
-            const T fF1 = eval_at<T>(F, iF1, P1), fG1 = eval_at<T>(G, iG1, P1);
-            const Slot<T> o = slot_interval<OP, T>(F, G, P, iF, iG, fF, fG, P1, val(fF1) - val(fG1));
+            const Seg<T> gF1 = iF1 == iF ? gF : seg_at<T>(F, iF1);
+            const Seg<T> gG1 = iG1 == iG ? gG : seg_at<T>(G, iG1);
+            const T fF1 = seg_eval<T>(gF1, P1), fG1 = seg_eval<T>(gG1, P1);
+            const Slot<T> o = slot_interval_seg<OP, T>(gF, gG, P, fF, fG, P1, val(fF1) - val(fG1));
             e.push(P, vv, o.rs);
             if (o.hc) e.push(o.cy, o.cv, o.crs);
-            P = P1; iF = iF1; iG = iG1; fF = fF1; fG = fG1;
+            P = P1; iF = iF1; iG = iG1; fF = fF1; fG = fG1; gF = gF1; gG = gG1;
         } else {
             const Slot<T> o = slot_right<OP, T>(F, G, P, fF, fG);
             e.push(P, vv, o.rs);
