@@ -599,7 +599,7 @@ __global__ __launch_bounds__(WG) void bt_band_kernel(KArgs A, int r)
 // Zero-cost recursion (Section 3, Appendix): no extra level;
 // V_N = max(xi + zeta S, 0), V_t = max(xi + zeta S, rho (p V_up + (1-p) V_dn))
 // (European variant: V_t = continuation value).  One workgroup per option.
-__device__ void price0_item(const KArgs &A, const Model &md, int opt, double *ws)
+__device__ __forceinline__ void price0_item(const KArgs &A, const Model &md, int opt, double *ws)
 {
     const int N = md.N;
     double *Stab = ws;
@@ -633,9 +633,98 @@ __device__ void price0_item(const KArgs &A, const Model &md, int opt, double *ws
     if (threadIdx.x == 0) A.out[opt].price0 = cur[0];
 }
 
+// The same recursion with the level in registers: lane l holds columns
+// l + 256 m, m < J.  A node's upper child is the next lane's value (a DPP
+// wave shift) or, for a wave's last lane, the first lane's value of the next
+// wave (or of wave 0 at m + 1), which each wave's first lane leaves in LDS;
+// two LDS buffers alternate by level, so one barrier per level suffices.
+// Same operations in the same order as price0_item.
+constexpr int P0_JMAX = 80;   // levels of up to 256 * 80 nodes stay in registers
+
+template <int J>
+__device__ __forceinline__ void price0_regs(const KArgs &A, const Model &md, int opt, double *Ptab,
+                                            double (*edge)[NWAVE][P0_JMAX])
+{
+    constexpr int CH = J < 8 ? J : 8;
+    static_assert(J % CH == 0, "columns per lane in whole groups");
+    const int N = md.N;
+    const int l = threadIdx.x, w = l >> 6, ll = l & 63;
+    const Inputs<double> in = inputs_of(md, 0.0);
+    // the exercise value max(xi + zeta S, 0) depends on the lattice index
+    // j = 2c - t alone: one table entry per j, computed as price0_item does
+    for (int idx = l; idx < 2 * N + 3; idx += WG) {
+        const int j = idx - (N + 1);
+        double S = md.S0 * (j >= 0 ? upow(md.u, j) : upow(md.d, -j)), xi, ze;
+        payoff(md, in, S, xi, ze);
+        const double P = xi + ze * S;
+        Ptab[idx] = P > 0.0 ? P : 0.0;
+    }
+    __syncthreads();
+    const bool euro = (md.flags & F_EUROPEAN) != 0;
+    double v[J];
+#pragma unroll
+    for (int m = 0; m < J; m++) {
+        const int c = l + WG * m;
+        v[m] = c <= N ? Ptab[2 * c + 1] : 0.0;
+    }
+    const double p = md.p, q = 1.0 - md.p, rho = md.rho;
+    for (int t = N - 1; t >= 0; t--) {
+        double(*eb)[P0_JMAX] = edge[t & 1];
+        // columns in groups of CH; the next group's exercise values load
+        // while the current group computes (the first group's before the
+        // barrier)
+        double Pn[CH];
+#pragma unroll
+        for (int k = 0; k < CH; k++) {
+            const int idx = 2 * (l + WG * k) - t + N + 1;
+            Pn[k] = euro ? 0.0 : Ptab[idx < 2 * N + 2 ? idx : 2 * N + 2];
+        }
+        if (ll == 0) {
+#pragma unroll
+            for (int m = 0; m < J; m++)
+                if (WG * m <= t + 1) eb[w][m] = v[m];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m0 = 0; m0 < J; m0 += CH) {
+            double Pg[CH];
+#pragma unroll
+            for (int k = 0; k < CH; k++) Pg[k] = Pn[k];
+            if (m0 + CH < J && WG * (m0 + CH) <= t && !euro) {
+#pragma unroll
+                for (int k = 0; k < CH; k++) {
+                    const int idx = 2 * (l + WG * (m0 + CH + k)) - t + N + 1;
+                    Pn[k] = Ptab[idx < 2 * N + 2 ? idx : 2 * N + 2];
+                }
+            }
+            if (WG * m0 > t) continue;
+            // the values past each wave's last lane, read together (every
+            // lane of a wave reads the same word)
+            double Eg[CH];
+#pragma unroll
+            for (int k = 0; k < CH; k++) {
+                const int m = m0 + k;
+                Eg[k] = w < NWAVE - 1 ? eb[w + 1][m] : (m + 1 < J ? eb[0][m + 1] : 0.0);
+            }
+#pragma unroll
+            for (int k = 0; k < CH; k++) {
+                const int m = m0 + k;
+                double up = dpp_d<0x130>(0.0, v[m]);
+                if (ll == 63) up = Eg[k];
+                if (l + WG * m <= t) {
+                    const double cont = rho * (p * up + q * v[m]);
+                    v[m] = euro ? cont : (Pg[k] > cont ? Pg[k] : cont);
+                }
+            }
+        }
+    }
+    if (l == 0) A.out[opt].price0 = v[0];
+}
+
 __global__ __launch_bounds__(WG) void bt_price0_kernel(KArgs A)
 {
     __shared__ int s_item;
+    __shared__ double s_edge[2][NWAVE][P0_JMAX];
     double *ws = A.wsp + (int64_t)blockIdx.x * A.p0_doubles;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(A.p0_queue, 1);
@@ -645,7 +734,12 @@ __global__ __launch_bounds__(WG) void bt_price0_kernel(KArgs A)
         if (q >= *A.p0_count) break;
         const int opt = A.p0_sched[q];
         const Model md = A.models[opt];
-        price0_item(A, md, opt, ws);
+        const int n1 = md.N + 1;
+        if (n1 <= WG * 4) price0_regs<4>(A, md, opt, ws, s_edge);
+        else if (n1 <= WG * 16) price0_regs<16>(A, md, opt, ws, s_edge);
+        else if (n1 <= WG * 40) price0_regs<40>(A, md, opt, ws, s_edge);
+        else if (n1 <= WG * P0_JMAX) price0_regs<P0_JMAX>(A, md, opt, ws, s_edge);
+        else price0_item(A, md, opt, ws);
         __syncthreads();
     }
 }

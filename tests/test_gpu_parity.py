@@ -228,6 +228,32 @@ def test_high_cost_book_needs_and_gets_larger_levels():
     check(b, bt.price_book(b))
 
 
+def test_zero_cost_price_at_every_level_width():
+    # the zero-cost recursion keeps a level of up to 256 J nodes in registers
+    # (J = 4, 16, 40, 80) and beyond that in global memory; N + 1 on both
+    # sides of every width, every payoff shape, American and European.
+    # k = 0 keeps the two costly recursions short
+    Ns = [1, 1023, 1024, 4095, 4096, 10239, 10240, 20479, 20480]
+    pays = [W.PUT, W.CALL, W.BULL, W.PUT_CASH, W.CALL_CASH, W.BEAR, W.STRADDLE]
+    rows = []
+    for i, n in enumerate(Ns):
+        rows.append(dict(S0=100.0, K=105.0, K2=120.0, R=0.04, sigma=0.3, T=1.0, k=0.0, N=n,
+                         payoff=pays[i % len(pays)], flags=W.EUROPEAN if i % 3 == 2 else 0))
+    b = W.book(rows)
+    say("case: zero-cost price across the register widths")
+    res = bt.price_book(b)
+
+    def ref(r):
+        return oracle.price(r["S0"], r["K"], r["R"], r["sigma"], r["T"], 0.0, r["N"], payoff=r["payoff"],
+                            K2=r["K2"], flags=r["flags"], sides=0)["price0"]
+
+    with ThreadPoolExecutor(max_workers=THREADS) as ex:
+        want = list(ex.map(ref, rows))
+    for i, r in enumerate(rows):
+        assert res[i]["status"] == 0, i
+        assert res[i]["price0"] == want[i], (r, res[i]["price0"], want[i])
+
+
 def test_long_put_n8192_and_n20000():
     b = W.book([dict(S0=100.0, K=100.0, R=0.05, sigma=0.4, T=2.0, k=0.01, N=8192, payoff=W.PUT)])
     say("case: put N=8192")
