@@ -519,11 +519,27 @@ struct Src {
 template <typename T>
 BTD void reverse_pts(const Arr<T> &o, int n)
 {
-    for (int i = 0, j = n - 1; i < j; i++, j--) {
-        T t;
-        t = o.X(i); o.X(i) = o.X(j); o.X(j) = t;
-        t = o.V(i); o.V(i) = o.V(j); o.V(j) = t;
-        t = o.S(i); o.S(i) = o.S(j); o.S(j) = t;
+    // pairs (i, n-1-i), a group of them loaded before any is stored
+    constexpr int B = sizeof(T) == sizeof(double) ? PWL_GROUP : 1;
+    const int h = n / 2;
+    for (int i0 = 0; i0 < h; i0 += B) {
+        T lx[B], lv[B], ls[B], rx[B], rv[B], rs[B];
+#pragma unroll
+        for (int u = 0; u < B; u++) {
+            const int i = i0 + u, j = n - 1 - i;
+            if (i < h) {
+                lx[u] = o.X(i); lv[u] = o.V(i); ls[u] = o.S(i);
+                rx[u] = o.X(j); rv[u] = o.V(j); rs[u] = o.S(j);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < B; u++) {
+            const int i = i0 + u, j = n - 1 - i;
+            if (i < h) {
+                o.X(i) = rx[u]; o.V(i) = rv[u]; o.S(i) = rs[u];
+                o.X(j) = lx[u]; o.V(j) = lv[u]; o.S(j) = ls[u];
+            }
+        }
     }
 }
 
@@ -603,16 +619,40 @@ BTD int sweep_a(const View<T> &F, const T &a, const Arr<T> &o)
 template <typename T>
 BTD void mirror_inplace(const Arr<T> &o, int n)
 {
-    for (int i = 0, j = n - 1; i < j; i++, j--) {
-        T t;
-        t = o.X(i); o.X(i) = o.X(j); o.X(j) = t;
-        t = o.V(i); o.V(i) = o.V(j); o.V(j) = t;
+    // points: pairs (i, n-1-i) (the middle one pairs with itself); slopes:
+    // pairs (i, n-i); a group of pairs loaded before any is stored
+    constexpr int B = sizeof(T) == sizeof(double) ? PWL_GROUP : 1;
+    const int hp = (n + 1) / 2;
+    for (int i0 = 0; i0 < hp; i0 += B) {
+        T lx[B], lv[B], rx[B], rv[B];
+#pragma unroll
+        for (int u = 0; u < B; u++) {
+            const int i = i0 + u, j = n - 1 - i;
+            if (i < hp) { lx[u] = o.X(i); lv[u] = o.V(i); rx[u] = o.X(j); rv[u] = o.V(j); }
+        }
+#pragma unroll
+        for (int u = 0; u < B; u++) {
+            const int i = i0 + u, j = n - 1 - i;
+            if (i < hp) {
+                o.X(i) = -rx[u]; o.V(i) = rv[u];
+                o.X(j) = -lx[u]; o.V(j) = lv[u];
+            }
+        }
     }
-    for (int i = 0; i < n; i++) o.X(i) = -o.X(i);
-    for (int i = 0, j = n; i < j; i++, j--) {
-        T t = o.S(i); o.S(i) = o.S(j); o.S(j) = t;
+    const int hs = n / 2 + 1;
+    for (int i0 = 0; i0 < hs; i0 += B) {
+        T ls[B], rs[B];
+#pragma unroll
+        for (int u = 0; u < B; u++) {
+            const int i = i0 + u;
+            if (i < hs) { ls[u] = o.S(i); rs[u] = o.S(n - i); }
+        }
+#pragma unroll
+        for (int u = 0; u < B; u++) {
+            const int i = i0 + u;
+            if (i < hs) { o.S(i) = -rs[u]; o.S(n - i) = -ls[u]; }
+        }
     }
-    for (int i = 0; i <= n; i++) o.S(i) = -o.S(i);
 }
 
 }  // namespace bt
