@@ -52,15 +52,14 @@ BTD Inputs<D4> inputs_of(const Model &md, D4)
 // A and B the two halves of ENV, V the restricted function, Z the result.
 struct Caps {
     int cW, cA, cB, cV, cZ;
-    int64_t oU, oW, oA, oB, oV, oZ, total;  // offsets / size in stride units
+    int64_t oW, oA, oB, oV, oZ, total;  // offsets / size in stride units
 };
 
 BTHD Caps make_caps(int cW, int cA, int cB, int cV, int cZ)
 {
     Caps c;
     c.cW = cW; c.cA = cA; c.cB = cB; c.cV = cV; c.cZ = cZ;
-    c.oU = 0;
-    c.oW = 4;
+    c.oW = 0;
     c.oA = c.oW + 3 * (int64_t)cW + 1;
     c.oB = c.oA + 3 * (int64_t)cA + 1;
     c.oV = c.oB + 3 * (int64_t)cB + 1;
@@ -248,13 +247,9 @@ BTD int node_update(const View<T> &Zu, const View<T> &Zd, const T &S, const T &k
         if (exf) *exf = exercise ? exercise_flag<SIDE, T>(V.view(mv), xi, zeta, a, b) : 0;
     }
     if (!exercise) { *zout = V; return mv; }
-    Arr<T> U = stage(base, st, cp.oU, 1);
-    // U occupies 4 numbers: x, v, s0, s1 (cap 1 -> x, v, s[0..1]).
-    if (SIDE == 0) { U.X(0) = zeta; U.V(0) = xi; }
-    else { U.X(0) = -zeta; U.V(0) = -xi; }
-    U.S(0) = a; U.S(1) = b;
+    const Kink<T> U{SIDE == 0 ? zeta : -zeta, SIDE == 0 ? xi : -xi, a, b, 1};
     Arr<T> Z = stage(base, st, cp.oZ, cp.cZ);
-    const int mz = merge<SIDE == 0 ? OPMAX : OPMIN, T>(U.view(1), V.view(mv), Z);
+    const int mz = merge<SIDE == 0 ? OPMAX : OPMIN, T>(U, V.view(mv), Z);
     *zout = Z;
     return mz;
 }

@@ -138,6 +138,17 @@ struct Seg {
     T x, v, s;
 };
 
+// One point with its two slopes, held in registers (a node's exercise
+// function u_t); the accessors of View.
+template <typename T>
+struct Kink {
+    T x, v, s0, s1;
+    int m;
+    BTD T X(int) const { return x; }
+    BTD T V(int) const { return v; }
+    BTD T S(int j) const { return j == 0 ? s0 : s1; }
+};
+
 template <typename T, typename F>
 BTD Seg<T> seg_at(const F &f, int i)
 {
