@@ -157,7 +157,7 @@ template <typename T>
 __device__ __forceinline__ void write_record(T *dst, const Arr<T> &z, int m)
 {
     dst[0] = z.S(0);
-    constexpr int B = PWL_GROUP;   // a group's loads before its stores
+    constexpr int B = pwl_group<T>();   // a group's loads before its stores
     for (int j0 = 0; j0 < m; j0 += B) {
         T x[B], v[B], sl[B];
 #pragma unroll

@@ -237,12 +237,15 @@ struct Emit {
 // before its stores (a store may alias a later load, so the compiler would
 // otherwise wait for each point's round trip to memory).
 constexpr int PWL_GROUP = 4;
+// Dual numbers take a point at a time: a group of them would spill.
+template <typename T>
+constexpr int pwl_group() { return sizeof(T) == sizeof(double) ? PWL_GROUP : 1; }
 
 // In-place CANON of a stored function; returns the new point count.
 template <typename T>
 BTD int canon(const Arr<T> &f, int m)
 {
-    constexpr int B = PWL_GROUP;
+    constexpr int B = pwl_group<T>();
     const T s0 = f.S(0);
     int k = 0;
     double sl = val(s0);
@@ -466,7 +469,7 @@ BTD int merge(const FF &F, const GG &G, const Arr<T> &out)
 template <typename T>
 BTD int scale(const Arr<T> &f, int m, const T &rho)
 {
-    constexpr int B = PWL_GROUP;
+    constexpr int B = pwl_group<T>();
     for (int j0 = 0; j0 <= m; j0 += B) {
         T vs[B], ss[B];
 #pragma unroll
@@ -499,7 +502,7 @@ BTD int clip(const Arr<T> &f, int m, const T &a, const T &b)
         f.X(0) = xq; f.V(0) = vq; f.S(0) = a; f.S(1) = a;
         return 1;
     }
-    constexpr int B = PWL_GROUP;
+    constexpr int B = pwl_group<T>();
     for (int j0 = 0; j0 <= m; j0 += B) {
         double ss[B];
 #pragma unroll
@@ -531,7 +534,7 @@ template <typename T>
 BTD void reverse_pts(const Arr<T> &o, int n)
 {
     // pairs (i, n-1-i), a group of them loaded before any is stored
-    constexpr int B = sizeof(T) == sizeof(double) ? PWL_GROUP : 1;
+    constexpr int B = pwl_group<T>();
     const int h = n / 2;
     for (int i0 = 0; i0 < h; i0 += B) {
         T lx[B], lv[B], ls[B], rx[B], rv[B], rs[B];
@@ -611,7 +614,7 @@ BTD int sweep_a(const View<T> &F, const T &a, const Arr<T> &o)
     reverse_pts(o, n);
     // s[i] now holds the right slope of point i: shift to s[i+1], left tail a
     {
-        constexpr int B = PWL_GROUP;
+        constexpr int B = pwl_group<T>();
         for (int i1 = n - 1; i1 >= 0; i1 -= B) {
             T ss[B];
 #pragma unroll
@@ -632,7 +635,7 @@ BTD void mirror_inplace(const Arr<T> &o, int n)
 {
     // points: pairs (i, n-1-i) (the middle one pairs with itself); slopes:
     // pairs (i, n-i); a group of pairs loaded before any is stored
-    constexpr int B = sizeof(T) == sizeof(double) ? PWL_GROUP : 1;
+    constexpr int B = pwl_group<T>();
     const int hp = (n + 1) / 2;
     for (int i0 = 0; i0 < hp; i0 += B) {
         T lx[B], lv[B], rx[B], rv[B];
