@@ -580,7 +580,7 @@ def main():
             "flops_per_step": flops, "launches_per_step": n_launch,
             "flops_per_launch": flops / n_launch, "ms_per_launch": ms_launch,
             "binding": "the dependent chain of one tree's buyer recursion: each level waits for its "
-                       "largest node, updated by one wavefront",
+                       "largest node, updated by its wavefront with a helper wave",
             "critical_tree_alone_ms": crit_ms, "step_over_critical_tree": ms_step / crit_ms if crit_ms else None}
     c = measured_counters(kernel)
     if c:
