@@ -638,7 +638,8 @@ __device__ __forceinline__ void price0_item(const KArgs &A, const Model &md, int
 // wave shift) or, for a wave's last lane, the first lane's value of the next
 // wave (or of wave 0 at m + 1), which each wave's first lane leaves in LDS;
 // two LDS buffers alternate by level, so one barrier per level suffices.
-// Same operations in the same order as price0_item.
+// Every node takes price0_item's operations in its order (the clamp of the
+// exercise value at 0 is taken once per lattice index), so the bits agree.
 constexpr int P0_JMAX = 80;   // levels of up to 256 * 80 nodes stay in registers
 
 template <int J>
