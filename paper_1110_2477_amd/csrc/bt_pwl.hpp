@@ -241,12 +241,13 @@ constexpr int PWL_GROUP = 4;
 template <typename T>
 constexpr int pwl_group() { return sizeof(T) == sizeof(double) ? PWL_GROUP : 1; }
 
-// In-place CANON of a stored function; returns the new point count.
-template <typename T>
-BTD int canon(const Arr<T> &f, int m)
+// In-place CANON of a stored function after mapping each value by fv and
+// each slope by fs, in one pass; returns the new point count.
+template <typename T, class FV, class FS>
+BTD int canon_map(const Arr<T> &f, int m, FV fv, FS fs)
 {
     constexpr int B = pwl_group<T>();
-    const T s0 = f.S(0);
+    const T s0 = fs(f.S(0));
     int k = 0;
     double sl = val(s0);
     for (int j0 = 0; j0 < m; j0 += B) {
@@ -257,7 +258,7 @@ BTD int canon(const Arr<T> &f, int m)
         T xs[B], vs[B], ss[B];
 #pragma unroll
         for (int u = 0; u < B; u++) {
-            if (j0 + u < m) { xs[u] = f.X(j0 + u); vs[u] = f.V(j0 + u); ss[u] = f.S(j0 + u + 1); }
+            if (j0 + u < m) { xs[u] = f.X(j0 + u); vs[u] = fv(f.V(j0 + u)); ss[u] = fs(f.S(j0 + u + 1)); }
         }
 #pragma unroll
         for (int u = 0; u < B; u++) {
@@ -274,6 +275,14 @@ BTD int canon(const Arr<T> &f, int m)
     f.S(0) = s0;
     if (k == 0) { f.S(1) = s0; k = 1; }
     return k;
+}
+
+// In-place CANON of a stored function; returns the new point count.
+template <typename T>
+BTD int canon(const Arr<T> &f, int m)
+{
+    const auto same = [](const T &y) { return y; };
+    return canon_map(f, m, same, same);
 }
 
 // What MERGE emits for one union point P_k: the slope leaving P_k to the
@@ -465,25 +474,12 @@ BTD int merge(const FF &F, const GG &G, const Arr<T> &out)
     return e.finish();
 }
 
-// SCALE by rho in place, then CANON.
+// SCALE by rho in place, then CANON (one pass).
 template <typename T>
 BTD int scale(const Arr<T> &f, int m, const T &rho)
 {
-    constexpr int B = pwl_group<T>();
-    for (int j0 = 0; j0 <= m; j0 += B) {
-        T vs[B], ss[B];
-#pragma unroll
-        for (int u = 0; u < B; u++) {
-            if (j0 + u < m) vs[u] = f.V(j0 + u);
-            if (j0 + u <= m) ss[u] = f.S(j0 + u);
-        }
-#pragma unroll
-        for (int u = 0; u < B; u++) {
-            if (j0 + u < m) f.V(j0 + u) = vs[u] * rho;
-            if (j0 + u <= m) f.S(j0 + u) = ss[u] * rho;
-        }
-    }
-    return canon(f, m);
+    const auto mul = [rho](const T &y) { return y * rho; };
+    return canon_map(f, m, mul, mul);
 }
 
 // CLIP(F, a, b) in place (seller, F convex).  a < b: clamp every slope into
@@ -502,21 +498,10 @@ BTD int clip(const Arr<T> &f, int m, const T &a, const T &b)
         f.X(0) = xq; f.V(0) = vq; f.S(0) = a; f.S(1) = a;
         return 1;
     }
-    constexpr int B = pwl_group<T>();
-    for (int j0 = 0; j0 <= m; j0 += B) {
-        double ss[B];
-#pragma unroll
-        for (int u = 0; u < B; u++)
-            if (j0 + u <= m) ss[u] = val(f.S(j0 + u));
-#pragma unroll
-        for (int u = 0; u < B; u++) {
-            if (j0 + u <= m) {
-                if (ss[u] < val(a)) f.S(j0 + u) = a;
-                else if (ss[u] > val(b)) f.S(j0 + u) = b;
-            }
-        }
-    }
-    return canon(f, m);
+    // the clamp and CANON in one pass
+    const auto same = [](const T &y) { return y; };
+    const auto clamp = [a, b](const T &sl) { return val(sl) < val(a) ? a : (val(sl) > val(b) ? b : sl); };
+    return canon_map(f, m, same, clamp);
 }
 
 // Accessors of F or of its mirror image y -> -y.
