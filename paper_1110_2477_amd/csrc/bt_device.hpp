@@ -235,11 +235,13 @@ BTD int node_update(const View<T> &Zu, const View<T> &Zd, const T &S, const T &k
             Arr<T> B = stage(base, st, cp.oB, cp.cB);
             const int ma = sweep_a<false, T>(Fv, a, A);
             if (ma < 0) return -1;
-            int mb = sweep_a<true, T>(Fv, -b, B);
+            const int mr = sweep_a<true, T>(Fv, -b, B);
+            if (mr < 0) return -1;
+            // B = mirror(RB), with its CANON, into W (free once both sweeps
+            // have read F)
+            const int mb = mirror_canon(B, mr, W);
             if (mb < 0) return -1;
-            mirror_inplace(B, mb);
-            mb = canon(B, mb);
-            mv = merge<OPMIN, T>(A.view(ma), B.view(mb), V);
+            mv = merge<OPMIN, T>(A.view(ma), W.view(mb), V);
             if (mv < 0) return -1;
         }
     }

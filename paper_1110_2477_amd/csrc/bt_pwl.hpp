@@ -614,44 +614,39 @@ BTD int sweep_a(const View<T> &F, const T &a, const Arr<T> &o)
     return canon(o, n);
 }
 
-// Mirror in place: x_j <- -x_{n-1-j}, v_j <- v_{n-1-j}, s_j <- -s_{n-j}.
+// The mirror image of src's n points (x_j <- -x_{n-1-j}, v_j <- v_{n-1-j},
+// s_j <- -s_{n-j}) written to dst with CANON in the same pass; returns the
+// point count, or -1 when dst cannot hold n points.
 template <typename T>
-BTD void mirror_inplace(const Arr<T> &o, int n)
+BTD int mirror_canon(const Arr<T> &src, int n, const Arr<T> &dst)
 {
-    // points: pairs (i, n-1-i) (the middle one pairs with itself); slopes:
-    // pairs (i, n-i); a group of pairs loaded before any is stored
+    if (n > dst.cap) return -1;
     constexpr int B = pwl_group<T>();
-    const int hp = (n + 1) / 2;
-    for (int i0 = 0; i0 < hp; i0 += B) {
-        T lx[B], lv[B], rx[B], rv[B];
+    const T s0 = -src.S(n);
+    int k = 0;
+    double sl = val(s0);
+    for (int j0 = 0; j0 < n; j0 += B) {
+        T xs[B], vs[B], ss[B];
 #pragma unroll
         for (int u = 0; u < B; u++) {
-            const int i = i0 + u, j = n - 1 - i;
-            if (i < hp) { lx[u] = o.X(i); lv[u] = o.V(i); rx[u] = o.X(j); rv[u] = o.V(j); }
+            const int r = n - 1 - (j0 + u);
+            if (j0 + u < n) { xs[u] = -src.X(r); vs[u] = src.V(r); ss[u] = -src.S(r); }
         }
 #pragma unroll
         for (int u = 0; u < B; u++) {
-            const int i = i0 + u, j = n - 1 - i;
-            if (i < hp) {
-                o.X(i) = -rx[u]; o.V(i) = rv[u];
-                o.X(j) = -lx[u]; o.V(j) = lv[u];
+            if (j0 + u < n) {
+                const double sr = val(ss[u]);
+                if (sl != sr) {
+                    dst.X(k) = xs[u]; dst.V(k) = vs[u]; dst.S(k + 1) = ss[u];
+                    k++;
+                }
+                sl = sr;
             }
         }
     }
-    const int hs = n / 2 + 1;
-    for (int i0 = 0; i0 < hs; i0 += B) {
-        T ls[B], rs[B];
-#pragma unroll
-        for (int u = 0; u < B; u++) {
-            const int i = i0 + u;
-            if (i < hs) { ls[u] = o.S(i); rs[u] = o.S(n - i); }
-        }
-#pragma unroll
-        for (int u = 0; u < B; u++) {
-            const int i = i0 + u;
-            if (i < hs) { o.S(i) = -rs[u]; o.S(n - i) = -ls[u]; }
-        }
-    }
+    dst.S(0) = s0;
+    if (k == 0) { dst.S(1) = s0; k = 1; }
+    return k;
 }
 
 }  // namespace bt
