@@ -231,17 +231,19 @@ BTD int node_update(const View<T> &Zu, const View<T> &Zd, const T &S, const T &k
             V.X(0) = xs; V.V(0) = vs; V.S(0) = a; V.S(1) = a;
             mv = 1;
         } else {
+            // the raw sweeps go to the A and B stages; A with its CANON lands
+            // in the Z stage (free until the final MERGE), B = mirror(RB)
+            // with its CANON in W (free once both sweeps have read F)
             Arr<T> A = stage(base, st, cp.oA, cp.cA);
             Arr<T> B = stage(base, st, cp.oB, cp.cB);
-            const int ma = sweep_a<false, T>(Fv, a, A);
+            Arr<T> Ac = stage(base, st, cp.oZ, cp.cZ);
+            const int ma = sweep_a<false, T>(Fv, a, A, Ac);
             if (ma < 0) return -1;
-            const int mr = sweep_a<true, T>(Fv, -b, B);
+            const int mr = sweep_raw<true, T>(Fv, -b, B);
             if (mr < 0) return -1;
-            // B = mirror(RB), with its CANON, into W (free once both sweeps
-            // have read F)
-            const int mb = mirror_canon(B, mr, W);
+            const int mb = mirror_canon_raw(B, mr, -b, W);
             if (mb < 0) return -1;
-            mv = merge<OPMIN, T>(A.view(ma), W.view(mb), V);
+            mv = merge<OPMIN, T>(Ac.view(ma), W.view(mb), V);
             if (mv < 0) return -1;
         }
     }

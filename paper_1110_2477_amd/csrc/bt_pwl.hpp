@@ -514,34 +514,6 @@ struct Src {
     BTD T S(int j) const { return MIR ? -f.S(f.m - j) : f.S(j); }
 };
 
-// Reverse points [0, n) and slopes [0, n) in place.
-template <typename T>
-BTD void reverse_pts(const Arr<T> &o, int n)
-{
-    // pairs (i, n-1-i), a group of them loaded before any is stored
-    constexpr int B = pwl_group<T>();
-    const int h = n / 2;
-    for (int i0 = 0; i0 < h; i0 += B) {
-        T lx[B], lv[B], ls[B], rx[B], rv[B], rs[B];
-#pragma unroll
-        for (int u = 0; u < B; u++) {
-            const int i = i0 + u, j = n - 1 - i;
-            if (i < h) {
-                lx[u] = o.X(i); lv[u] = o.V(i); ls[u] = o.S(i);
-                rx[u] = o.X(j); rv[u] = o.V(j); rs[u] = o.S(j);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < B; u++) {
-            const int i = i0 + u, j = n - 1 - i;
-            if (i < h) {
-                o.X(i) = rx[u]; o.V(i) = rv[u]; o.S(i) = rs[u];
-                o.X(j) = lx[u]; o.V(j) = lv[u]; o.S(j) = ls[u];
-            }
-        }
-    }
-}
-
 // A(y) = a y + min_{y' >= y} (F(y') - a y') over F (or its mirror): the
 // buying half of the restriction.  With h_j = v_j - a x_j, SM_j the minimum
 // of h_i over i > j and Q_j the smallest such i attaining it, the piece
@@ -554,11 +526,13 @@ BTD void reverse_pts(const Arr<T> &o, int n)
 //   FLAT    otherwise: L_j.
 // Left tail flat (slope a), right tail F.  Points: every x_j with v_j and
 // the SPLIT points, each with the slope to its right; then CANON.  Computed
-// right to left with a running minimum (ties keep the nearer index), written
-// in reverse and flipped.  Requires s_0 < a < s_m.  Returns the count or -1
-// on overflow.
+// right to left with a running minimum (ties keep the nearer index):
+// sweep_raw leaves the points in `o` in that order (decreasing x), each with
+// its right slope at the same index, and returns their count (-1 on
+// overflow); sweep_a reads them back in increasing x into `o2` (not the raw
+// array) with CANON in the same pass.  Requires s_0 < a < s_m.
 template <bool MIR, typename T>
-BTD int sweep_a(const View<T> &F, const T &a, const Arr<T> &o)
+BTD int sweep_raw(const View<T> &F, const T &a, const Arr<T> &o)
 {
     Src<MIR, T> f{F, F.m};
     const int m = F.m;
@@ -596,41 +570,61 @@ BTD int sweep_a(const View<T> &F, const T &a, const Arr<T> &o)
         if (j == m - 1 || val(hj) <= val(SMc)) { SMc = hj; Qc = j; xq = xj; vq = vj; }
         xr = val(xj);
     }
-    reverse_pts(o, n);
-    // s[i] now holds the right slope of point i: shift to s[i+1], left tail a
-    {
-        constexpr int B = pwl_group<T>();
-        for (int i1 = n - 1; i1 >= 0; i1 -= B) {
-            T ss[B];
-#pragma unroll
-            for (int u = 0; u < B; u++)
-                if (i1 - u >= 0) ss[u] = o.S(i1 - u);
-#pragma unroll
-            for (int u = 0; u < B; u++)
-                if (i1 - u >= 0) o.S(i1 - u + 1) = ss[u];
-        }
-    }
-    o.S(0) = a;
-    return canon(o, n);
+    return n;
 }
 
-// The mirror image of src's n points (x_j <- -x_{n-1-j}, v_j <- v_{n-1-j},
-// s_j <- -s_{n-j}) written to dst with CANON in the same pass; returns the
-// point count, or -1 when dst cannot hold n points.
+template <bool MIR, typename T>
+BTD int sweep_a(const View<T> &F, const T &a, const Arr<T> &raw, const Arr<T> &o2)
+{
+    const int n = sweep_raw<MIR, T>(F, a, raw);
+    if (n < 0 || n > o2.cap) return -1;
+    constexpr int B = pwl_group<T>();
+    int k = 0;
+    double sl = val(a);
+    for (int i0 = 0; i0 < n; i0 += B) {
+        T xs[B], vs[B], ss[B];
+#pragma unroll
+        for (int u = 0; u < B; u++) {
+            const int r = n - 1 - (i0 + u);
+            if (i0 + u < n) { xs[u] = raw.X(r); vs[u] = raw.V(r); ss[u] = raw.S(r); }
+        }
+#pragma unroll
+        for (int u = 0; u < B; u++) {
+            if (i0 + u < n) {
+                const double sr = val(ss[u]);
+                if (sl != sr) {
+                    o2.X(k) = xs[u]; o2.V(k) = vs[u]; o2.S(k + 1) = ss[u];
+                    k++;
+                }
+                sl = sr;
+            }
+        }
+    }
+    o2.S(0) = a;
+    if (k == 0) { o2.S(1) = a; k = 1; }
+    return k;
+}
+
+// B = mirror(RB) with CANON, read straight from the raw sweep of RB (slope
+// aR on its left tail): the raw order (decreasing x of RB) is B's increasing
+// x; point j of B is (-x_j, v_j) with left slope -s_j and right slope
+// -s_{j+1} (-aR for the last).  Slopes here are never zero, so dropping
+// RB's collinear points before the mirror or after it keeps the same points
+// and the same bits.  -1 when dst cannot hold n points.
 template <typename T>
-BTD int mirror_canon(const Arr<T> &src, int n, const Arr<T> &dst)
+BTD int mirror_canon_raw(const Arr<T> &raw, int n, const T &aR, const Arr<T> &dst)
 {
     if (n > dst.cap) return -1;
     constexpr int B = pwl_group<T>();
-    const T s0 = -src.S(n);
+    const T s0 = -raw.S(0);
     int k = 0;
     double sl = val(s0);
     for (int j0 = 0; j0 < n; j0 += B) {
         T xs[B], vs[B], ss[B];
 #pragma unroll
         for (int u = 0; u < B; u++) {
-            const int r = n - 1 - (j0 + u);
-            if (j0 + u < n) { xs[u] = -src.X(r); vs[u] = src.V(r); ss[u] = -src.S(r); }
+            const int j = j0 + u;
+            if (j < n) { xs[u] = -raw.X(j); vs[u] = raw.V(j); ss[u] = j + 1 < n ? -raw.S(j + 1) : -aR; }
         }
 #pragma unroll
         for (int u = 0; u < B; u++) {
