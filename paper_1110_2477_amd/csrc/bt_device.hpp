@@ -209,9 +209,8 @@ BTD int node_update(const View<T> &Zu, const View<T> &Zd, const T &S, const T &k
     const T a = -((one + kt) * S);
     const T b = -((one - kt) * S);
     Arr<T> W = stage(base, st, cp.oW, cp.cW);
-    int mw = merge<OPMAX, T>(Zu, Zd, W);
+    const int mw = merge_scale<OPMAX, T>(Zu, Zd, W, rho);
     if (mw < 0) return -1;
-    mw = scale(W, mw, rho);
     Arr<T> V;
     int mv;
     if (SIDE == 0) {

@@ -233,6 +233,57 @@ struct Emit {
     }
 };
 
+// Emit followed by SCALE by rho and its CANON, in one pass: a point that
+// Emit keeps is stored with v rho and s rho unless its scaled slopes are
+// equal (the scaled CANON's decision on Emit's sequence).  When nothing is
+// stored, the one point left is Emit's (its first kept point, else the first
+// pushed), as SCALE and CANON after Emit would leave it.
+template <typename T>
+struct EmitScaled {
+    Arr<T> o;
+    T rho;
+    int m, mu;
+    bool ovf, have0;
+    double cur, curs;
+    T x0, v0, xk, vk;
+    BTD void start(const Arr<T> &out, const T &s_left)
+    {
+        o = out; m = 0; mu = 0; ovf = false; have0 = false;
+        cur = val(s_left);
+        const T ss = s_left * rho;
+        curs = val(ss);
+        o.S(0) = ss;
+    }
+    BTD void push(const T &x, const T &v, const T &s_right)
+    {
+        if (!have0) { x0 = x; v0 = v; have0 = true; }
+        if (cur != val(s_right)) {
+            if (mu == 0) { xk = x; vk = v; }
+            if (mu >= o.cap) ovf = true;   // where Emit would overflow
+            mu++;
+            cur = val(s_right);
+            const T ss = s_right * rho;
+            if (curs != val(ss)) {
+                if (m < o.cap) { o.X(m) = x; o.V(m) = v * rho; o.S(m + 1) = ss; }
+                else ovf = true;
+                m++;
+                curs = val(ss);
+            }
+        }
+    }
+    BTD int finish()
+    {
+        if (ovf) return -1;
+        if (m == 0) {
+            if (mu == 0) { o.X(0) = x0; o.V(0) = v0 * rho; }
+            else { o.X(0) = xk; o.V(0) = vk * rho; }
+            o.S(1) = o.S(0);
+            m = 1;
+        }
+        return m;
+    }
+};
+
 // Points per group of the in-place loops below: a group's loads issue
 // before its stores (a store may alias a later load, so the compiler would
 // otherwise wait for each point's round trip to memory).
@@ -421,8 +472,8 @@ BTD Slot<T> slot_left(const FF &F, const GG &G, const T &P0, const T &fF, const 
 //    strictly outside the end point.
 //  - Values are op(EVAL(F, y), EVAL(G, y)); slopes are the winner's.
 // F and G are any types with m, X(j), V(j), S(j).
-template <int OP, typename T, typename FF, typename GG>
-BTD int merge(const FF &F, const GG &G, const Arr<T> &out)
+template <int OP, typename T, class EM, typename FF, typename GG>
+BTD int merge_em(const FF &F, const GG &G, const Arr<T> &out, EM &e)
 {
     const double INF = __builtin_huge_val();
     int a = 0, b = 0;
@@ -442,7 +493,6 @@ BTD int merge(const FF &F, const GG &G, const Arr<T> &out)
         fF = seg_eval<T>(gF, P);
         fG = seg_eval<T>(gG, P);
     }
-    Emit<T> e;
     {
         const Slot<T> L = slot_left<OP, T>(F, G, P, fF, fG);
         e.start(out, L.rs);
@@ -472,6 +522,22 @@ BTD int merge(const FF &F, const GG &G, const Arr<T> &out)
         }
     }
     return e.finish();
+}
+
+template <int OP, typename T, typename FF, typename GG>
+BTD int merge(const FF &F, const GG &G, const Arr<T> &out)
+{
+    Emit<T> e;
+    return merge_em<OP, T>(F, G, out, e);
+}
+
+// MERGE, then SCALE by rho with its CANON, in one pass over the output.
+template <int OP, typename T, typename FF, typename GG>
+BTD int merge_scale(const FF &F, const GG &G, const Arr<T> &out, const T &rho)
+{
+    EmitScaled<T> e;
+    e.rho = rho;
+    return merge_em<OP, T>(F, G, out, e);
 }
 
 // SCALE by rho in place, then CANON (one pass).
