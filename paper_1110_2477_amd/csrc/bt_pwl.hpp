@@ -674,9 +674,11 @@ BTD int sweep_a(const View<T> &F, const T &a, const Arr<T> &raw, const Arr<T> &o
 // B = mirror(RB) with CANON, read straight from the raw sweep of RB (slope
 // aR on its left tail): the raw order (decreasing x of RB) is B's increasing
 // x; point j of B is (-x_j, v_j) with left slope -s_j and right slope
-// -s_{j+1} (-aR for the last).  Slopes here are never zero, so dropping
-// RB's collinear points before the mirror or after it keeps the same points
-// and the same bits.  -1 when dst cannot hold n points.
+// -s_{j+1} (-aR for the last).  The slopes are negative (between
+// -(1+k)S and -(1-k)S, scaled by powers of rho, with S > 0 and k < 1;
+// only an underflow of S could make one zero), so dropping RB's collinear
+// points before the mirror or after it keeps the same points and the same
+// bits.  -1 when dst cannot hold n points.
 template <typename T>
 BTD int mirror_canon_raw(const Arr<T> &raw, int n, const T &aR, const Arr<T> &dst)
 {
